@@ -1,0 +1,185 @@
+/*
+ * cbie.h -- C-ABI of the MI355X (gfx950) H-matrix direct solver for the
+ * Chebyshev-based Nystrom boundary integral equation (CBIE), after
+ * Hu, Sever, Babazadeh, Jeffrey, Okhmatovski, Sideris, "H-Matrix Accelerated
+ * Direct Matrix Solver for Maxwell's Equations using the Chebyshev-based
+ * Nystrom Boundary Integral Equation Method" (arXiv 2408.17116).
+ *
+ * Problem (Sec. II).  A closed PEC surface is cut into curved quadrilateral
+ * patches; on each patch the contravariant components F^u, F^v of the
+ * surface current (eq. 11) are sampled on a q x q grid of first-kind
+ * Chebyshev (Fejer) points (eqs. 12, 13).  The MFIE (eq. 10, second row,
+ * with the sign fixed by eqs. 2, 5, 6:  J/2 - n x curl S[J] = n x H_inc),
+ * tested with sqrt(G) a^u, sqrt(G) a^v (eqs. 17, 18), gives the dense complex
+ * system of eq. (22).  Far entries use the plain Fejer rule; self and near
+ * entries (eq. 20) are integrals against the Chebyshev basis computed with a
+ * singularity-cancelling change of variables.  The matrix is held as an
+ * H-matrix (Sec. III: cluster tree, admissibility eq. 21, leaf size n_leaf,
+ * ACA for admissible blocks), factorized by H-LU and solved by forward/back
+ * substitution (eqs. 23-28), in the "entire matrix" ordering with
+ * interleaved u/v unknowns at repeated points (Sec. III-B).
+ *
+ * Conventions
+ *  - Units are normalized: eps0 = mu0 = 1, eta0 = 1, omega = k0.  Time
+ *    dependence e^{j omega t}.  The mu_1 row factor of eq. (22) is dropped.
+ *  - Vectors crossing the ABI are complex128 (two doubles, re then im),
+ *    column-major with leading dimension ld >= n_unknowns, device pointers
+ *    on the context's device, in the ORIGINAL unknown order: object-major,
+ *    then patch p, node (k, l) with l the u-index, then component (u, v):
+ *    index = 2 * ((p * q + k) * q + l) + a within an object.
+ *  - Every call is ordered on the context stream and returns after the
+ *    work has completed, so the status reflects device errors.  Nothing is
+ *    printed, thrown or aborted across the ABI; a failing call leaves the
+ *    context valid and sets cbie_last_error().
+ *  - Ownership: the caller owns every buffer it passes; the library never
+ *    frees them and never keeps them after the call returns.  The library
+ *    owns everything it allocates and frees it in cbie_destroy().
+ *  - State machine: create -> build_tree -> fill -> compress -> factor ->
+ *    solve.  matvec is valid after compress.  factor may be repeated with
+ *    another precision.  Calls out of order return CBIE_ESTATE.
+ */
+#ifndef CBIE_H
+#define CBIE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CBIE_OK = 0,
+    CBIE_EINVAL = -1,     /* bad argument (null pointer, size, range)      */
+    CBIE_ENOMEM = -2,     /* device or host allocation failed              */
+    CBIE_EHIP = -3,       /* a HIP runtime call or kernel failed           */
+    CBIE_ESTATE = -4,     /* call out of order                             */
+    CBIE_ENOCONV = -5,    /* iterative refinement did not reach tolerance  */
+    CBIE_ESINGULAR = -6,  /* zero pivot in a diagonal leaf                 */
+    CBIE_EINTERNAL = -7   /* unsupported internal case (reported, no UB)   */
+} cbie_status;
+
+typedef struct cbie_ctx cbie_ctx;
+
+typedef enum { CBIE_MFIE_PEC = 0, CBIE_NMULLER = 1 } cbie_formulation;
+typedef enum { CBIE_PREC_C128 = 0, CBIE_PREC_C64_IR = 1 } cbie_precision;
+typedef enum { CBIE_RANK_ADAPTIVE = 0, CBIE_RANK_PREDICTED = 1 } cbie_rank_mode;
+
+/* One patch of the equiangular cube sphere mapped onto an ellipsoid:
+ * face f (0..5 = +x,-x,+y,-y,+z,-z), sub-square (i, j) of split x split,
+ * r(u,v) = center + diag(axes) c/|c|, c = e_n + tan(pi xi/4) e_1 +
+ * tan(pi eta/4) e_2, xi = (2i+1+u)/split - 1, eta = (2j+1+v)/split - 1.  */
+typedef struct {
+    int face, i, j, split;
+} cbie_patch;
+
+typedef struct {
+    cbie_formulation form;     /* only CBIE_MFIE_PEC is implemented          */
+    double k0;                 /* exterior wavenumber, rad/m, > 0           */
+    double axes[3];            /* ellipsoid semi-axes, > 0                   */
+    double center[3];
+    int q;                     /* Chebyshev points per direction, 2..8       */
+    int n_patches;
+    const cbie_patch* patches; /* host array of n_patches, copied at create  */
+} cbie_object;
+
+/* Create a context for n_objs independent objects (block-diagonal system,
+ * no coupling between objects).  hip_stream: a hipStream_t, or NULL for
+ * the null stream.  Copies the patch tables.  Errors: EINVAL, ENOMEM, EHIP. */
+cbie_status cbie_create(const cbie_object* objs, int n_objs, void* hip_stream,
+                        cbie_ctx** out);
+
+/* Geometry of the nodes (eqs. 11, 14, 17, 18), near classification (eq. 20:
+ * patch p is near node i iff dist(r_i, p) < near_delta * diam(p), diam =
+ * longer corner diagonal, dist by projection; the owner patch is "self"),
+ * cluster tree by patch-atomic bisection of node bounding boxes until a
+ * cluster holds <= leaf_size unknowns or one patch, and block cluster tree
+ * with admissibility min(diam_t, diam_s) <= eta dist(t, s) on bounding
+ * boxes (eq. 21); a block holding a near pair is never admissible.
+ * Errors: EINVAL (leaf_size < 2 q^2, eta <= 0, near_delta <= 0), ENOMEM, EHIP. */
+cbie_status cbie_build_tree(cbie_ctx* ctx, int leaf_size, double eta, double near_delta);
+
+/* Fill the inadmissible (dense) blocks: far entries by the Fejer rule,
+ * self/near entries by the change-of-variables quadrature, 1/2 identity.
+ * n_ang / n_rad: points of the singular rule per angular / radial direction
+ * (0 = defaults 40 / 32).  Errors: ESTATE, ENOMEM, EHIP. */
+cbie_status cbie_fill(cbie_ctx* ctx, int n_ang, int n_rad);
+
+/* Compress the admissible blocks by partial-pivot ACA to relative Frobenius
+ * tolerance aca_tol, then recompress each block (QR + SVD truncation at the
+ * same tolerance).  Errors: ESTATE, EINVAL, ENOMEM, EHIP. */
+cbie_status cbie_compress(cbie_ctx* ctx, double aca_tol, cbie_rank_mode mode);
+
+/* H-LU factorization (eqs. 23-28): partial pivoting inside diagonal leaves,
+ * none across blocks; formatted updates truncated at the compress tolerance.
+ * CBIE_PREC_C128: complex128 on FP64 MFMA.  CBIE_PREC_C64_IR: complex64 on
+ * FP32 MFMA (FP32 accumulation); solve() then refines in FP64.
+ * Errors: ESTATE, ENOMEM, EHIP, ESINGULAR. */
+cbie_status cbie_factor(cbie_ctx* ctx, cbie_precision prec);
+
+/* Solve A x = b for nrhs right-hand sides (per object).  b_dev, x_dev:
+ * complex128 device arrays, n_unknowns x nrhs, leading dimension ld,
+ * original order; b_dev is not modified; x_dev may not alias b_dev.
+ * After a C64_IR factorization: x = LU^{-1} b, then iterate
+ * r = b - A x (FP64, stored operator), x += LU^{-1} r until
+ * max_j |r_j|/|b_j| <= ir_tol or ir_maxit sweeps (ENOCONV then, x holds
+ * the last iterate).  ir_iters_out (may be NULL) receives the sweep count.
+ * Errors: ESTATE, EINVAL, ENOCONV, EHIP. */
+cbie_status cbie_solve(cbie_ctx* ctx, int nrhs, const void* b_dev, void* x_dev, long ld,
+                       double ir_tol, int ir_maxit, int* ir_iters_out);
+
+/* y = A_H x with the compressed operator in FP64 arithmetic (complex128),
+ * nrhs columns, original order, leading dimension ld.  Errors: ESTATE, EINVAL, EHIP. */
+cbie_status cbie_matvec(cbie_ctx* ctx, int nrhs, const void* x_dev, void* y_dev, long ld);
+
+/* Right-hand sides of eq. (22) for nw plane waves E = pol e^{-j k khat.r},
+ * H = khat x E: b_u = -a_v . H, b_v = a_u . H.  khat, pol: host arrays of
+ * 3*nw doubles.  b_dev: complex128 device array n_unknowns x nw, ld.
+ * Errors: ESTATE (before build_tree), EINVAL, EHIP. */
+cbie_status cbie_rhs_planewave(cbie_ctx* ctx, int nw, const double* khat, const double* pol,
+                               void* b_dev, long ld);
+
+/* Far field r e^{j k r} E_s = -j k N_perp / (4 pi), N = sum_nodes
+ * w (F^u a_u + F^v a_v) e^{j k rhat.r}, for nrhs solutions x_dev (device,
+ * ld) at ndir directions rhat (host, 3*ndir doubles).  E_out: host array of
+ * 3 * ndir * nrhs complex128 (x,y,z fastest, then direction, then rhs).
+ * Errors: ESTATE, EINVAL, EHIP. */
+cbie_status cbie_farfield(cbie_ctx* ctx, int nrhs, const void* x_dev, long ld, int ndir,
+                          const double* rhat, void* E_out);
+
+/* Statistics.  Fills as many leading fields of cbie_stats as `bytes` allows. */
+typedef struct {
+    int64_t n_unknowns, n_nodes, n_patches, n_objects;
+    int64_t n_clusters, n_leaves, n_dense_blocks, n_lr_blocks;
+    int64_t n_near_pairs;            /* (target node, patch) pairs incl. self */
+    int64_t dense_entries;           /* stored dense entries                  */
+    int64_t lr_entries;              /* stored low-rank entries (m + n) r     */
+    int64_t max_rank, sum_rank;
+    double compression_rate;         /* 1 - stored / N^2 (Sec. IV-A)          */
+    double t_tree, t_fill, t_compress, t_factor, t_solve;  /* seconds          */
+    int64_t factor_flops;            /* algorithmic flops of the last factor  */
+    int64_t n_kernel_launches;       /* launches in the last factor           */
+    int64_t ir_iterations;           /* sweeps of the last solve              */
+    double quad_seconds;             /* near/self quadrature kernel time      */
+} cbie_stats;
+cbie_status cbie_get_stats(cbie_ctx* ctx, void* stats_out, size_t bytes);
+
+/* Parity hooks (small problems; no effect on the solver state).
+ * Near pairs after build_tree: for each pair, target node and patch index
+ * (original numbering).  cap: capacity of the host arrays; count_out gets
+ * the total (the arrays hold min(cap, total), sorted by (target, patch)).  */
+cbie_status cbie_get_near_pairs(cbie_ctx* ctx, int64_t cap, int32_t* targets, int32_t* patches,
+                                int64_t* count_out);
+/* After fill (dense blocks) and compress (low-rank blocks): the full matrix,
+ * N x N complex128, device, column-major with leading dimension ld, original
+ * order.  Admissible blocks not yet compressed are filled with the plain
+ * Fejer rule.  Errors: ESTATE, EINVAL, ENOMEM, EHIP. */
+cbie_status cbie_export_dense(cbie_ctx* ctx, void* a_dev, long ld);
+
+const char* cbie_last_error(const cbie_ctx* ctx);
+void cbie_destroy(cbie_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CBIE_H */

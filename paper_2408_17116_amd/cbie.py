@@ -1,0 +1,215 @@
+"""Thin ctypes binding of libcbie.so (argument marshalling only).
+
+Every step of the solver runs in the library's HIP kernels; PyTorch only
+provides device memory and the stream.  Device vectors are complex128
+tensors; a block of nrhs vectors of length n is held as a contiguous
+(nrhs, n) tensor, i.e. column-major (n, nrhs) with leading dimension n, in
+the original unknown order (object, patch, node (k, l), component u/v).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcbie.so")
+
+OK, EINVAL, ENOMEM, EHIP, ESTATE, ENOCONV, ESINGULAR, EINTERNAL = 0, -1, -2, -3, -4, -5, -6, -7
+MFIE_PEC, NMULLER = 0, 1
+PREC_C128, PREC_C64_IR = 0, 1
+RANK_ADAPTIVE, RANK_PREDICTED = 0, 1
+
+EXPORTED = ["cbie_create", "cbie_build_tree", "cbie_fill", "cbie_compress", "cbie_factor",
+            "cbie_solve", "cbie_matvec", "cbie_rhs_planewave", "cbie_farfield", "cbie_get_stats",
+            "cbie_get_near_pairs", "cbie_export_dense", "cbie_last_error", "cbie_destroy"]
+
+
+class CbieError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"cbie error {code}: {msg}")
+        self.code = code
+
+
+class _Patch(C.Structure):
+    _fields_ = [("face", C.c_int), ("i", C.c_int), ("j", C.c_int), ("split", C.c_int)]
+
+
+class _Object(C.Structure):
+    _fields_ = [("form", C.c_int), ("k0", C.c_double), ("axes", C.c_double * 3),
+                ("center", C.c_double * 3), ("q", C.c_int), ("n_patches", C.c_int),
+                ("patches", C.POINTER(_Patch))]
+
+
+class Stats(C.Structure):
+    _fields_ = [(n, C.c_int64) for n in (
+        "n_unknowns", "n_nodes", "n_patches", "n_objects", "n_clusters", "n_leaves",
+        "n_dense_blocks", "n_lr_blocks", "n_near_pairs", "dense_entries", "lr_entries",
+        "max_rank", "sum_rank")] + [
+        ("compression_rate", C.c_double), ("t_tree", C.c_double), ("t_fill", C.c_double),
+        ("t_compress", C.c_double), ("t_factor", C.c_double), ("t_solve", C.c_double),
+        ("factor_flops", C.c_int64), ("n_kernel_launches", C.c_int64),
+        ("ir_iterations", C.c_int64), ("quad_seconds", C.c_double)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libcbie.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: run __graft_entry__.build() (hipcc, gfx950) first")
+    lib = C.CDLL(path)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int, C.c_int64, C.c_double
+    sig = {
+        "cbie_create": ([C.POINTER(_Object), i32, vp, C.POINTER(vp)], i32),
+        "cbie_build_tree": ([vp, i32, dbl, dbl], i32),
+        "cbie_fill": ([vp, i32, i32], i32),
+        "cbie_compress": ([vp, dbl, i32], i32),
+        "cbie_factor": ([vp, i32], i32),
+        "cbie_solve": ([vp, i32, vp, vp, C.c_long, dbl, i32, C.POINTER(i32)], i32),
+        "cbie_matvec": ([vp, i32, vp, vp, C.c_long], i32),
+        "cbie_rhs_planewave": ([vp, i32, vp, vp, vp, C.c_long], i32),
+        "cbie_farfield": ([vp, i32, vp, C.c_long, i32, vp, vp], i32),
+        "cbie_get_stats": ([vp, vp, C.c_size_t], i32),
+        "cbie_get_near_pairs": ([vp, i64, vp, vp, C.POINTER(i64)], i32),
+        "cbie_export_dense": ([vp, vp, C.c_long], i32),
+        "cbie_last_error": ([vp], C.c_char_p),
+        "cbie_destroy": ([vp], None),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return C.c_void_p(t.data_ptr())
+
+
+class Solver:
+    """One context: a set of independent objects (block-diagonal system)."""
+
+    def __init__(self, objects, stream=None):
+        import torch
+        self.torch = torch
+        self.lib = load()
+        if not isinstance(objects, (list, tuple)):
+            objects = [objects]
+        self.objects = list(objects)
+        objs = (_Object * len(objects))()
+        self._keep = []
+        for o, spec in enumerate(objects):
+            pts = spec.patches()
+            arr = (_Patch * len(pts))(*[_Patch(f, i, j, s) for (f, i, j, s) in pts])
+            self._keep.append(arr)
+            objs[o].form = spec.form
+            objs[o].k0 = spec.k0
+            objs[o].axes = (C.c_double * 3)(*spec.axes)
+            objs[o].center = (C.c_double * 3)(*spec.center)
+            objs[o].q = spec.q
+            objs[o].n_patches = len(pts)
+            objs[o].patches = arr
+        self.n = sum(s.n_unknowns for s in objects)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        st = self.lib.cbie_create(objs, len(objects), C.c_void_p(stream.cuda_stream), C.byref(h))
+        if st != OK:
+            raise CbieError(st, "cbie_create failed")
+        self.h = h
+
+    def _check(self, st):
+        if st != OK:
+            raise CbieError(st, self.lib.cbie_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.cbie_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------ stages
+    def build_tree(self, leaf_size=256, eta=1.0, near_delta=1.0):
+        self._check(self.lib.cbie_build_tree(self.h, leaf_size, eta, near_delta))
+
+    def fill(self, n_ang=0, n_rad=0):
+        self._check(self.lib.cbie_fill(self.h, n_ang, n_rad))
+
+    def compress(self, tol=1e-6, mode=RANK_ADAPTIVE):
+        self._check(self.lib.cbie_compress(self.h, tol, mode))
+
+    def factor(self, prec=PREC_C128):
+        self._check(self.lib.cbie_factor(self.h, prec))
+
+    def _cols(self, v):
+        """(n,) or (n, m) complex128 cuda tensor -> contiguous (m, n) tensor."""
+        t = self.torch
+        v = t.as_tensor(v)
+        if v.dim() == 1:
+            v = v[:, None]
+        return v.to(device="cuda", dtype=t.complex128).t().contiguous()
+
+    def solve(self, b, tol=1e-10, maxit=0, raise_on_noconv=True):
+        bc = self._cols(b)
+        x = self.torch.empty_like(bc)
+        it = C.c_int(0)
+        st = self.lib.cbie_solve(self.h, bc.shape[0], _ptr(bc), _ptr(x), self.n, tol, maxit, C.byref(it))
+        if st == ENOCONV and not raise_on_noconv:
+            return x.t(), it.value
+        self._check(st)
+        return x.t(), it.value
+
+    def matvec(self, x):
+        xc = self._cols(x)
+        y = self.torch.empty_like(xc)
+        self._check(self.lib.cbie_matvec(self.h, xc.shape[0], _ptr(xc), _ptr(y), self.n))
+        return y.t()
+
+    def rhs_planewave(self, khat, pol):
+        khat = np.ascontiguousarray(np.atleast_2d(khat), dtype=np.float64)
+        pol = np.ascontiguousarray(np.atleast_2d(pol), dtype=np.float64)
+        nw = khat.shape[0]
+        b = self.torch.empty((nw, self.n), dtype=self.torch.complex128, device="cuda")
+        self._check(self.lib.cbie_rhs_planewave(self.h, nw, khat.ctypes.data_as(C.c_void_p),
+                                                pol.ctypes.data_as(C.c_void_p), _ptr(b), self.n))
+        return b.t()
+
+    def farfield(self, x, rhat):
+        xc = self._cols(x)
+        rhat = np.ascontiguousarray(np.atleast_2d(rhat), dtype=np.float64)
+        out = np.empty((xc.shape[0], rhat.shape[0], 3), dtype=np.complex128)
+        self._check(self.lib.cbie_farfield(self.h, xc.shape[0], _ptr(xc), self.n, rhat.shape[0],
+                                           rhat.ctypes.data_as(C.c_void_p), out.ctypes.data_as(C.c_void_p)))
+        return out
+
+    def stats(self) -> dict:
+        s = Stats()
+        self._check(self.lib.cbie_get_stats(self.h, C.byref(s), C.sizeof(s)))
+        return {name: getattr(s, name) for name, _ in Stats._fields_}
+
+    def near_pairs(self):
+        cnt = C.c_int64(0)
+        self._check(self.lib.cbie_get_near_pairs(self.h, 0, None, None, C.byref(cnt)))
+        t = np.empty(cnt.value, dtype=np.int32)
+        p = np.empty(cnt.value, dtype=np.int32)
+        self._check(self.lib.cbie_get_near_pairs(self.h, cnt.value, t.ctypes.data_as(C.c_void_p),
+                                                 p.ctypes.data_as(C.c_void_p), C.byref(cnt)))
+        return t, p
+
+    def export_dense(self):
+        A = self.torch.empty((self.n, self.n), dtype=self.torch.complex128, device="cuda")
+        self._check(self.lib.cbie_export_dense(self.h, _ptr(A), self.n))
+        return A.t()   # the library writes column-major

@@ -1,0 +1,437 @@
+// Geometry, near classification, self/near change-of-variables quadrature and
+// dense-block fill of the CBIE MFIE matrix (Sec. II-B, eqs. 11-20).
+#include "fill.hpp"
+
+namespace cbie {
+
+// ------------------------------------------------------------ node geometry
+// One thread per node (original order): r, a_u, a_v at the Fejer point
+// (u_l, v_k) of its patch, tensor weight w_l w_k.
+__global__ void k_nodes(const PatchDev* __restrict__ patches, const ObjDev* __restrict__ objs,
+                        const double* __restrict__ fej_x, const double* __restrict__ fej_w,
+                        const int* __restrict__ node_patch, int n_nodes, NodeArrays nd) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_nodes) return;
+    const PatchDev P = patches[node_patch[i]];
+    const ObjDev O = objs[P.obj];
+    const int loc = i - P.node0;
+    const int kk = loc / P.q, ll = loc % P.q;
+    const double* x = fej_x + P.q * (P.q - 1) / 2;    // rule of size q stored at offset q(q-1)/2
+    const double* w = fej_w + P.q * (P.q - 1) / 2;
+    const double u = x[ll], v = x[kk];
+    V3 r, au, av;
+    patch_eval(P, O, u, v, r, au, av);
+    nd.rx[i] = r.x; nd.ry[i] = r.y; nd.rz[i] = r.z;
+    nd.aux[i] = au.x; nd.auy[i] = au.y; nd.auz[i] = au.z;
+    nd.avx[i] = av.x; nd.avy[i] = av.y; nd.avz[i] = av.z;
+    nd.w[i] = w[ll] * w[kk];
+    nd.u[i] = u; nd.v[i] = v;
+}
+
+// Per patch: centre point r(0,0), corner-diagonal diameter, and a radius
+// bounding the patch around the centre (1.25 x the farthest corner or edge
+// midpoint), used only to skip patches that cannot be near.
+__global__ void k_patch_info(const PatchDev* __restrict__ patches, const ObjDev* __restrict__ objs,
+                             int n_patches, double* __restrict__ info) {
+    int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= n_patches) return;
+    const PatchDev P = patches[p];
+    const ObjDev O = objs[P.obj];
+    V3 c, au, av, r[8];
+    patch_eval(P, O, 0.0, 0.0, c, au, av);
+    const double us[8] = {-1, 1, 1, -1, 0, 1, 0, -1};
+    const double vs[8] = {-1, -1, 1, 1, -1, 0, 1, 0};
+    double rad = 0.0;
+    for (int t = 0; t < 8; ++t) {
+        patch_eval(P, O, us[t], vs[t], r[t], au, av);
+        rad = fmax(rad, norm(r[t] - c));
+    }
+    const double diam = fmax(norm(r[0] - r[2]), norm(r[1] - r[3]));
+    info[5 * p + 0] = c.x;
+    info[5 * p + 1] = c.y;
+    info[5 * p + 2] = c.z;
+    info[5 * p + 3] = diam;
+    info[5 * p + 4] = 1.25 * rad;
+}
+
+// Closest point of the patch to `t`: Gauss-Newton on |r(u,v) - t|^2 from
+// the patch centre, each iterate clamped to the square.
+__device__ inline double project(const PatchDev& P, const ObjDev& O, V3 t, double& uo, double& vo) {
+    double u = 0.0, v = 0.0;
+    V3 r, au, av;
+    for (int it = 0; it < 80; ++it) {
+        patch_eval(P, O, u, v, r, au, av);
+        const V3 d = r - t;
+        const double g0 = dot(d, au), g1 = dot(d, av);
+        const double h00 = dot(au, au), h01 = dot(au, av), h11 = dot(av, av);
+        const double det = h00 * h11 - h01 * h01;
+        const double du = (h11 * g0 - h01 * g1) / det;
+        const double dv = (h00 * g1 - h01 * g0) / det;
+        const double un = fmin(1.0, fmax(-1.0, u - du));
+        const double vn = fmin(1.0, fmax(-1.0, v - dv));
+        const bool done = fabs(un - u) + fabs(vn - v) < 1e-15;
+        u = un; v = vn;
+        if (done) break;
+    }
+    patch_eval(P, O, u, v, r, au, av);
+    uo = u; vo = v;
+    return norm(r - t);
+}
+
+// Near test of one (node, patch) pair; fills (u*, v*, dist) when near.
+__device__ inline bool near_test(const PatchDev* patches, const ObjDev* objs, const double* info,
+                                 const NodeArrays& nd, int i, int p, int own, double delta,
+                                 double& us, double& vs, double& dist) {
+    if (p == own) {
+        us = nd.u[i]; vs = nd.v[i]; dist = 0.0;
+        return true;
+    }
+    const V3 t = v3(nd.rx[i], nd.ry[i], nd.rz[i]);
+    const V3 c = v3(info[5 * p], info[5 * p + 1], info[5 * p + 2]);
+    const double diam = info[5 * p + 3];
+    if (norm(t - c) >= delta * diam + info[5 * p + 4]) return false;
+    const PatchDev P = patches[p];
+    dist = project(P, objs[P.obj], t, us, vs);
+    return dist < delta * diam;
+}
+
+// Pass 1: count near patches per node.  Pass 2: write them in patch order.
+__global__ void k_near(const PatchDev* __restrict__ patches, const ObjDev* __restrict__ objs,
+                       const double* __restrict__ info, const int* __restrict__ node_patch,
+                       const int* __restrict__ obj_patch0, const int* __restrict__ obj_npatch,
+                       NodeArrays nd, int n_nodes, double delta, int* __restrict__ counts,
+                       const int64_t* __restrict__ offsets, NearPair* __restrict__ out) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_nodes) return;
+    const int own = node_patch[i];
+    const int ob = patches[own].obj;
+    const int p0 = obj_patch0[ob], p1 = p0 + obj_npatch[ob];
+    int cnt = 0;
+    int64_t pos = offsets ? offsets[i] : 0;
+    for (int p = p0; p < p1; ++p) {
+        double us, vs, dist;
+        if (near_test(patches, objs, info, nd, i, p, own, delta, us, vs, dist)) {
+            if (out) {
+                NearPair e;
+                e.target = i; e.patch = p; e.us = us; e.vs = vs; e.dist = dist;
+                e.self = (p == own);
+                out[pos + cnt] = e;
+            }
+            ++cnt;
+        }
+    }
+    if (!out) counts[i] = cnt;
+}
+
+// ------------------------------------------------- singular / near quadrature
+// Barycentric Lagrange basis at first-kind Chebyshev points (ascending):
+// ell_l(x) = [lam_l/(x - x_l)] / sum_m [lam_m/(x - x_m)],
+// lam_l = (-1)^l sin((2l+1) pi / (2q)).
+__device__ inline void lagrange(int q, const double* xn, double x, double* L) {
+    for (int l = 0; l < q; ++l) {
+        if (x == xn[l]) {
+            for (int m = 0; m < q; ++m) L[m] = (m == l) ? 1.0 : 0.0;
+            return;
+        }
+    }
+    double den = 0.0;
+    for (int l = 0; l < q; ++l) {
+        const double lam = ((l & 1) ? -1.0 : 1.0) * sin((2 * l + 1) * M_PI / (2.0 * q));
+        L[l] = lam / (x - xn[l]);
+        den += L[l];
+    }
+    const double inv = 1.0 / den;
+    for (int l = 0; l < q; ++l) L[l] *= inv;
+}
+
+// One work-group of 256 threads per (target node, source patch) pair.
+//
+// Change of variables (the singularity-cancelling step of Sec. II-B, eq. 20):
+// [-1,1]^2 is cut at the singular point P = (u*, v*) into up to four
+// rectangles with corner P; each rectangle into two triangles along its
+// diagonal; on a triangle x = P + s (a, t b) (or P + s (t a, b)) the Duffy
+// Jacobian s|ab| cancels the 1/R singularity.  The angular variable uses
+// t = (L1/L2) sinh(sigma asinh(L2/L1)) (L1 the leg along the axis, L2 the
+// far side), which flattens the angular peak of thin rectangles.  Radially:
+// self pairs use a plain Fejer rule in s; near pairs (target off the patch
+// at parameter distance d) use s = e sinh(sigma asinh(s1/e)) on [0, s1],
+// e = d/|ray|, s1 = min(1/2, 6e), and a plain Fejer rule on [s1, 1].
+// All 1D rules are Fejer-1 on [0, 1] (tables fej_x, fej_w at offset n(n-1)/2).
+//
+// Contraction: thread (b, a, k, l) accumulates
+//   sum_points w K[b][a](x) ell_k(v) ell_l(u)
+// over point tiles staged in LDS.
+struct QuadPointLDS {
+    double kw[256][8];   // w K (4 complex) per point
+    double lu[256][8];
+    double lv[256][8];
+};
+
+__global__ __launch_bounds__(256) void k_quad(
+    const PatchDev* __restrict__ patches, const ObjDev* __restrict__ objs, NodeArrays nd,
+    const NearPair* __restrict__ pairs, int64_t n_pairs, const double* __restrict__ fej11_x,
+    const double* __restrict__ fej_x, const double* __restrict__ fej_w, QuadRule rule,
+    int64_t stride, zd* __restrict__ out) {
+    __shared__ QuadPointLDS S;
+    __shared__ double s_tri[8][6];   // per triangle: a, b, L1/L2, hi, kind(0/1), valid
+    __shared__ int s_ntri;
+    const int64_t pid = blockIdx.x;
+    if (pid >= n_pairs) return;
+    const NearPair E = pairs[pid];
+    const PatchDev P = patches[E.patch];
+    const ObjDev O = objs[P.obj];
+    const int q = P.q;
+    const int i = E.target;
+    const V3 rt = v3(nd.rx[i], nd.ry[i], nd.rz[i]);
+    const V3 aut = v3(nd.aux[i], nd.auy[i], nd.auz[i]);
+    const V3 avt = v3(nd.avx[i], nd.avy[i], nd.avz[i]);
+    const double us = E.us, vs = E.vs;
+    const double* xq = fej11_x + q * (q - 1) / 2;   // the patch's own Chebyshev points
+    const int tid = threadIdx.x;
+
+    if (tid == 0) {
+        int nt = 0;
+        for (int iu = 0; iu < 2; ++iu) {
+            const double a = (iu ? 1.0 : -1.0) - us;
+            if (fabs(a) < 1e-14) continue;
+            for (int iv = 0; iv < 2; ++iv) {
+                const double b = (iv ? 1.0 : -1.0) - vs;
+                if (fabs(b) < 1e-14) continue;
+                for (int kind = 0; kind < 2; ++kind) {
+                    const double L1 = kind ? fabs(b) : fabs(a);
+                    const double L2 = kind ? fabs(a) : fabs(b);
+                    s_tri[nt][0] = a;
+                    s_tri[nt][1] = b;
+                    s_tri[nt][2] = L1 / L2;
+                    s_tri[nt][3] = asinh(L2 / L1);
+                    s_tri[nt][4] = kind;
+                    ++nt;
+                }
+            }
+        }
+        s_ntri = nt;
+    }
+    __syncthreads();
+    const int ntri = s_ntri;
+
+    // near: parameter distance of the target from the projection point
+    double dpar = 0.0;
+    if (!E.self) {
+        V3 r0, au0, av0;
+        patch_eval(P, O, us, vs, r0, au0, av0);
+        dpar = E.dist / sqrt(norm(au0) * norm(av0));
+    }
+    const int nt = rule.n_ang;
+    const int nr = E.self ? rule.n_rad : (rule.n_in + rule.n_out);
+    const int64_t npts = (int64_t)ntri * nt * nr;
+    const double* tx = fej_x + rule.off_ang;
+    const double* tw = fej_w + rule.off_ang;
+
+    // output ownership
+    const int q2 = q * q;
+    const int nout = 4 * q2;
+    const bool owner = tid < nout;
+    const int ba = owner ? tid / q2 : 0;      // b * 2 + a
+    const int kl = owner ? tid % q2 : 0;
+    const int ok = kl / q, ol = kl % q;
+    double acc_re = 0.0, acc_im = 0.0;
+
+    for (int64_t base = 0; base < npts; base += 256) {
+        const int64_t pidx = base + tid;
+        double kw[8];
+        double Lu[8], Lv[8];
+        for (int c = 0; c < 8; ++c) { kw[c] = 0.0; Lu[c] = 0.0; Lv[c] = 0.0; }
+        if (pidx < npts) {
+            const int tri = (int)(pidx / ((int64_t)nt * nr));
+            const int rem = (int)(pidx % ((int64_t)nt * nr));
+            const int it = rem / nr, ir = rem % nr;
+            const double a = s_tri[tri][0], b = s_tri[tri][1];
+            const double ratio = s_tri[tri][2], hi = s_tri[tri][3];
+            const int kind = (int)s_tri[tri][4];
+            const double sig = tx[it];
+            const double t = ratio * sinh(hi * sig);
+            const double wt = tw[it] * hi * ratio * cosh(hi * sig);
+            const double eu = kind ? t * a : a;
+            const double ev = kind ? b : t * b;
+            double s, ws;
+            if (E.self) {
+                s = fej_x[rule.off_rad + ir];
+                ws = fej_w[rule.off_rad + ir];
+            } else {
+                const double rho = sqrt(eu * eu + ev * ev);
+                const double e = dpar / rho;
+                const double s1 = fmin(0.5, 6.0 * e);
+                if (ir < rule.n_in) {
+                    const double h2 = asinh(s1 / e);
+                    const double sg = fej_x[rule.off_in + ir];
+                    s = e * sinh(h2 * sg);
+                    ws = fej_w[rule.off_in + ir] * h2 * e * cosh(h2 * sg);
+                } else {
+                    const int jr = ir - rule.n_in;
+                    s = s1 + (1.0 - s1) * fej_x[rule.off_out + jr];
+                    ws = fej_w[rule.off_out + jr] * (1.0 - s1);
+                }
+            }
+            const double du = s * eu, dv = s * ev;
+            const double u = us + du, v = vs + dv;
+            const double wgt = wt * ws * s * fabs(a * b);
+            V3 r, au, av;
+            patch_eval(P, O, u, v, r, au, av);
+            const V3 R = E.self ? patch_delta(P, O, us, vs, du, dv) : (rt - r);
+            zd K[2][2];
+            mfie_kernel(O.k0, R, aut, avt, au, av, K);
+            kw[0] = wgt * K[0][0].re; kw[1] = wgt * K[0][0].im;
+            kw[2] = wgt * K[0][1].re; kw[3] = wgt * K[0][1].im;
+            kw[4] = wgt * K[1][0].re; kw[5] = wgt * K[1][0].im;
+            kw[6] = wgt * K[1][1].re; kw[7] = wgt * K[1][1].im;
+            lagrange(q, xq, u, Lu);
+            lagrange(q, xq, v, Lv);
+        }
+        __syncthreads();
+        for (int c = 0; c < 8; ++c) {
+            S.kw[tid][c] = kw[c];
+            S.lu[tid][c] = Lu[c];
+            S.lv[tid][c] = Lv[c];
+        }
+        __syncthreads();
+        if (owner) {
+            const int cnt = (int)min((int64_t)256, npts - base);
+            for (int pnt = 0; pnt < cnt; ++pnt) {
+                const double bb = S.lv[pnt][ok] * S.lu[pnt][ol];
+                acc_re = fma(S.kw[pnt][2 * ba], bb, acc_re);
+                acc_im = fma(S.kw[pnt][2 * ba + 1], bb, acc_im);
+            }
+        }
+    }
+    if (owner) {
+        const int b = ba >> 1, a = ba & 1;
+        // identity term 1/2 F^b at the target node itself
+        if (E.self && a == b && (P.node0 + kl) == i) acc_re += 0.5;
+        out[pid * stride + ((int64_t)b * q2 + kl) * 2 + a] = zd{acc_re, acc_im};
+    }
+}
+
+// ------------------------------------------------------------- far fill
+// Dense block tile: 64 row nodes x 16 column nodes per work-group; thread
+// (ti, tj4) handles row node ti and four column nodes.  Entries use the
+// plain Fejer rule  A[(i,b),(j,a)] = w_j K[b][a](r_i - r_j).  Column-major
+// storage: rows 2i, 2i+1 of column 2j+a are adjacent, so a wave writes
+// 64 x 32 contiguous bytes per column.
+template <typename T>
+__global__ __launch_bounds__(256) void k_far_fill(const DenseTile* __restrict__ tiles, int n_tiles,
+                                                  const DenseBlockDev* __restrict__ blocks,
+                                                  const int* __restrict__ tree_node, NodeArrays nd,
+                                                  const ObjDev* __restrict__ objs,
+                                                  cplx<T>* __restrict__ store) {
+    const int tile = blockIdx.x;
+    if (tile >= n_tiles) return;
+    const DenseTile Tl = tiles[tile];
+    const DenseBlockDev B = blocks[Tl.block];
+    const int ti = Tl.row0 + (threadIdx.x & 63);
+    if (ti >= B.row_nodes) return;
+    const int gi = tree_node[B.row_node0 + ti];
+    const V3 ri = v3(nd.rx[gi], nd.ry[gi], nd.rz[gi]);
+    const V3 aui = v3(nd.aux[gi], nd.auy[gi], nd.auz[gi]);
+    const V3 avi = v3(nd.avx[gi], nd.avy[gi], nd.avz[gi]);
+    const double k = objs[B.obj].k0;
+    cplx<T>* base = store + B.offset;
+    for (int c = 0; c < 4; ++c) {
+        const int tj = Tl.col0 + (threadIdx.x >> 6) * 4 + c;
+        if (tj >= B.col_nodes) break;
+        const int gj = tree_node[B.col_node0 + tj];
+        zd K[2][2];
+        if (gi == gj) {
+            K[0][0] = K[0][1] = K[1][0] = K[1][1] = zd{0.0, 0.0};
+        } else {
+            const V3 R = ri - v3(nd.rx[gj], nd.ry[gj], nd.rz[gj]);
+            mfie_kernel(k, R, aui, avi, v3(nd.aux[gj], nd.auy[gj], nd.auz[gj]),
+                        v3(nd.avx[gj], nd.avy[gj], nd.avz[gj]), K);
+        }
+        const double w = nd.w[gj];
+        for (int a = 0; a < 2; ++a) {
+            cplx<T>* col = base + (int64_t)(2 * tj + a) * B.ld + 2 * ti;
+            col[0] = cplx<T>{(T)(w * K[0][a].re), (T)(w * K[0][a].im)};
+            col[1] = cplx<T>{(T)(w * K[1][a].re), (T)(w * K[1][a].im)};
+        }
+    }
+}
+
+// Overwrite the near/self entries of each pair in its dense block.
+template <typename T>
+__global__ void k_near_scatter(const NearDest* __restrict__ dest, int64_t n_pairs, int64_t stride,
+                               const zd* __restrict__ vals, const DenseBlockDev* __restrict__ blocks,
+                               cplx<T>* __restrict__ store) {
+    const int64_t pid = blockIdx.x;
+    if (pid >= n_pairs) return;
+    const NearDest D = dest[pid];
+    const int q2 = D.q2;
+    const DenseBlockDev B = blocks[D.block];
+    for (int t = threadIdx.x; t < 4 * q2; t += blockDim.x) {
+        const int b = t / (2 * q2);
+        const int rem = t % (2 * q2);
+        const int jl = rem / 2, a = rem % 2;
+        const zd v = vals[pid * stride + t];
+        const int64_t row = 2 * (int64_t)D.row_node + b;
+        const int64_t col = 2 * (int64_t)(D.col_node0 + jl) + a;
+        store[B.offset + col * B.ld + row] = cplx<T>{(T)v.re, (T)v.im};
+    }
+}
+
+template __global__ void k_far_fill<double>(const DenseTile*, int, const DenseBlockDev*, const int*,
+                                            NodeArrays, const ObjDev*, zd*);
+template __global__ void k_far_fill<float>(const DenseTile*, int, const DenseBlockDev*, const int*,
+                                           NodeArrays, const ObjDev*, zf*);
+template __global__ void k_near_scatter<double>(const NearDest*, int64_t, int64_t, const zd*,
+                                                const DenseBlockDev*, zd*);
+template __global__ void k_near_scatter<float>(const NearDest*, int64_t, int64_t, const zd*,
+                                               const DenseBlockDev*, zf*);
+
+}  // namespace cbie
+
+namespace cbie {
+
+// ----------------------------------------------------------- dense export
+// Scatter a dense block (tree order, column-major) into an N x N matrix in
+// the original unknown order.
+__global__ void k_export_dense_block(const DenseBlockDev* __restrict__ blocks, int n_blocks,
+                                     const int* __restrict__ tree_node, const zd* __restrict__ store,
+                                     zd* __restrict__ A, int64_t lda) {
+    const int bid = blockIdx.y;
+    if (bid >= n_blocks) return;
+    const DenseBlockDev B = blocks[bid];
+    const int64_t m = 2 * (int64_t)B.row_nodes, n = 2 * (int64_t)B.col_nodes;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m * n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t r = e % m, c = e / m;
+        const int64_t gr = 2 * (int64_t)tree_node[B.row_node0 + r / 2] + (r & 1);
+        const int64_t gc = 2 * (int64_t)tree_node[B.col_node0 + c / 2] + (c & 1);
+        A[gc * lda + gr] = store[B.offset + c * B.ld + r];
+    }
+}
+
+// Plain-rule entries of a block (used for admissible blocks before
+// compression), written in the original order.
+__global__ void k_export_far(const DenseBlockDev* __restrict__ blocks, int n_blocks,
+                             const int* __restrict__ tree_node, NodeArrays nd,
+                             const ObjDev* __restrict__ objs, zd* __restrict__ A, int64_t lda) {
+    const int bid = blockIdx.y;
+    if (bid >= n_blocks) return;
+    const DenseBlockDev B = blocks[bid];
+    const int64_t np = (int64_t)B.row_nodes * B.col_nodes;
+    const double k = objs[B.obj].k0;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < np;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int gi = tree_node[B.row_node0 + e % B.row_nodes];
+        const int gj = tree_node[B.col_node0 + e / B.row_nodes];
+        const V3 R = v3(nd.rx[gi] - nd.rx[gj], nd.ry[gi] - nd.ry[gj], nd.rz[gi] - nd.rz[gj]);
+        zd K[2][2];
+        mfie_kernel(k, R, v3(nd.aux[gi], nd.auy[gi], nd.auz[gi]), v3(nd.avx[gi], nd.avy[gi], nd.avz[gi]),
+                    v3(nd.aux[gj], nd.auy[gj], nd.auz[gj]), v3(nd.avx[gj], nd.avy[gj], nd.avz[gj]), K);
+        const double w = nd.w[gj];
+        for (int b = 0; b < 2; ++b)
+            for (int a = 0; a < 2; ++a)
+                A[(2 * (int64_t)gj + a) * lda + 2 * (int64_t)gi + b] = zd{w * K[b][a].re, w * K[b][a].im};
+    }
+}
+
+}  // namespace cbie
