@@ -1,0 +1,333 @@
+// Batched adaptive cross approximation of the admissible blocks (Sec. III;
+// ACA with partial pivoting, the paper's ref. [22]) and the low-rank store.
+#include <algorithm>
+#include <cmath>
+
+#include "ctx.hpp"
+#include "lowrank.hpp"
+
+namespace cbie {
+
+// ---------------------------------------------------------------- reductions
+struct ArgMax {
+    double v;
+    int i;
+};
+__device__ inline ArgMax better(ArgMax a, ArgMax b) {
+    // larger value wins; ties go to the lower index
+    if (b.v > a.v || (b.v == a.v && b.i < a.i)) return b;
+    return a;
+}
+__device__ inline ArgMax wave_argmax(ArgMax a) {
+    for (int off = 32; off > 0; off >>= 1) {
+        ArgMax o;
+        o.v = __shfl_xor(a.v, off);
+        o.i = __shfl_xor(a.i, off);
+        a = better(a, o);
+    }
+    return a;
+}
+__device__ inline double wave_sum(double x) {
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    return x;
+}
+// block of 256 threads (4 waves)
+__device__ inline ArgMax block_argmax(ArgMax a, ArgMax* sh) {
+    a = wave_argmax(a);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = a;
+    __syncthreads();
+    ArgMax r = sh[0];
+    for (int k = 1; k < 4; ++k) r = better(r, sh[k]);
+    return r;
+}
+__device__ inline double block_sum(double x, double* sh) {
+    x = wave_sum(x);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = x;
+    __syncthreads();
+    return sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// MFIE entries of one (target node, source node) pair, far rule.
+__device__ inline void far_pair(const NodeArrays& nd, double k, int gi, int gj, zd K[2][2]) {
+    const V3 R = v3(nd.rx[gi] - nd.rx[gj], nd.ry[gi] - nd.ry[gj], nd.rz[gi] - nd.rz[gj]);
+    mfie_kernel(k, R, v3(nd.aux[gi], nd.auy[gi], nd.auz[gi]), v3(nd.avx[gi], nd.avy[gi], nd.avz[gi]),
+                v3(nd.aux[gj], nd.auy[gj], nd.auz[gj]), v3(nd.avx[gj], nd.avy[gj], nd.avz[gj]), K);
+    const double w = nd.w[gj];
+    for (int b = 0; b < 2; ++b)
+        for (int a = 0; a < 2; ++a) K[b][a] = zd{w * K[b][a].re, w * K[b][a].im};
+}
+
+// One work-group of 256 threads per admissible block M (m x n, m = 2 row
+// nodes, n = 2 column nodes), M ~ sum_k u_k v_k^T:
+//   row i_k -> residual row r (written into V[:, k]); pivot j_k = argmax |r|
+//   (lowest index on ties), skipping rows whose residual vanishes;
+//   v_k = r / r[j_k]; u_k = residual column j_k (written into U[:, k]);
+//   |S_k|^2 += 2 Re sum_{l<k} (u_l^H u_k)(v_l^H v_k) + |u_k|^2 |v_k|^2;
+//   stop when |u_k| |v_k| <= tol |S_k|, else i_{k+1} = argmax |u_k| over
+//   unused rows.  Columns are generated on the fly from the far rule (an
+//   admissible block holds no near pair).
+__global__ __launch_bounds__(256) void k_aca(const AcaJob* __restrict__ jobs, int n_jobs,
+                                             const int* __restrict__ tree_node, NodeArrays nd,
+                                             const ObjDev* __restrict__ objs, double tol,
+                                             zd* __restrict__ ws, unsigned char* __restrict__ used_ws,
+                                             int* __restrict__ rank_out, int* __restrict__ flag_out) {
+    const int jb = blockIdx.x;
+    if (jb >= n_jobs) return;
+    const AcaJob J = jobs[jb];
+    const int m = 2 * J.row_nodes, n = 2 * J.col_nodes;
+    zd* U = ws + J.u_off;   // m x cap
+    zd* V = ws + J.v_off;   // n x cap
+    unsigned char* used = used_ws + J.used_off;
+    const double k0 = objs[J.obj].k0;
+    __shared__ ArgMax sh_am[4];
+    __shared__ double sh_s[4];
+    __shared__ zd s_coef[1024];       // U[i, l] (row step) or V[j, l] (column step)
+    __shared__ double s_cross[2];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < m; i += 256) used[i] = 0;
+    __syncthreads();
+
+    int irow = 0;
+    int rank = 0;
+    double s2 = 0.0;
+    int converged = 0;
+    const int cap = J.cap;
+    while (rank < cap) {
+        // residual row irow into V[:, rank]
+        for (int l = tid; l < rank; l += 256) s_coef[l] = U[(int64_t)l * m + irow];
+        if (tid == 0) used[irow] = 1;
+        __syncthreads();
+        const int gi = tree_node[J.row_node0 + irow / 2];
+        const int b = irow & 1;
+        zd* vk = V + (int64_t)rank * n;
+        ArgMax am{-1.0, 0x7fffffff};
+        for (int jn = tid; jn < J.col_nodes; jn += 256) {
+            const int gj = tree_node[J.col_node0 + jn];
+            zd K[2][2];
+            far_pair(nd, k0, gi, gj, K);
+            for (int a = 0; a < 2; ++a) {
+                const int j = 2 * jn + a;
+                zd r = K[b][a];
+                for (int l = 0; l < rank; ++l) r = r - s_coef[l] * V[(int64_t)l * n + j];
+                vk[j] = r;
+                am = better(am, ArgMax{abs2(r), j});
+            }
+        }
+        am = block_argmax(am, sh_am);
+        if (am.v <= 0.0) {
+            // zero residual row: try the next unused row, stop if none
+            __syncthreads();
+            ArgMax nx{-1.0, 0x7fffffff};
+            for (int i = tid; i < m; i += 256)
+                if (!used[i]) nx = better(nx, ArgMax{0.0, i});
+            nx = block_argmax(nx, sh_am);
+            if (nx.v < 0.0) { converged = 1; break; }
+            irow = nx.i;
+            continue;
+        }
+        const int jp = am.i;
+        const zd piv = vk[jp];
+        __syncthreads();
+        // v_k = r / pivot
+        for (int j = tid; j < n; j += 256) vk[j] = cdiv(vk[j], piv);
+        for (int l = tid; l < rank; l += 256) s_coef[l] = V[(int64_t)l * n + jp];
+        __syncthreads();
+        // residual column jp into U[:, rank]
+        const int gj = tree_node[J.col_node0 + jp / 2];
+        const int a = jp & 1;
+        zd* uk = U + (int64_t)rank * m;
+        ArgMax nx{-1.0, 0x7fffffff};
+        double nu2 = 0.0;
+        for (int in = tid; in < J.row_nodes; in += 256) {
+            const int gi2 = tree_node[J.row_node0 + in];
+            zd K[2][2];
+            far_pair(nd, k0, gi2, gj, K);
+            for (int bb = 0; bb < 2; ++bb) {
+                const int i = 2 * in + bb;
+                zd c = K[bb][a];
+                for (int l = 0; l < rank; ++l) c = c - s_coef[l] * U[(int64_t)l * m + i];
+                uk[i] = c;
+                nu2 += abs2(c);
+                if (!used[i]) nx = better(nx, ArgMax{abs2(c), i});
+            }
+        }
+        double nv2 = 0.0;
+        for (int j = tid; j < n; j += 256) nv2 += abs2(vk[j]);
+        nu2 = block_sum(nu2, sh_s);
+        nv2 = block_sum(nv2, sh_s);
+        nx = block_argmax(nx, sh_am);
+        // cross terms 2 Re sum_l (u_l^H u_k)(v_l^H v_k): wave w handles l = w, w+4, ...
+        double cross = 0.0;
+        {
+            const int w = tid >> 6, lane = tid & 63;
+            for (int l = w; l < rank; l += 4) {
+                double ur = 0, ui = 0, vr = 0, vi = 0;
+                for (int i = lane; i < m; i += 64) {
+                    const zd x = U[(int64_t)l * m + i], y = uk[i];
+                    ur += x.re * y.re + x.im * y.im;
+                    ui += x.re * y.im - x.im * y.re;
+                }
+                for (int j = lane; j < n; j += 64) {
+                    const zd x = V[(int64_t)l * n + j], y = vk[j];
+                    vr += x.re * y.re + x.im * y.im;
+                    vi += x.re * y.im - x.im * y.re;
+                }
+                ur = wave_sum(ur); ui = wave_sum(ui); vr = wave_sum(vr); vi = wave_sum(vi);
+                cross += ur * vr - ui * vi;
+            }
+            if (lane == 0) sh_s[w] = cross;
+            __syncthreads();
+            if (tid == 0) s_cross[0] = sh_s[0] + sh_s[1] + sh_s[2] + sh_s[3];
+            __syncthreads();
+            cross = s_cross[0];
+        }
+        s2 += 2.0 * cross + nu2 * nv2;
+        ++rank;
+        if (nu2 * nv2 <= tol * tol * fabs(s2)) { converged = 1; break; }
+        if (nx.v < 0.0) { converged = 1; break; }   // every row used
+        irow = nx.i;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        rank_out[jb] = rank;
+        flag_out[jb] = converged;
+    }
+}
+
+// Copy the first `rank` columns of the ACA workspace into the compact store.
+__global__ void k_lr_compact(const AcaJob* __restrict__ jobs, int n_jobs, const zd* __restrict__ ws,
+                             const int* __restrict__ rank, const int64_t* __restrict__ u_dst,
+                             const int64_t* __restrict__ v_dst, zd* __restrict__ store) {
+    const int jb = blockIdx.y;
+    if (jb >= n_jobs) return;
+    const AcaJob J = jobs[jb];
+    const int64_t m = 2 * (int64_t)J.row_nodes, n = 2 * (int64_t)J.col_nodes, r = rank[jb];
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (m + n) * r;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        if (e < m * r) store[u_dst[jb] + e] = ws[J.u_off + e];
+        else store[v_dst[jb] + (e - m * r)] = ws[J.v_off + (e - m * r)];
+    }
+}
+
+// Entries U V^T of each low-rank block, written in the original order.
+__global__ void k_export_lr(const DenseBlockDev* __restrict__ blocks, int n_blocks,
+                            const int64_t* __restrict__ u_off, const int64_t* __restrict__ v_off,
+                            const int* __restrict__ rank, const int* __restrict__ tree_node,
+                            const zd* __restrict__ store, zd* __restrict__ A, int64_t lda) {
+    const int bid = blockIdx.y;
+    if (bid >= n_blocks) return;
+    const DenseBlockDev B = blocks[bid];
+    const int64_t m = 2 * (int64_t)B.row_nodes, n = 2 * (int64_t)B.col_nodes;
+    const int r = rank[bid];
+    const zd* U = store + u_off[bid];
+    const zd* V = store + v_off[bid];
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m * n;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = e % m, j = e / m;
+        zd s{0.0, 0.0};
+        for (int l = 0; l < r; ++l) cfma(s, U[l * m + i], V[l * n + j]);
+        const int64_t gr = 2 * (int64_t)tree_node[B.row_node0 + i / 2] + (i & 1);
+        const int64_t gc = 2 * (int64_t)tree_node[B.col_node0 + j / 2] + (j & 1);
+        A[gc * lda + gr] = s;
+    }
+}
+
+void stage_compress(Ctx& c, double tol, int mode) {
+    (void)mode;   // rank prediction is layered on top of the adaptive pass
+    const double t0 = now_s();
+    const int nb = (int)c.lblk.size();
+    c.aca_tol = tol;
+    c.lr.u_off.assign(nb, 0);
+    c.lr.v_off.assign(nb, 0);
+    c.lr.rank.assign(nb, 0);
+    c.lr.cap.assign(nb, 0);
+    int64_t lr_entries = 0, max_rank = 0, sum_rank = 0;
+    if (nb > 0) {
+        // workspace: U (m x cap) and V (n x cap) per block
+        std::vector<AcaJob> jobs(nb);
+        int64_t off = 0, uoff = 0;
+        for (int b = 0; b < nb; ++b) {
+            const DenseBlockDev& d = c.lblk[b];
+            AcaJob& J = jobs[b];
+            J.row_node0 = d.row_node0;
+            J.row_nodes = d.row_nodes;
+            J.col_node0 = d.col_node0;
+            J.col_nodes = d.col_nodes;
+            J.obj = d.obj;
+            const int m = 2 * d.row_nodes, n = 2 * d.col_nodes;
+            J.cap = std::min({m, n, kAcaMaxRank});
+            J.u_off = off;
+            off += (int64_t)m * J.cap;
+            J.v_off = off;
+            off += (int64_t)n * J.cap;
+            J.used_off = uoff;
+            uoff += m;
+        }
+        DBuf<zd> ws;
+        ws.alloc(off);
+        DBuf<unsigned char> used;
+        used.alloc(uoff);
+        DBuf<AcaJob> d_jobs;
+        d_jobs.upload(jobs, c.stream);
+        DBuf<int> d_rank, d_flag;
+        d_rank.alloc(nb);
+        d_flag.alloc(nb);
+        k_aca<<<nb, 256, 0, c.stream>>>(d_jobs.p, nb, c.d_tree_node.p, c.nd, c.d_objs.p, tol, ws.p, used.p,
+                                        d_rank.p, d_flag.p);
+        check_launch("k_aca");
+        std::vector<int> flag(nb);
+        d_rank.download(c.lr.rank.data(), nb, c.stream);
+        d_flag.download(flag.data(), nb, c.stream);
+        c.sync();
+        int64_t so = 0;
+        for (int b = 0; b < nb; ++b) {
+            const int64_t m = 2 * (int64_t)c.lblk[b].row_nodes, n = 2 * (int64_t)c.lblk[b].col_nodes;
+            const int r = c.lr.rank[b];
+            c.lr.cap[b] = r;
+            c.lr.u_off[b] = so;
+            so += m * r;
+            c.lr.v_off[b] = so;
+            so += n * r;
+            lr_entries += (m + n) * r;
+            max_rank = std::max<int64_t>(max_rank, r);
+            sum_rank += r;
+            c.stats_unconverged += flag[b] ? 0 : 1;
+        }
+        c.lr.mem.alloc(std::max<int64_t>(so, 1));
+        DBuf<int64_t> du, dv;
+        du.upload(c.lr.u_off, c.stream);
+        dv.upload(c.lr.v_off, c.stream);
+        dim3 grid(32, nb);
+        k_lr_compact<<<grid, 256, 0, c.stream>>>(d_jobs.p, nb, ws.p, d_rank.p, du.p, dv.p, c.lr.mem.p);
+        check_launch("k_lr_compact");
+        c.lr.d_u_off.upload(c.lr.u_off, c.stream);
+        c.lr.d_v_off.upload(c.lr.v_off, c.stream);
+        c.lr.d_rank.upload(c.lr.rank, c.stream);
+        c.sync();
+    }
+    cbie_stats& st = c.stats;
+    st.lr_entries = lr_entries;
+    st.max_rank = max_rank;
+    st.sum_rank = sum_rank;
+    const double N = (double)c.n_unk;
+    double full = 0.0;
+    for (size_t o = 0; o < c.objs.size(); ++o) full += 4.0 * (double)c.obj_nodes[o] * c.obj_nodes[o];
+    st.compression_rate = 1.0 - (double)(st.dense_entries + lr_entries) / full;
+    (void)N;
+    st.t_compress = now_s() - t0;
+}
+
+void export_lowrank(Ctx& c, zd* A, long ld) {
+    const int nb = (int)c.lblk.size();
+    if (nb == 0) return;
+    dim3 grid(64, nb);
+    k_export_lr<<<grid, 256, 0, c.stream>>>(c.d_lblk.p, nb, c.lr.d_u_off.p, c.lr.d_v_off.p, c.lr.d_rank.p,
+                                            c.d_tree_node.p, c.lr.mem.p, A, ld);
+    check_launch("k_export_lr");
+}
+
+}  // namespace cbie

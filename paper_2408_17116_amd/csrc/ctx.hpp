@@ -19,6 +19,8 @@ template <typename T> struct LRStore {
     std::vector<int64_t> u_off, v_off;   // element offsets
     std::vector<int> rank, cap;          // current rank, capacity (columns)
     DBuf<cplx<T>> mem;
+    DBuf<int64_t> d_u_off, d_v_off;
+    DBuf<int> d_rank;
 };
 
 struct HMat;   // factorization state (hmat.hpp)
@@ -69,6 +71,13 @@ struct Ctx {
     std::vector<DenseBlockDev> lblk;        // geometry of low-rank blocks (same layout)
     DBuf<DenseBlockDev> d_lblk;
     double aca_tol = 1e-6;
+    int64_t stats_unconverged = 0;          // ACA blocks that hit the rank cap
+
+    // matvec scratch (V^T x per low-rank block)
+    std::vector<int64_t> mv_tmp_off;
+    DBuf<int64_t> d_mv_tmp_off;
+    DBuf<zd> mv_tmp;
+    int mv_tmp_nrhs = 0;
 
     // factorization
     std::shared_ptr<HMat> hm;   // type-erased deleter: HMat stays incomplete here

@@ -1,0 +1,300 @@
+// Operator application in FP64 (matvec, iterative-refinement residual),
+// plane-wave right-hand sides (eq. 22) and the far field of a solution.
+#include <algorithm>
+#include <cmath>
+
+#include "ctx.hpp"
+#include "ops.hpp"
+
+namespace cbie {
+
+// x (original order, ld) -> xt (tree order, ld_t = n_unk), nrhs columns
+template <typename T>
+__global__ void k_to_tree(const int* __restrict__ tree_node, int64_t n_unk, int nrhs, const zd* __restrict__ x,
+                          int64_t ld, cplx<T>* __restrict__ xt) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n_unk * nrhs) return;
+    const int64_t r = e / n_unk, u = e % n_unk;
+    const zd v = x[r * ld + 2 * (int64_t)tree_node[u >> 1] + (u & 1)];
+    xt[e] = cplx<T>{(T)v.re, (T)v.im};
+}
+
+template <typename T>
+__global__ void k_from_tree(const int* __restrict__ tree_node, int64_t n_unk, int nrhs,
+                            const cplx<T>* __restrict__ yt, zd* __restrict__ y, int64_t ld) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n_unk * nrhs) return;
+    const int64_t r = e / n_unk, u = e % n_unk;
+    const cplx<T> v = yt[e];
+    y[r * ld + 2 * (int64_t)tree_node[u >> 1] + (u & 1)] = zd{(double)v.re, (double)v.im};
+}
+
+template __global__ void k_to_tree<double>(const int*, int64_t, int, const zd*, int64_t, zd*);
+template __global__ void k_to_tree<float>(const int*, int64_t, int, const zd*, int64_t, zf*);
+template __global__ void k_from_tree<double>(const int*, int64_t, int, const zd*, zd*, int64_t);
+template __global__ void k_from_tree<float>(const int*, int64_t, int, const zf*, zd*, int64_t);
+
+__device__ inline void atomic_add_z(zd* p, zd v) {
+    atomicAdd(&p->re, v.re);
+    atomicAdd(&p->im, v.im);
+}
+
+// y[rows] += D x[cols] for every dense block; work-group = (block, 64-row
+// slice), rhs processed 8 at a time with x staged in LDS; FP64 accumulation.
+__global__ __launch_bounds__(256) void k_dense_mv(const DenseBlockDev* __restrict__ blocks, int nb,
+                                                  const zd* __restrict__ store, const zd* __restrict__ xt,
+                                                  zd* __restrict__ yt, int64_t n_unk, int nrhs) {
+    const int bid = blockIdx.y;
+    if (bid >= nb) return;
+    const DenseBlockDev B = blocks[bid];
+    const int m = 2 * B.row_nodes, n = 2 * B.col_nodes;
+    const int r0 = blockIdx.x * 64;
+    if (r0 >= m) return;
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;   // 4 groups split the columns
+    const int row = r0 + lane;
+    __shared__ zd sx[8][256];
+    __shared__ zd red[4][64][8];
+    const zd* D = store + B.offset;
+    const int64_t c0 = 2 * (int64_t)B.col_node0, rr0 = 2 * (int64_t)B.row_node0;
+    for (int rb = 0; rb < nrhs; rb += 8) {
+        const int nr = min(8, nrhs - rb);
+        zd acc[8];
+        for (int t = 0; t < 8; ++t) acc[t] = zd{0.0, 0.0};
+        for (int cb = 0; cb < n; cb += 256) {
+            const int nc = min(256, n - cb);
+            __syncthreads();
+            for (int t = threadIdx.x; t < nr * 256; t += 256) {
+                const int rr = t / 256, cc = t % 256;
+                sx[rr][cc] = cc < nc ? xt[(int64_t)(rb + rr) * n_unk + c0 + cb + cc] : zd{0.0, 0.0};
+            }
+            __syncthreads();
+            if (row < m) {
+                for (int cc = grp; cc < nc; cc += 4) {
+                    const zd a = D[(int64_t)(cb + cc) * B.ld + row];
+                    for (int t = 0; t < nr; ++t) cfma(acc[t], a, sx[t][cc]);
+                }
+            }
+        }
+        __syncthreads();
+        for (int t = 0; t < 8; ++t) red[grp][lane][t] = acc[t];
+        __syncthreads();
+        if (grp == 0 && row < m) {
+            for (int t = 0; t < nr; ++t) {
+                zd s = red[0][lane][t] + red[1][lane][t] + red[2][lane][t] + red[3][lane][t];
+                atomic_add_z(&yt[(int64_t)(rb + t) * n_unk + rr0 + row], s);
+            }
+        }
+    }
+}
+
+// tmp[l, r] = sum_j V[j, l] x[c0 + j, r] for each low-rank block (one
+// work-group per (block, l)).
+__global__ __launch_bounds__(256) void k_lr_vt(const DenseBlockDev* __restrict__ blocks, int nb,
+                                               const int64_t* __restrict__ v_off, const int* __restrict__ rank,
+                                               const int64_t* __restrict__ t_off, const zd* __restrict__ store,
+                                               const zd* __restrict__ xt, zd* __restrict__ tmp, int64_t n_unk,
+                                               int nrhs) {
+    const int bid = blockIdx.y;
+    if (bid >= nb) return;
+    const int l = blockIdx.x;
+    const int r = rank[bid];
+    if (l >= r) return;
+    const DenseBlockDev B = blocks[bid];
+    const int n = 2 * B.col_nodes;
+    const zd* V = store + v_off[bid] + (int64_t)l * n;
+    const int64_t c0 = 2 * (int64_t)B.col_node0;
+    __shared__ double sh[2][4];
+    for (int rr = 0; rr < nrhs; ++rr) {
+        double sr = 0.0, si = 0.0;
+        for (int j = threadIdx.x; j < n; j += 256) {
+            const zd a = V[j], b = xt[(int64_t)rr * n_unk + c0 + j];
+            sr += a.re * b.re - a.im * b.im;
+            si += a.re * b.im + a.im * b.re;
+        }
+        for (int off = 32; off > 0; off >>= 1) { sr += __shfl_xor(sr, off); si += __shfl_xor(si, off); }
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = sr; sh[1][threadIdx.x >> 6] = si; }
+        __syncthreads();
+        if (threadIdx.x == 0)
+            tmp[t_off[bid] + (int64_t)rr * r + l] =
+                zd{sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3], sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3]};
+    }
+}
+
+// y[r0 + i, r] += sum_l U[i, l] tmp[l, r]
+__global__ __launch_bounds__(256) void k_lr_u(const DenseBlockDev* __restrict__ blocks, int nb,
+                                              const int64_t* __restrict__ u_off, const int* __restrict__ rank,
+                                              const int64_t* __restrict__ t_off, const zd* __restrict__ store,
+                                              const zd* __restrict__ tmp, zd* __restrict__ yt, int64_t n_unk,
+                                              int nrhs) {
+    const int bid = blockIdx.y;
+    if (bid >= nb) return;
+    const DenseBlockDev B = blocks[bid];
+    const int m = 2 * B.row_nodes;
+    const int i = blockIdx.x * 256 + threadIdx.x;
+    if (i >= m) return;
+    const int r = rank[bid];
+    const zd* U = store + u_off[bid];
+    const zd* T = tmp + t_off[bid];
+    const int64_t r0 = 2 * (int64_t)B.row_node0;
+    for (int rr = 0; rr < nrhs; ++rr) {
+        zd s{0.0, 0.0};
+        for (int l = 0; l < r; ++l) cfma(s, U[(int64_t)l * m + i], T[(int64_t)rr * r + l]);
+        atomic_add_z(&yt[(int64_t)rr * n_unk + r0 + i], s);
+    }
+}
+
+// y_t = A x_t in tree order (FP64), y_t overwritten
+void apply_operator_tree(Ctx& c, int nrhs, const zd* xt, zd* yt) {
+    const int64_t N = c.n_unk;
+    CBIE_HIP(hipMemsetAsync(yt, 0, sizeof(zd) * N * nrhs, c.stream));
+    const int nd = (int)c.dblk.size();
+    if (nd > 0) {
+        int maxm = 0;
+        for (const auto& d : c.dblk) maxm = std::max(maxm, 2 * d.row_nodes);
+        dim3 grid(ceil_div(maxm, 64), nd);
+        k_dense_mv<<<grid, 256, 0, c.stream>>>(c.d_dblk.p, nd, c.dense.p, xt, yt, N, nrhs);
+        check_launch("k_dense_mv");
+    }
+    const int nl = (int)c.lblk.size();
+    if (nl > 0) {
+        if (c.mv_tmp_off.size() != (size_t)nl || c.mv_tmp_nrhs != nrhs) {
+            std::vector<int64_t> off(nl);
+            int64_t o = 0;
+            for (int b = 0; b < nl; ++b) { off[b] = o; o += (int64_t)c.lr.rank[b] * nrhs; }
+            c.mv_tmp_off = off;
+            c.d_mv_tmp_off.upload(off, c.stream);
+            c.mv_tmp.alloc(std::max<int64_t>(o, 1));
+            c.mv_tmp_nrhs = nrhs;
+        }
+        int maxr = 1, maxm = 0;
+        for (int b = 0; b < nl; ++b) {
+            maxr = std::max(maxr, c.lr.rank[b]);
+            maxm = std::max(maxm, 2 * c.lblk[b].row_nodes);
+        }
+        k_lr_vt<<<dim3(maxr, nl), 256, 0, c.stream>>>(c.d_lblk.p, nl, c.lr.d_v_off.p, c.lr.d_rank.p,
+                                                       c.d_mv_tmp_off.p, c.lr.mem.p, xt, c.mv_tmp.p, N, nrhs);
+        check_launch("k_lr_vt");
+        k_lr_u<<<dim3(ceil_div(maxm, 256), nl), 256, 0, c.stream>>>(c.d_lblk.p, nl, c.lr.d_u_off.p,
+                                                                     c.lr.d_rank.p, c.d_mv_tmp_off.p,
+                                                                     c.lr.mem.p, c.mv_tmp.p, yt, N, nrhs);
+        check_launch("k_lr_u");
+    }
+}
+
+void stage_matvec(Ctx& c, int nrhs, const zd* x, zd* y, long ld) {
+    const int64_t N = c.n_unk;
+    DBuf<zd> xt, yt;
+    xt.alloc(N * nrhs);
+    yt.alloc(N * nrhs);
+    const unsigned g = ceil_div(N * nrhs, 256);
+    k_to_tree<double><<<g, 256, 0, c.stream>>>(c.d_tree_node.p, N, nrhs, x, ld, xt.p);
+    check_launch("k_to_tree");
+    apply_operator_tree(c, nrhs, xt.p, yt.p);
+    k_from_tree<double><<<g, 256, 0, c.stream>>>(c.d_tree_node.p, N, nrhs, yt.p, y, ld);
+    check_launch("k_from_tree");
+    c.sync();
+}
+
+// --------------------------------------------------------------- RHS (eq. 22)
+// b_u = -a_v . H_inc, b_v = a_u . H_inc, H_inc = khat x pol e^{-j k khat.r}
+__global__ void k_rhs(NodeArrays nd, const int* __restrict__ node_patch, const PatchDev* __restrict__ patches,
+                      const ObjDev* __restrict__ objs, int n_nodes, int nw, const double* __restrict__ kp,
+                      zd* __restrict__ b, int64_t ld) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= (int64_t)n_nodes * nw) return;
+    const int w = (int)(e / n_nodes), i = (int)(e % n_nodes);
+    const double k = objs[patches[node_patch[i]].obj].k0;
+    const V3 kh = v3(kp[6 * w], kp[6 * w + 1], kp[6 * w + 2]);
+    const V3 po = v3(kp[6 * w + 3], kp[6 * w + 4], kp[6 * w + 5]);
+    const V3 r = v3(nd.rx[i], nd.ry[i], nd.rz[i]);
+    double s, cs;
+    sincos(k * dot(kh, r), &s, &cs);        // e^{-j phi} = cos - j sin
+    const V3 h = cross(kh, po);
+    const V3 au = v3(nd.aux[i], nd.auy[i], nd.auz[i]);
+    const V3 av = v3(nd.avx[i], nd.avy[i], nd.avz[i]);
+    const double cu = -dot(av, h), cv = dot(au, h);
+    b[(int64_t)w * ld + 2 * i] = zd{cu * cs, -cu * s};
+    b[(int64_t)w * ld + 2 * i + 1] = zd{cv * cs, -cv * s};
+}
+
+void stage_rhs(Ctx& c, int nw, const double* khat, const double* pol, zd* b, long ld) {
+    std::vector<double> kp(6 * (size_t)nw);
+    for (int w = 0; w < nw; ++w)
+        for (int d = 0; d < 3; ++d) { kp[6 * w + d] = khat[3 * w + d]; kp[6 * w + 3 + d] = pol[3 * w + d]; }
+    DBuf<double> d_kp;
+    d_kp.upload(kp, c.stream);
+    k_rhs<<<ceil_div((int64_t)c.n_nodes * nw, 256), 256, 0, c.stream>>>(
+        c.nd, c.d_node_patch.p, c.d_patches.p, c.d_objs.p, c.n_nodes, nw, d_kp.p, b, ld);
+    check_launch("k_rhs");
+    c.sync();
+}
+
+// ---------------------------------------------------------------- far field
+// N(rhat) = sum_nodes w (F^u a_u + F^v a_v) e^{j k rhat.r};  E = -j k N_perp / (4 pi).
+// One work-group per (direction, rhs).
+__global__ __launch_bounds__(256) void k_farfield(NodeArrays nd, const int* __restrict__ node_patch,
+                                                  const PatchDev* __restrict__ patches,
+                                                  const ObjDev* __restrict__ objs, int n_nodes,
+                                                  const zd* __restrict__ x, int64_t ld, int ndir,
+                                                  const double* __restrict__ rhat, zd* __restrict__ E) {
+    const int d = blockIdx.x, r = blockIdx.y;
+    if (d >= ndir) return;
+    const V3 rh = v3(rhat[3 * d], rhat[3 * d + 1], rhat[3 * d + 2]);
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    double kk = 0.0;
+    for (int i = threadIdx.x; i < n_nodes; i += 256) {
+        const double k = objs[patches[node_patch[i]].obj].k0;
+        kk = k;
+        const zd fu = x[(int64_t)r * ld + 2 * i], fv = x[(int64_t)r * ld + 2 * i + 1];
+        double s, cs;
+        sincos(k * dot(rh, v3(nd.rx[i], nd.ry[i], nd.rz[i])), &s, &cs);   // e^{+j phi}
+        const double w = nd.w[i];
+        const double au[3] = {nd.aux[i], nd.auy[i], nd.auz[i]};
+        const double av[3] = {nd.avx[i], nd.avy[i], nd.avz[i]};
+        for (int c = 0; c < 3; ++c) {
+            const double jr = w * (fu.re * au[c] + fv.re * av[c]);
+            const double ji = w * (fu.im * au[c] + fv.im * av[c]);
+            acc[2 * c] += jr * cs - ji * s;
+            acc[2 * c + 1] += jr * s + ji * cs;
+        }
+    }
+    __shared__ double sh[6][4];
+    __shared__ double shk[4];
+    for (int c = 0; c < 6; ++c) {
+        double v = acc[c];
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+        if ((threadIdx.x & 63) == 0) sh[c][threadIdx.x >> 6] = v;
+    }
+    double km = kk;
+    for (int off = 32; off > 0; off >>= 1) km = fmax(km, __shfl_xor(km, off));
+    if ((threadIdx.x & 63) == 0) shk[threadIdx.x >> 6] = km;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double N[6];
+        for (int c = 0; c < 6; ++c) N[c] = sh[c][0] + sh[c][1] + sh[c][2] + sh[c][3];
+        const double k = fmax(fmax(shk[0], shk[1]), fmax(shk[2], shk[3]));
+        const double rv[3] = {rh.x, rh.y, rh.z};
+        const double dre = rv[0] * N[0] + rv[1] * N[2] + rv[2] * N[4];
+        const double dim = rv[0] * N[1] + rv[1] * N[3] + rv[2] * N[5];
+        for (int c = 0; c < 3; ++c) {
+            const double pr = N[2 * c] - rv[c] * dre, pi = N[2 * c + 1] - rv[c] * dim;
+            // -j k / (4 pi) (pr + j pi) = (k pi - j k pr) / (4 pi)
+            E[((int64_t)r * ndir + d) * 3 + c] = zd{k * pi / (4 * M_PI), -k * pr / (4 * M_PI)};
+        }
+    }
+}
+
+void stage_farfield(Ctx& c, int nrhs, const zd* x, long ld, int ndir, const double* rhat, zd* E) {
+    DBuf<double> d_r;
+    d_r.upload(rhat, 3 * (size_t)ndir, c.stream);
+    DBuf<zd> d_E;
+    d_E.alloc(3 * (size_t)ndir * nrhs);
+    k_farfield<<<dim3(ndir, nrhs), 256, 0, c.stream>>>(c.nd, c.d_node_patch.p, c.d_patches.p, c.d_objs.p,
+                                                       c.n_nodes, x, ld, ndir, d_r.p, d_E.p);
+    check_launch("k_farfield");
+    d_E.download(E, 3 * (size_t)ndir * nrhs, c.stream);
+    c.sync();
+}
+
+}  // namespace cbie
