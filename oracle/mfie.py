@@ -213,8 +213,14 @@ def near_pairs(nd: Nodes, delta=NEAR_DELTA):
 
 # ----------------------------------------------------------- assembly ---
 
-def dense_matrix(nd: Nodes, k, delta=NEAR_DELTA, rule=None, pairs=None):
-    """Dense complex128 MFIE matrix (2n x 2n) in the original unknown order."""
+def _singular_chunk(args):
+    nd, k, chunk, rule = args
+    return [singular_block(nd, k, t, p, u, v, rule) for (t, p, u, v, _s) in chunk]
+
+
+def dense_matrix(nd: Nodes, k, delta=NEAR_DELTA, rule=None, pairs=None, workers=1):
+    """Dense complex128 MFIE matrix (2n x 2n) in the original unknown order.
+    `workers` > 1 spreads the singular integrals over a process pool."""
     n = nd.size
     q2 = nd.q * nd.q
     A = np.empty((n, 2, n, 2), dtype=complex)
@@ -226,8 +232,16 @@ def dense_matrix(nd: Nodes, k, delta=NEAR_DELTA, rule=None, pairs=None):
             A[a0:a0 + step] = far_block(nd, k, ti, idx)
     if pairs is None:
         pairs = near_pairs(nd, delta)
-    for (t, p, u, v, _self) in pairs:
-        blk = singular_block(nd, k, t, p, u, v, rule)
+    if workers > 1:
+        from multiprocessing import Pool
+        size = max(1, len(pairs) // (8 * workers))
+        chunks = [pairs[i:i + size] for i in range(0, len(pairs), size)]
+        with Pool(workers) as pool:
+            results = pool.map(_singular_chunk, [(nd, k, ch, rule) for ch in chunks])
+        blocks = [b for r in results for b in r]
+    else:
+        blocks = (singular_block(nd, k, t, p, u, v, rule) for (t, p, u, v, _s) in pairs)
+    for (t, p, u, v, _self), blk in zip(pairs, blocks):
         A[t, :, p * q2:(p + 1) * q2, :] = blk
     A = A.reshape(2 * n, 2 * n)
     A[np.arange(2 * n), np.arange(2 * n)] += 0.5

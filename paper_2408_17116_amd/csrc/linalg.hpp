@@ -1,0 +1,46 @@
+// Dense complex kernels used by the H-LU (column-major, complex64 or
+// complex128).  Every routine enqueues work on `s` and returns at once.
+#pragma once
+#include "common.hpp"
+
+namespace cbie {
+
+// C = alpha op(A) op(B) + beta C, op in {'N', 'T'} (plain transpose)
+template <typename T>
+void gemm(hipStream_t s, char ta, char tb, int m, int n, int k, cplx<T> alpha, const cplx<T>* A, int lda,
+          const cplx<T>* B, int ldb, cplx<T> beta, cplx<T>* C, int ldc);
+
+// P A = L U in place for an n x n leaf (partial pivoting, LAPACK-style
+// ipiv: row j was swapped with row piv[j]).  info[0] > 0 when a pivot is
+// exactly zero (first such column + 1); the factorization still completes.
+template <typename T>
+void getrf(hipStream_t s, int n, cplx<T>* A, int lda, int* piv, int* info);
+
+// B (m x n) := L^{-1} P^T B with the unit-lower factor and pivots of getrf
+template <typename T>
+void trsm_llnu_piv(hipStream_t s, int m, int n, const cplx<T>* LU, int ld, const int* piv, cplx<T>* B, int ldb);
+// B (m x n) := U^{-1} B (upper, non-unit, left)
+template <typename T>
+void trsm_lunn(hipStream_t s, int m, int n, const cplx<T>* LU, int ld, cplx<T>* B, int ldb);
+// B (m x n) := B U^{-1} (upper n x n, non-unit, right)
+template <typename T>
+void trsm_runn(hipStream_t s, int m, int n, const cplx<T>* LU, int ld, cplx<T>* B, int ldb);
+
+// B (n x m) = A^T (A: m x n)
+template <typename T>
+void transpose(hipStream_t s, int m, int n, const cplx<T>* A, int lda, cplx<T>* B, int ldb);
+// B (m x n) = alpha A (A may be null: B = 0)
+template <typename T>
+void copy_scale(hipStream_t s, int m, int n, cplx<T> alpha, const cplx<T>* A, int lda, cplx<T>* B, int ldb);
+// element-wise precision conversion of a contiguous array
+template <typename Tin, typename Tout>
+void convert(hipStream_t s, int64_t n, const cplx<Tin>* a, cplx<Tout>* b);
+
+// ACA of the implicit product M = Ucat Vcat^T (m x n, inner K): writes
+// U (m x cap) and V (n x cap) with M ~ U V^T to relative Frobenius
+// tolerance tol; rank_out[0] gets the rank (device int).
+template <typename T>
+void aca_product(hipStream_t s, int m, int n, int K, const cplx<T>* Ucat, const cplx<T>* Vcat, double tol,
+                 int cap, cplx<T>* U, cplx<T>* V, unsigned char* used, int* rank_out);
+
+}  // namespace cbie
