@@ -1,0 +1,98 @@
+// Batched kernels executed level by level by the H-LU task scheduler.
+#pragma once
+#include "common.hpp"
+
+namespace cbie {
+
+// C = alpha op(A) op(B) + beta C; op N, T (transpose) or C (conjugate transpose)
+template <typename T> struct GemmDesc {
+    int m, n, k;
+    int ta, tb;              // 0 = N, 1 = T, 2 = C
+    cplx<T> alpha, beta;
+    const cplx<T>* A;
+    const cplx<T>* B;
+    cplx<T>* C;
+    int lda, ldb, ldc;
+    int pad;
+};
+struct GemmTile {
+    int desc, m0, n0, pad;
+};
+
+// B = alpha op(A) (A == nullptr: B = 0); op 'N' or 'T'
+template <typename T> struct CopyDesc {
+    int m, n;                // size of B
+    int trans;
+    int lda, ldb;
+    cplx<T> alpha;
+    const cplx<T>* A;
+    cplx<T>* B;
+};
+struct CopyTile {
+    int desc, e0;            // element chunk start
+};
+
+// LU with partial pivoting of a diagonal leaf followed by the explicit
+// inverses LP = L^{-1} P and UI = U^{-1} (n x n each, leading dimension n)
+template <typename T> struct LeafDesc {
+    int n, lda;
+    cplx<T>* A;
+    int* piv;
+    int* info;
+    cplx<T>* LP;
+    cplx<T>* UI;
+};
+
+// uniform random entries in (-1, 1) + i (-1, 1) from a counter-based hash
+template <typename T> struct RandDesc {
+    cplx<T>* p;
+    int m, n, ld;
+    uint32_t seed;
+};
+
+// Hermitian eigen-decomposition A = E diag(lam) E^H of a p x p matrix
+// (p <= 512) by parallel cyclic Jacobi; eigenvalues descending.  A is
+// overwritten.  mode 0: write E;  mode 1 (orthonormalisation of a Gram
+// matrix): scale column k of E by lam_k^{-1/2}, or 0 when lam_k <= thr lam_0;
+// mode 2 (truncation): rank_out = smallest r with sum_{k>=r} lam_k <=
+// tol^2 sum lam_k.
+template <typename T> struct EigDesc {
+    cplx<T>* A;
+    cplx<T>* Ework;
+    cplx<T>* E;
+    int p, mode;
+    double thr;
+    int* rank_out;
+};
+
+// Pivoted Cholesky of a p x p Hermitian positive semi-definite Gram matrix
+// G (p <= 512, overwritten): G[pi, pi] ~ R^H R with pivots by largest
+// remaining diagonal, stopped when it falls below thr times the largest
+// diagonal; k = number of pivots taken.  Writes S (p x p): S[pi(t), j] =
+// (R^{-1})[t, j] for t <= j < k, zero elsewhere, so that Q = Y S has k
+// orthonormal columns spanning the range of Y (then zero columns).
+template <typename T> struct PcholDesc {
+    cplx<T>* G;
+    cplx<T>* S;
+    int p;
+    double thr;
+    int* k_out;
+};
+template <typename T>
+void pchol_batched(hipStream_t s, const PcholDesc<T>* d_desc, int n);
+
+template <typename T>
+void rand_batched(hipStream_t s, const RandDesc<T>* d_desc, int n);
+template <typename T>
+void eig_batched(hipStream_t s, const EigDesc<T>* d_desc, int n);
+
+template <typename T>
+void gemm_batched(hipStream_t s, const GemmDesc<T>* d_desc, const GemmTile* d_tiles, int ntiles);
+template <typename T>
+void copy_batched(hipStream_t s, const CopyDesc<T>* d_desc, const CopyTile* d_tiles, int ntiles);
+template <typename T>
+void leaf_batched(hipStream_t s, const LeafDesc<T>* d_desc, int n);
+
+constexpr int kCopyChunk = 8192;
+
+}  // namespace cbie

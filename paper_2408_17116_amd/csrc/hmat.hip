@@ -5,14 +5,26 @@
 // children (t1, t2):
 //   HLU(A11);  A12 := L11^{-1} A12;  A21 := A21 U11^{-1};
 //   A22 := A22 - A21 A12 (formatted);  HLU(A22).
-// Leaves: LU with partial pivoting inside the diagonal leaf (P A = L U),
-// no pivoting across blocks.  Updates of low-rank blocks are accumulated as
-// low-rank terms and recompressed once, by ACA of the summed factors, when
-// the block is next read ("lazy" formatted addition).
+// Leaves: LU with partial pivoting inside the diagonal leaf (P A = L U), no
+// pivoting across blocks; the leaf triangles are applied through their
+// explicit inverses, so every leaf solve is a GEMM.
+//
+// Execution.  The recursion does not launch work; it records tasks (GEMM,
+// copy, leaf LU) with host-known sizes and the blocks they read and write.
+// Each task gets the earliest level after every conflicting task, and a
+// level runs as one batched launch per task kind.  Updates of a low-rank
+// block are appended as extra columns of its factors, U V^T + sum X Y^T =
+// [U X][V Y]^T; triangular solves and products act on all columns, so no
+// rank has to be known on the host until the accumulated width passes a
+// limit.  Then the recorded program runs and every grown block is
+// recompressed in one batched ACA of its stacked factors (formatted
+// addition with truncation at the ACA tolerance).
 #include <algorithm>
 #include <cmath>
-#include <functional>
+#include <cstring>
+#include <unordered_map>
 
+#include "batch.hpp"
 #include "ctx.hpp"
 #include "linalg.hpp"
 #include "ops.hpp"
@@ -23,16 +35,14 @@ namespace cbie {
 template <typename T> struct Arena {
     std::vector<DBuf<cplx<T>>> chunks;
     std::vector<size_t> used;
-    size_t chunk_elems = size_t(1) << 26;   // 1 GiB of complex128 per chunk
+    size_t chunk_elems = size_t(1) << 26;
     int cur = -1;
-    size_t total = 0;
+    size_t live = 0;
     cplx<T>* alloc(size_t n) {
         n = (n + 31) & ~size_t(31);
         if (n == 0) n = 32;
-        if (cur < 0 && !chunks.empty()) cur = 0;   // chunks kept by a release to the empty mark
-        while (cur >= 0 && cur + 1 < (int)chunks.size() && used[cur] + n > chunks[cur].n) {
-            ++cur;   // reuse a chunk kept by an earlier release
-        }
+        if (cur < 0 && !chunks.empty()) cur = 0;
+        while (cur >= 0 && cur + 1 < (int)chunks.size() && used[cur] + n > chunks[cur].n) ++cur;
         if (cur < 0 || used[cur] + n > chunks[cur].n) {
             DBuf<cplx<T>> b;
             b.alloc(std::max(n, chunk_elems));
@@ -42,20 +52,21 @@ template <typename T> struct Arena {
         }
         cplx<T>* p = chunks[cur].p + used[cur];
         used[cur] += n;
-        total += n;
+        live += n;
         return p;
     }
-    struct Mark {
-        int cur;
-        size_t used;
-    };
-    Mark mark() const { return Mark{cur, cur >= 0 ? used[cur] : 0}; }
-    // stream ordering makes reuse safe: later kernels run after earlier ones
-    void release(Mark m) {
-        for (int k = m.cur + 1; k <= cur; ++k) used[k] = 0;
-        cur = m.cur;
-        if (cur >= 0) used[cur] = m.used;
+    void reset() {
+        for (auto& u : used) u = 0;
+        cur = chunks.empty() ? -1 : 0;
+        live = 0;
     }
+};
+
+// owner of the memory a task touches, for dependency tracking
+struct Res {
+    int kind;          // 0 dense block, 1 low-rank block, 2 right-hand-side rows, 3 temporary
+    int id;
+    int64_t a, b;      // row interval (kind 2)
 };
 
 template <typename T> struct HF {
@@ -64,38 +75,453 @@ template <typename T> struct HF {
     const Tree& T_;
     double tol;
     DBuf<cplx<T>> dense;
-    std::vector<int64_t> piv_off;   // per dense block (diagonal leaves), -1 otherwise
+    std::vector<int64_t> piv_off, inv_off;   // per dense block (diagonal leaves), -1 otherwise
     DBuf<int> piv, info;
-    // A low-rank block U V^T.  The factors live in accumulation buffers of
-    // `cap` columns: columns [0, r) hold the current factors, columns
-    // [r, K) hold pending update terms (zero outside their row / column
-    // ranges), recompressed together when the block is next read.
+    DBuf<cplx<T>> inv;   // L^{-1} P and U^{-1} of each diagonal leaf
+
+    // low-rank block: factor columns [0, r) + pending term columns [r, K)
     struct LR {
         cplx<T>* U;
         cplx<T>* V;
         int m, n, r;
         int K = 0, cap = 0;
+        cplx<T>* D = nullptr;   // dense accumulator of dense x dense updates (m x n)
+        bool dirty = false;     // D holds pending updates
+        bool pending() const { return K > r || dirty; }
     };
+    static constexpr int64_t kDenseAccMax = int64_t(1) << 26;   // entries
     std::vector<LR> lr;
     Arena<T> arena, scratch;
-    DBuf<unsigned char> used;
-    DBuf<int> d_rank;
+    DBuf<AcaProdJob<T>> jobbuf;
     int64_t launches = 0;
     double flops = 0.0;
+    int kmax = 768;            // accumulated width that triggers recompression
+    bool debug = getenv("CBIE_DEBUG") != nullptr;
+    double t_start = now_s();
 
+    // ------------------------------------------------------ task program
+    std::vector<GemmDesc<T>> gd;
+    std::vector<int> glev;
+    std::vector<CopyDesc<T>> cd;
+    std::vector<int> clev;
+    std::vector<LeafDesc<T>> ld;
+    std::vector<int> llev;
+    struct St {
+        int w = -1, r = -1;
+    };
+    std::unordered_map<int64_t, St> st;
+    struct Iv {
+        int64_t a, b;
+        int w, r;
+    };
+    std::vector<Iv> rhs_st;
+    int next_temp = 0;
+    int max_level = -1;
+    void* pinned = nullptr;
+    size_t pinned_bytes = 0;
+
+    HF(Ctx& cc, double t) : c(cc), s(cc.stream), T_(cc.tree), tol(t) {}
+    ~HF() {
+        if (pinned) (void)hipHostFree(pinned);
+        if (imm_pinned) (void)hipHostFree(imm_pinned);
+    }
+
+    static int64_t key(const Res& r) { return ((int64_t)r.kind << 40) | (int64_t)(uint32_t)r.id; }
+
+    int level_of(const std::vector<Res>& rd, const std::vector<Res>& wr) {
+        int lv = 0;
+        for (const Res& r : rd) {
+            if (r.kind == 2) {
+                for (const Iv& v : rhs_st)
+                    if (v.a < r.b && r.a < v.b) lv = std::max(lv, v.w + 1);
+            } else {
+                auto it = st.find(key(r));
+                if (it != st.end()) lv = std::max(lv, it->second.w + 1);
+            }
+        }
+        for (const Res& r : wr) {
+            if (r.kind == 2) {
+                for (const Iv& v : rhs_st)
+                    if (v.a < r.b && r.a < v.b) lv = std::max(lv, std::max(v.w, v.r) + 1);
+            } else {
+                auto it = st.find(key(r));
+                if (it != st.end()) lv = std::max(lv, std::max(it->second.w, it->second.r) + 1);
+            }
+        }
+        for (const Res& r : rd) {
+            if (r.kind == 2) rhs_st.push_back(Iv{r.a, r.b, -1, lv});
+            else {
+                St& x = st[key(r)];
+                x.r = std::max(x.r, lv);
+            }
+        }
+        for (const Res& r : wr) {
+            if (r.kind == 2) rhs_st.push_back(Iv{r.a, r.b, lv, -1});
+            else st[key(r)].w = lv;
+        }
+        max_level = std::max(max_level, lv);
+        return lv;
+    }
+    Res temp() { return Res{3, next_temp++, 0, 0}; }
+
+    void rec_gemm(int ta, int tb, int m, int n, int k, cplx<T> al, const cplx<T>* A, int lda, const cplx<T>* B,
+                  int ldb, cplx<T> be, cplx<T>* C, int ldc, const std::vector<Res>& rd, const std::vector<Res>& wr) {
+        if (m <= 0 || n <= 0) return;
+        if (k <= 0) {
+            if (be.re == (T)1 && be.im == (T)0) return;
+            rec_copy(0, m, n, be, (be.re == (T)0 && be.im == (T)0) ? nullptr : C, ldc, C, ldc, rd, wr);
+            return;
+        }
+        GemmDesc<T> g{m, n, k, ta, tb, al, be, A, B, C, lda, ldb, ldc, 0};
+        std::vector<Res> rr = rd;
+        if (!(be.re == (T)0 && be.im == (T)0)) rr.insert(rr.end(), wr.begin(), wr.end());
+        glev.push_back(level_of(rr, wr));
+        gd.push_back(g);
+        flops += 8.0 * m * n * k;
+    }
+    void rec_copy(int trans, int m, int n, cplx<T> al, const cplx<T>* A, int lda, cplx<T>* B, int ldb,
+                  const std::vector<Res>& rd, const std::vector<Res>& wr) {
+        if (m <= 0 || n <= 0) return;
+        cd.push_back(CopyDesc<T>{m, n, trans, lda, ldb, al, A, B});
+        clev.push_back(level_of(rd, wr));
+    }
+    void rec_leaf(int leaf) {
+        const DenseBlockDev& db = c.dblk[leaf];
+        cplx<T>* LP = inv.p + inv_off[leaf];
+        ld.push_back(LeafDesc<T>{db.ld, db.ld, dense.p + db.offset, piv.p + piv_off[leaf], info.p + leaf, LP,
+                                 LP + (int64_t)db.ld * db.ld});
+        const Res r{0, leaf, 0, 0};
+        llev.push_back(level_of({r}, {r}));
+        flops += 16.0 / 3.0 * (double)db.ld * db.ld * db.ld;
+    }
+
+    // run everything recorded so far, level by level
+    void execute() {
+        if (max_level < 0) {
+            scratch.reset();
+            return;
+        }
+        const int L = max_level + 1;
+        std::vector<std::vector<int>> gl(L), cl(L), ll(L);
+        for (size_t i = 0; i < gd.size(); ++i) gl[glev[i]].push_back((int)i);
+        for (size_t i = 0; i < cd.size(); ++i) cl[clev[i]].push_back((int)i);
+        for (size_t i = 0; i < ld.size(); ++i) ll[llev[i]].push_back((int)i);
+        // one pinned staging buffer: per level [gemm descs][gemm tiles][copy descs][copy tiles][leaf descs]
+        struct Seg {
+            size_t g, gt, c, ct, l;
+            int ng, ngt, nc, nct, nl;
+        };
+        std::vector<Seg> seg(L);
+        std::vector<char> host;
+        auto put = [&](const void* src, size_t bytes) {
+            size_t off = (host.size() + 255) & ~size_t(255);
+            host.resize(off + bytes);
+            if (bytes) std::memcpy(host.data() + off, src, bytes);
+            return off;
+        };
+        for (int lv = 0; lv < L; ++lv) {
+            Seg& sg = seg[lv];
+            std::vector<GemmDesc<T>> g;
+            std::vector<GemmTile> gt;
+            for (int i : gl[lv]) {
+                const GemmDesc<T>& d = gd[i];
+                const int di = (int)g.size();
+                g.push_back(d);
+                for (int m0 = 0; m0 < d.m; m0 += 64)
+                    for (int n0 = 0; n0 < d.n; n0 += 64) gt.push_back(GemmTile{di, m0, n0, 0});
+            }
+            std::vector<CopyDesc<T>> cc;
+            std::vector<CopyTile> ct;
+            for (int i : cl[lv]) {
+                const CopyDesc<T>& d = cd[i];
+                const int di = (int)cc.size();
+                cc.push_back(d);
+                for (int64_t e0 = 0; e0 < (int64_t)d.m * d.n; e0 += kCopyChunk) ct.push_back(CopyTile{di, (int)e0});
+            }
+            std::vector<LeafDesc<T>> lf;
+            for (int i : ll[lv]) lf.push_back(ld[i]);
+            sg.g = put(g.data(), g.size() * sizeof(GemmDesc<T>));
+            sg.gt = put(gt.data(), gt.size() * sizeof(GemmTile));
+            sg.c = put(cc.data(), cc.size() * sizeof(CopyDesc<T>));
+            sg.ct = put(ct.data(), ct.size() * sizeof(CopyTile));
+            sg.l = put(lf.data(), lf.size() * sizeof(LeafDesc<T>));
+            sg.ng = (int)g.size(); sg.ngt = (int)gt.size();
+            sg.nc = (int)cc.size(); sg.nct = (int)ct.size();
+            sg.nl = (int)lf.size();
+        }
+        if (host.size() > pinned_bytes) {
+            if (pinned) CBIE_HIP(hipHostFree(pinned));
+            pinned_bytes = std::max(host.size(), pinned_bytes * 2);
+            CBIE_HIP(hipHostMalloc(&pinned, pinned_bytes));
+        }
+        // the previous use of the staging buffers must be complete
+        CBIE_HIP(hipStreamSynchronize(s));
+        std::memcpy(pinned, host.data(), host.size());
+        DBuf<char>& dev = descbuf;
+        if (dev.n < host.size()) dev.alloc(std::max(host.size(), (size_t)1 << 20));
+        CBIE_HIP(hipMemcpyAsync(dev.p, pinned, host.size(), hipMemcpyHostToDevice, s));
+        for (int lv = 0; lv < L; ++lv) {
+            const Seg& sg = seg[lv];
+            if (sg.nl) { leaf_batched<T>(s, (const LeafDesc<T>*)(dev.p + sg.l), sg.nl); ++launches; }
+            if (sg.ngt) {
+                gemm_batched<T>(s, (const GemmDesc<T>*)(dev.p + sg.g), (const GemmTile*)(dev.p + sg.gt), sg.ngt);
+                ++launches;
+            }
+            if (sg.nct) {
+                copy_batched<T>(s, (const CopyDesc<T>*)(dev.p + sg.c), (const CopyTile*)(dev.p + sg.ct), sg.nct);
+                ++launches;
+            }
+        }
+        levels_run += L;
+        gd.clear(); glev.clear(); cd.clear(); clev.clear(); ld.clear(); llev.clear();
+        st.clear();
+        rhs_st.clear();
+        max_level = -1;
+        next_temp = 0;
+        // temporaries of this program are dead once it has run (stream order)
+        scratch.reset();
+    }
+    DBuf<char> descbuf;
+    int64_t levels_run = 0;
+
+    // ------------------------------------------- immediate batched launches
+    // (outside the recorded program: used by the recompression)
+    std::vector<char> imm_host;
+    DBuf<char> imm_dev;
+    void* imm_pinned = nullptr;
+    size_t imm_pinned_bytes = 0;
+    size_t imm_off = 0;
+    template <typename D> const D* stage_upload(const std::vector<D>& v) {
+        const size_t bytes = v.size() * sizeof(D);
+        const size_t off = (imm_off + 255) & ~size_t(255);
+        CBIE_REQUIRE(off + bytes <= imm_dev.n, -7, "recompression descriptor buffer overflow");
+        std::memcpy((char*)imm_pinned + off, v.data(), bytes);
+        CBIE_HIP(hipMemcpyAsync(imm_dev.p + off, (char*)imm_pinned + off, bytes, hipMemcpyHostToDevice, s));
+        imm_off = off + bytes;
+        return (const D*)(imm_dev.p + off);
+    }
+    void imm_begin(size_t bytes) {
+        CBIE_HIP(hipStreamSynchronize(s));   // earlier uploads from the pinned buffer are done
+        if (bytes > imm_pinned_bytes) {
+            if (imm_pinned) CBIE_HIP(hipHostFree(imm_pinned));
+            imm_pinned_bytes = std::max(bytes, 2 * imm_pinned_bytes);
+            CBIE_HIP(hipHostMalloc(&imm_pinned, imm_pinned_bytes));
+            imm_dev.alloc(imm_pinned_bytes);
+        }
+        imm_off = 0;
+    }
+    void run_gemms(const std::vector<GemmDesc<T>>& g) {
+        if (g.empty()) return;
+        std::vector<GemmTile> tiles;
+        for (size_t i = 0; i < g.size(); ++i) {
+            flops += 8.0 * g[i].m * g[i].n * g[i].k;
+            for (int m0 = 0; m0 < g[i].m; m0 += 64)
+                for (int n0 = 0; n0 < g[i].n; n0 += 64) tiles.push_back(GemmTile{(int)i, m0, n0, 0});
+        }
+        const GemmDesc<T>* dg = stage_upload(g);
+        const GemmTile* dt = stage_upload(tiles);
+        gemm_batched<T>(s, dg, dt, (int)tiles.size());
+        ++launches;
+    }
+    void run_copies(const std::vector<CopyDesc<T>>& c2) {
+        if (c2.empty()) return;
+        std::vector<CopyTile> tiles;
+        for (size_t i = 0; i < c2.size(); ++i)
+            for (int64_t e0 = 0; e0 < (int64_t)c2[i].m * c2[i].n; e0 += kCopyChunk) tiles.push_back(CopyTile{(int)i, (int)e0});
+        const CopyDesc<T>* dc = stage_upload(c2);
+        const CopyTile* dt = stage_upload(tiles);
+        copy_batched<T>(s, dc, dt, (int)tiles.size());
+        ++launches;
+    }
+
+    // Recompression of M = D + U V^T (U: m x K, V: n x K, D optional) for
+    // a batch of blocks by a randomized range finder:
+    //   Y = M Omega (Omega: n x p random);  Gram G = Y^H Y, pivoted
+    //   Cholesky G[pi, pi] = R^H R (rank-revealing), Q = Y[:, pi] R^{-1};
+    //   B = Q^H M (p x n);  ACA of B to the tolerance, B ~ X Z^T;
+    //   U' = Q X, V' = Z.
+    // When the ACA rank comes within 8 of the sample's numerical rank the
+    // block is redone with twice the sample size.  Every product is a
+    // batched GEMM over the whole GPU.
+    void recompress(std::vector<int> todo) {
+        std::vector<int> pq(todo.size());
+        for (size_t q = 0; q < todo.size(); ++q) {
+            const LR& L = lr[todo[q]];
+            pq[q] = std::min({L.m, L.n, L.r + 32 + (L.dirty ? 32 : 0), 512});
+        }
+        // Gram eigenvalue ratio kept by the pivoted Cholesky: CholeskyQR2 is
+        // stable while cond(Y) < u^{-1/2}, i.e. ratio > ~u (FP64 1e-16, FP32 1e-7)
+        const double gram_thr = sizeof(T) == 8 ? 1e-16 : 1e-7;
+        while (!todo.empty()) {
+            const size_t nb = todo.size();
+            size_t bytes = 0;
+            for (size_t q = 0; q < nb; ++q)
+                bytes += 64 * 1024 + (size_t)((lr[todo[q]].m + lr[todo[q]].n) / 64 + 4) * ((pq[q] + 63) / 64 + 2) * 64;
+            imm_begin(std::max<size_t>(bytes * 4, (size_t)1 << 22));
+            struct Tmp {
+                cplx<T> *Om, *W, *Y, *G, *S, *Q1, *G2, *S2, *Q, *Z, *B, *Ub, *Vb, *Uo;
+                int cap;
+            };
+            std::vector<Tmp> tm(nb);
+            int* ints = reinterpret_cast<int*>(scratch.alloc(nb));     // ranks
+            int* ks = reinterpret_cast<int*>(scratch.alloc(nb));       // sample ranks
+            std::vector<RandDesc<T>> rd;
+            std::vector<GemmDesc<T>> g1, g2, g3, g4, g5, g6, h1, h2, h4, q1, q2;
+            std::vector<PcholDesc<T>> pc, pc2;
+            int* ks2 = reinterpret_cast<int*>(scratch.alloc(nb));
+            std::vector<AcaProdJob<T>> aj;
+            const cplx<T> o = one(), z = zero();
+            for (size_t q = 0; q < nb; ++q) {
+                const LR& L = lr[todo[q]];
+                const int m = L.m, n = L.n, K = L.K, pp = pq[q];
+                Tmp& t = tm[q];
+                t.cap = std::min(pp, n);
+                t.Om = scratch.alloc((size_t)n * pp);
+                t.W = scratch.alloc((size_t)std::max(K, 1) * pp);
+                t.Y = scratch.alloc((size_t)m * pp);
+                t.G = scratch.alloc((size_t)pp * pp);
+                t.S = scratch.alloc((size_t)pp * pp);
+                t.Q1 = scratch.alloc((size_t)m * pp);
+                t.G2 = scratch.alloc((size_t)pp * pp);
+                t.S2 = scratch.alloc((size_t)pp * pp);
+                t.Q = scratch.alloc((size_t)m * pp);
+                t.Z = scratch.alloc((size_t)pp * std::max(K, 1));
+                t.B = scratch.alloc((size_t)pp * n);
+                t.Ub = scratch.alloc((size_t)pp * t.cap);
+                t.Vb = scratch.alloc((size_t)n * t.cap);
+                t.Uo = scratch.alloc((size_t)m * t.cap);
+                rd.push_back(RandDesc<T>{t.Om, n, pp, n,
+                                         (uint32_t)(0x9e3779b9u * (uint32_t)(flushes + 1) + 7919u * (uint32_t)todo[q] + (uint32_t)pp)});
+                if (K > 0) {
+                    g1.push_back(GemmDesc<T>{K, pp, n, 1, 0, o, z, L.V, t.Om, t.W, n, n, K, 0});
+                    g2.push_back(GemmDesc<T>{m, pp, K, 0, 0, o, z, L.U, t.W, t.Y, m, K, m, 0});
+                }
+                if (L.dirty) g3.push_back(GemmDesc<T>{m, pp, n, 0, 0, o, K > 0 ? o : z, L.D, t.Om, t.Y, m, n, m, 0});
+                g4.push_back(GemmDesc<T>{pp, pp, m, 2, 0, o, z, t.Y, t.Y, t.G, m, m, pp, 0});
+                pc.push_back(PcholDesc<T>{t.G, t.S, pp, gram_thr, ks + q});
+                g5.push_back(GemmDesc<T>{m, pp, pp, 0, 0, o, z, t.Y, t.S, t.Q1, m, pp, m, 0});
+                // second CholeskyQR pass restores orthogonality
+                q1.push_back(GemmDesc<T>{pp, pp, m, 2, 0, o, z, t.Q1, t.Q1, t.G2, m, m, pp, 0});
+                pc2.push_back(PcholDesc<T>{t.G2, t.S2, pp, 1e-4, ks2 + q});
+                q2.push_back(GemmDesc<T>{m, pp, pp, 0, 0, o, z, t.Q1, t.S2, t.Q, m, pp, m, 0});
+                if (K > 0) g6.push_back(GemmDesc<T>{pp, K, m, 2, 0, o, z, t.Q, L.U, t.Z, m, m, pp, 0});
+                if (K > 0) h1.push_back(GemmDesc<T>{pp, n, K, 0, 1, o, z, t.Z, L.V, t.B, pp, n, pp, 0});
+                if (L.dirty) h2.push_back(GemmDesc<T>{pp, n, m, 2, 0, o, K > 0 ? o : z, t.Q, L.D, t.B, m, m, pp, 0});
+                AcaProdJob<T> J{};
+                J.m = pp; J.n = n; J.K = 0; J.cap = t.cap;
+                J.D = t.B; J.Uc = nullptr; J.Vc = nullptr;
+                J.U = t.Ub; J.V = t.Vb;
+                J.used = reinterpret_cast<unsigned char*>(scratch.alloc(((size_t)pp + sizeof(cplx<T>) - 1) / sizeof(cplx<T>)));
+                J.rank_out = ints + q;
+                aj.push_back(J);
+                h4.push_back(GemmDesc<T>{m, t.cap, pp, 0, 0, o, z, t.Q, t.Ub, t.Uo, m, pp, m, 0});
+            }
+            rand_batched<T>(s, stage_upload(rd), (int)rd.size());
+            ++launches;
+            run_gemms(g1);
+            run_gemms(g2);
+            run_gemms(g3);
+            run_gemms(g4);
+            pchol_batched<T>(s, stage_upload(pc), (int)pc.size());
+            ++launches;
+            run_gemms(g5);
+            run_gemms(q1);
+            pchol_batched<T>(s, stage_upload(pc2), (int)pc2.size());
+            ++launches;
+            run_gemms(q2);
+            run_gemms(g6);
+            run_gemms(h1);
+            run_gemms(h2);
+            aca_product_batched<T>(s, (int)aj.size(), stage_upload(aj), tol);
+            ++launches;
+            run_gemms(h4);
+            std::vector<int> r(nb), kq(nb);
+            CBIE_HIP(hipMemcpyAsync(r.data(), ints, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+            CBIE_HIP(hipMemcpyAsync(kq.data(), ks, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+            CBIE_HIP(hipStreamSynchronize(s));
+            std::vector<int> again, again_p;
+            std::vector<CopyDesc<T>> cp;
+            for (size_t q = 0; q < nb; ++q) {
+                LR& L = lr[todo[q]];
+                const int pp = pq[q], full = std::min(L.m, L.n);
+                if (kq[q] >= pp - 2 && r[q] > kq[q] - 8 && pp < full) {
+                    CBIE_REQUIRE(pp < 512, -7, "low-rank block rank above 500: increase the leaf size or the tolerance");
+                    again.push_back(todo[q]);
+                    again_p.push_back(std::min({2 * pp, full, 512}));
+                    continue;
+                }
+                const int rr = r[q];
+                if (rr > L.cap) {
+                    L.cap = rr;
+                    L.U = arena.alloc((size_t)L.m * L.cap);
+                    L.V = arena.alloc((size_t)L.n * L.cap);
+                }
+                cp.push_back(CopyDesc<T>{L.m, rr, 0, L.m, L.m, o, tm[q].Uo, L.U});
+                cp.push_back(CopyDesc<T>{L.n, rr, 0, L.n, L.n, o, tm[q].Vb, L.V});
+                if (L.dirty) cp.push_back(CopyDesc<T>{L.m, L.n, 0, L.m, L.m, z, nullptr, L.D});
+                L.r = L.K = rr;
+                L.dirty = false;
+            }
+            run_copies(cp);
+            CBIE_HIP(hipStreamSynchronize(s));
+            scratch.reset();
+            todo = again;
+            pq = again_p;
+            ++recompress_rounds;
+        }
+    }
+    int64_t recompress_rounds = 0;
+
+    // run the program, then recompress the given low-rank blocks that hold
+    // pending columns or a dirty dense accumulator
+    void flush_set(const std::vector<int>& leaves) {
+        execute();
+        std::vector<int> todo;
+        for (int b : leaves)
+            if (lr[b].pending()) todo.push_back(b);
+        if (todo.empty()) return;
+        for (int b : todo) flush_k += lr[b].K;
+        recompress(todo);
+        ++flushes;
+        if (debug && flushes % 25 == 0)
+            fprintf(stderr, "[cbie] flush %lld: %zu blocks, %.2f s\n", (long long)flushes, todo.size(), now_s() - t_start);
+    }
+    void flush_all() {
+        std::vector<int> all(lr.size());
+        for (size_t b = 0; b < lr.size(); ++b) all[b] = (int)b;
+        flush_set(all);
+    }
+    void collect_lr(int blk, std::vector<int>& out) const {
+        const Block& b = T_.blocks[blk];
+        if (b.type == BLK_LR) out.push_back(b.leaf_index);
+        else if (b.type == BLK_HIER)
+            for (int k = 0; k < 4; ++k) collect_lr(b.child[k], out);
+    }
+    int64_t flushes = 0;
+    double width_lr_a = 0, width_lr_b = 0, width_dd = 0, flush_k = 0;
+    // the dense accumulator of a block, allocated and cleared on first use
+    cplx<T>* dacc(int leaf) {
+        LR& L = lr[leaf];
+        if (!L.D) {
+            L.D = arena.alloc((size_t)L.m * L.n);
+            const Res rs{1, leaf, 0, 0};
+            rec_copy(0, L.m, L.n, zero(), nullptr, L.m, L.D, L.m, {}, {rs});
+        }
+        L.dirty = true;
+        return L.D;
+    }
+
+    // ------------------------------------------------------------- views
     struct View {
-        int blk = -1;        // block node, or -1 for a raw dense buffer
-        int r0 = 0, c0 = 0;  // offset inside a leaf block
+        int blk = -1;           // block node, or -1 for a raw buffer
+        int r0 = 0, c0 = 0;     // offset inside a leaf block
         int m = 0, n = 0;
         int rc = -1, cc = -1;   // row / column cluster (-1: not split)
         cplx<T>* p = nullptr;   // raw buffer (already offset)
         int ld = 0;
+        Res own{2, 0, 0, 0};    // owner of a raw buffer
     };
     enum Kind { RAW, DENSE, LRK, HIER };
-
-    HF(Ctx& cc, double t) : c(cc), s(cc.stream), T_(cc.tree), tol(t) {}
-
-    // ------------------------------------------------------------- helpers
     int kind(const View& v) const {
         if (v.blk < 0) return RAW;
         const int ty = T_.blocks[v.blk].type;
@@ -112,103 +538,70 @@ template <typename T> struct HF {
         v.n = nunk(b.s);
         return v;
     }
-    View raw(cplx<T>* p, int ld, int m, int n, int rc, int cc) const {
+    View raw(cplx<T>* p, int ldp, int m, int n, int rc, int cc, Res own) const {
         View v;
-        v.p = p; v.ld = ld; v.m = m; v.n = n; v.rc = rc; v.cc = cc;
+        v.p = p; v.ld = ldp; v.m = m; v.n = n; v.rc = rc; v.cc = cc; v.own = own;
         return v;
     }
     View sub(const View& v, int ri, int ci) const {
-        if (kind(v) == HIER) {
-            const Block& b = T_.blocks[v.blk];
-            return full(b.child[ri * 2 + ci]);
-        }
+        if (kind(v) == HIER) return full(T_.blocks[v.blk].child[ri * 2 + ci]);
         View w = v;
         if (ri >= 0) {
             const Cluster& cl = T_.clusters[v.rc];
-            const int ch = cl.child[ri];
             const int off = ri == 0 ? 0 : nunk(cl.child[0]);
-            w.rc = ch;
-            w.m = nunk(ch);
-            if (v.blk < 0) w.p += off; else w.r0 += off;
+            w.rc = cl.child[ri];
+            w.m = nunk(w.rc);
+            if (v.blk < 0) {
+                w.p += off;
+                if (w.own.kind == 2) { w.own.a = v.own.a + off; w.own.b = w.own.a + w.m; }
+            } else w.r0 += off;
         }
         if (ci >= 0) {
             const Cluster& cl = T_.clusters[v.cc];
-            const int ch = cl.child[ci];
             const int off = ci == 0 ? 0 : nunk(cl.child[0]);
-            w.cc = ch;
-            w.n = nunk(ch);
+            w.cc = cl.child[ci];
+            w.n = nunk(w.cc);
             if (v.blk < 0) w.p += (int64_t)off * v.ld; else w.c0 += off;
         }
         return w;
     }
-    // dense pointer / leading dimension of a RAW or DENSE view
-    cplx<T>* dptr(const View& v, int& ld) const {
-        if (v.blk < 0) { ld = v.ld; return v.p; }
+    Res res(const View& v) const {
+        if (v.blk < 0) return v.own;
+        const Block& b = T_.blocks[v.blk];
+        return Res{b.type == BLK_DENSE ? 0 : 1, b.leaf_index, 0, 0};
+    }
+    cplx<T>* dptr(const View& v, int& ldp) const {
+        if (v.blk < 0) { ldp = v.ld; return v.p; }
         const DenseBlockDev& d = c.dblk[T_.blocks[v.blk].leaf_index];
-        ld = d.ld;
+        ldp = d.ld;
         return dense.p + d.offset + (int64_t)v.c0 * d.ld + v.r0;
     }
     LR& lrb(const View& v) { return lr[T_.blocks[v.blk].leaf_index]; }
-
-    // counted launches
-    void g(char ta, char tb, int m, int n, int k, cplx<T> al, const cplx<T>* A, int lda, const cplx<T>* B, int ldb,
-           cplx<T> be, cplx<T>* C, int ldc) {
-        if (m <= 0 || n <= 0) return;
-        gemm<T>(s, ta, tb, m, n, k, al, A, lda, B, ldb, be, C, ldc);
-        ++launches;
-        flops += 8.0 * m * n * std::max(k, 0);
-    }
     static cplx<T> one() { return cplx<T>{(T)1, (T)0}; }
     static cplx<T> zero() { return cplx<T>{(T)0, (T)0}; }
     static cplx<T> neg() { return cplx<T>{(T)-1, (T)0}; }
 
-    // ------------------------------------------------- lazy low-rank sums
-    void flush_block(int leaf) {
-        LR& L = lr[leaf];
-        if (L.K == L.r) return;
-        const int m = L.m, n = L.n, K = L.K;
-        auto mk = scratch.mark();
-        const int cap = std::min({m, n, K, 1024});
-        cplx<T>* U = scratch.alloc((size_t)m * cap);
-        cplx<T>* V = scratch.alloc((size_t)n * cap);
-        aca_product<T>(s, m, n, K, L.U, L.V, tol, cap, U, V, used.p, d_rank.p);
-        ++launches;
-        int r = 0;
-        CBIE_HIP(hipMemcpyAsync(&r, d_rank.p, sizeof(int), hipMemcpyDeviceToHost, s));
-        CBIE_HIP(hipStreamSynchronize(s));
-        flops += 8.0 * (double)(m + n) * K * r;   // entries of r rows and columns
-        copy_scale<T>(s, m, r, one(), U, m, L.U, m);
-        copy_scale<T>(s, n, r, one(), V, n, L.V, n);
-        launches += 2;
-        scratch.release(mk);
-        L.r = L.K = r;
-    }
-    void flush(const View& v) {
-        if (v.blk >= 0 && kind(v) == LRK) flush_block(T_.blocks[v.blk].leaf_index);
-    }
-    // room for k more term columns of block C; returns the first new column
-    // (zeroed).  X goes to U + col m + r0, Y to V + col n + c0.
+    // room for k more columns of low-rank block C (zeroed); returns the
+    // first new column
     int reserve(const View& C, int k) {
         const int leaf = T_.blocks[C.blk].leaf_index;
         LR& L = lr[leaf];
-        if (L.K + k > 1024) flush_block(leaf);
+        const Res rs{1, leaf, 0, 0};
         if (L.K + k > L.cap) {
             const int nc = std::max(L.K + k, 2 * L.cap);
             cplx<T>* U = arena.alloc((size_t)L.m * nc);
             cplx<T>* V = arena.alloc((size_t)L.n * nc);
             if (L.K > 0) {
-                copy_scale<T>(s, L.m, L.K, one(), L.U, L.m, U, L.m);
-                copy_scale<T>(s, L.n, L.K, one(), L.V, L.n, V, L.n);
-                launches += 2;
+                rec_copy(0, L.m, L.K, one(), L.U, L.m, U, L.m, {rs}, {rs});
+                rec_copy(0, L.n, L.K, one(), L.V, L.n, V, L.n, {rs}, {rs});
             }
             L.U = U;
             L.V = V;
             L.cap = nc;
         }
         const int col = L.K;
-        copy_scale<T>(s, L.m, k, zero(), nullptr, L.m, L.U + (int64_t)col * L.m, L.m);
-        copy_scale<T>(s, L.n, k, zero(), nullptr, L.n, L.V + (int64_t)col * L.n, L.n);
-        launches += 2;
+        rec_copy(0, L.m, k, zero(), nullptr, L.m, L.U + (int64_t)col * L.m, L.m, {}, {rs});
+        rec_copy(0, L.n, k, zero(), nullptr, L.n, L.V + (int64_t)col * L.n, L.n, {}, {rs});
         L.K += k;
         return col;
     }
@@ -224,11 +617,40 @@ template <typename T> struct HF {
                         update(sub(C, i, j), sub(A, i, k), sub(B, k, j), al);
             return;
         }
-        flush(A);
-        flush(B);
+        // A low-rank operand holding a dense accumulator is the sum of its
+        // factor part and its dense part: every part pair is applied once.
+        // Room in a low-rank C is made before anything is recorded, so no
+        // recompression can fold an operand's parts mid-way.
+        if (kind(C) == LRK) {
+            int need = 0;
+            const bool da = kind(A) == LRK && lrb(A).dirty, db = kind(B) == LRK && lrb(B).dirty;
+            const int wa = kind(A) == LRK ? lrb(A).K : -1, wb = kind(B) == LRK ? lrb(B).K : -1;
+            const bool small = (int64_t)lrb(C).m * lrb(C).n <= kDenseAccMax;
+            auto pair_w = [&](int a_lr, int b_lr) {   // width appended for one part pair
+                if (a_lr >= 0) return a_lr;
+                if (b_lr >= 0) return b_lr;
+                return small ? 0 : A.n;
+            };
+            for (int pa = 0; pa < (da ? 2 : 1); ++pa)
+                for (int pb = 0; pb < (db ? 2 : 1); ++pb)
+                    need += pair_w(pa == 0 ? wa : -1, pb == 0 ? wb : -1);
+            if (lrb(C).K + need > kmax) flush_all();
+        }
+        const bool dirtyA = kind(A) == LRK && lrb(A).dirty, dirtyB = kind(B) == LRK && lrb(B).dirty;
+        for (int pa = 0; pa < (dirtyA ? 2 : 1); ++pa)
+            for (int pb = 0; pb < (dirtyB ? 2 : 1); ++pb)
+                update_parts(C, pa == 1 ? dense_part(A) : A, pb == 1 ? dense_part(B) : B, al);
+    }
+    View dense_part(const View& X) {
+        LR& L = lrb(X);
+        return raw(L.D + (int64_t)X.c0 * L.m + X.r0, L.m, X.m, X.n, X.rc, X.cc, res(X));
+    }
+    // C += alpha A B for leaf-level views; low-rank operands contribute their
+    // factor columns only (their dense parts are passed separately)
+    void update_parts(const View& C, const View& A, const View& B, cplx<T> al) {
         const int kA = kind(A), kB = kind(B), kC = kind(C);
         const bool dA = kA != LRK, dB = kB != LRK;
-        auto mk = scratch.mark();
+        const Res rA = res(A), rB = res(B), rC = res(C);
         if (kC != LRK) {
             int ldc;
             cplx<T>* Cp = dptr(C, ldc);
@@ -236,163 +658,215 @@ template <typename T> struct HF {
                 int lda, ldb;
                 cplx<T>* Ap = dptr(A, lda);
                 cplx<T>* Bp = dptr(B, ldb);
-                g('N', 'N', C.m, C.n, A.n, al, Ap, lda, Bp, ldb, one(), Cp, ldc);
+                rec_gemm(0, 0, C.m, C.n, A.n, al, Ap, lda, Bp, ldb, one(), Cp, ldc, {rA, rB}, {rC});
             } else if (!dA) {
                 LR& La = lrb(A);
-                const int ra = La.r;
-                if (ra > 0) {
-                    const cplx<T>* Ua = La.U + A.r0;
-                    const cplx<T>* Va = La.V + A.c0;
-                    cplx<T>* Tm = scratch.alloc((size_t)ra * C.n);
-                    if (dB) {
-                        int ldb;
-                        cplx<T>* Bp = dptr(B, ldb);
-                        g('T', 'N', ra, C.n, B.m, one(), Va, La.n, Bp, ldb, zero(), Tm, ra);
-                    } else {
-                        LR& Lb = lrb(B);
-                        const int rb = Lb.r;
-                        cplx<T>* W = scratch.alloc((size_t)ra * std::max(rb, 1));
-                        if (rb > 0) {
-                            g('T', 'N', ra, rb, B.m, one(), Va, La.n, Lb.U + B.r0, Lb.m, zero(), W, ra);
-                            g('N', 'T', ra, C.n, rb, one(), W, ra, Lb.V + B.c0, Lb.n, zero(), Tm, ra);
-                        } else {
-                            copy_scale<T>(s, ra, C.n, zero(), nullptr, ra, Tm, ra);
-                            ++launches;
-                        }
-                    }
-                    g('N', 'N', C.m, C.n, ra, al, Ua, La.m, Tm, ra, one(), Cp, ldc);
+                const int ka = La.K;
+                if (ka == 0) return;
+                const Res t = temp();
+                cplx<T>* Tm = scratch.alloc((size_t)ka * C.n);
+                if (dB) {
+                    int ldb;
+                    cplx<T>* Bp = dptr(B, ldb);
+                    rec_gemm(1, 0, ka, C.n, B.m, one(), La.V + A.c0, La.n, Bp, ldb, zero(), Tm, ka, {rA, rB}, {t});
+                } else {
+                    LR& Lb = lrb(B);
+                    const int kb = Lb.K;
+                    if (kb == 0) return;
+                    const Res t2 = temp();
+                    cplx<T>* W = scratch.alloc((size_t)ka * kb);
+                    rec_gemm(1, 0, ka, kb, B.m, one(), La.V + A.c0, La.n, Lb.U + B.r0, Lb.m, zero(), W, ka, {rA, rB},
+                             {t2});
+                    rec_gemm(0, 1, ka, C.n, kb, one(), W, ka, Lb.V + B.c0, Lb.n, zero(), Tm, ka, {t2, rB}, {t});
                 }
+                rec_gemm(0, 0, C.m, C.n, ka, al, La.U + A.r0, La.m, Tm, ka, one(), Cp, ldc, {rA, t}, {rC});
             } else {
                 LR& Lb = lrb(B);
-                const int rb = Lb.r;
-                if (rb > 0) {
-                    int lda;
-                    cplx<T>* Ap = dptr(A, lda);
-                    cplx<T>* Tm = scratch.alloc((size_t)C.m * rb);
-                    g('N', 'N', C.m, rb, A.n, one(), Ap, lda, Lb.U + B.r0, Lb.m, zero(), Tm, C.m);
-                    g('N', 'T', C.m, C.n, rb, al, Tm, C.m, Lb.V + B.c0, Lb.n, one(), Cp, ldc);
-                }
+                const int kb = Lb.K;
+                if (kb == 0) return;
+                int lda;
+                cplx<T>* Ap = dptr(A, lda);
+                const Res t = temp();
+                cplx<T>* Tm = scratch.alloc((size_t)C.m * kb);
+                rec_gemm(0, 0, C.m, kb, A.n, one(), Ap, lda, Lb.U + B.r0, Lb.m, zero(), Tm, C.m, {rA, rB}, {t});
+                rec_gemm(0, 1, C.m, C.n, kb, al, Tm, C.m, Lb.V + B.c0, Lb.n, one(), Cp, ldc, {t, rB}, {rC});
             }
-            scratch.release(mk);
             return;
         }
-        // C low rank: append the product as X Y^T, recompressed when C is read
-        scratch.release(mk);
-        LR& Lc = lrb(C);
+        // C low rank: append the product as new columns [X | Y]
         if (!dA) {
+            const int ka = lrb(A).K;
+            if (ka == 0) return;
+            if (!dB && lrb(B).K == 0) return;
+            width_lr_a += ka;
+            const int col = reserve(C, ka);
+            LR& Lc = lrb(C);
             LR& La = lrb(A);
-            const int ra = La.r;
-            if (ra == 0) return;
-            const cplx<T>* Va = La.V + A.c0;
-            if (!dB && lrb(B).r == 0) return;
-            const int col = reserve(C, ra);
             cplx<T>* X = Lc.U + (int64_t)col * Lc.m + C.r0;
             cplx<T>* Y = Lc.V + (int64_t)col * Lc.n + C.c0;
-            copy_scale<T>(s, C.m, ra, al, La.U + A.r0, La.m, X, Lc.m);
-            ++launches;
+            rec_copy(0, C.m, ka, al, La.U + A.r0, La.m, X, Lc.m, {rA}, {rC});
             if (dB) {
                 int ldb;
                 cplx<T>* Bp = dptr(B, ldb);
-                g('T', 'N', C.n, ra, B.m, one(), Bp, ldb, Va, La.n, zero(), Y, Lc.n);
+                rec_gemm(1, 0, C.n, ka, B.m, one(), Bp, ldb, La.V + A.c0, La.n, zero(), Y, Lc.n, {rA, rB}, {rC});
             } else {
                 LR& Lb = lrb(B);
-                const int rb = Lb.r;
-                auto mk2 = scratch.mark();
-                cplx<T>* W = scratch.alloc((size_t)rb * ra);
-                g('T', 'N', rb, ra, B.m, one(), Lb.U + B.r0, Lb.m, Va, La.n, zero(), W, rb);
-                g('N', 'N', C.n, ra, rb, one(), Lb.V + B.c0, Lb.n, W, rb, zero(), Y, Lc.n);
-                scratch.release(mk2);
+                const int kb = Lb.K;
+                const Res t = temp();
+                cplx<T>* W = scratch.alloc((size_t)kb * ka);
+                rec_gemm(1, 0, kb, ka, B.m, one(), Lb.U + B.r0, Lb.m, La.V + A.c0, La.n, zero(), W, kb, {rA, rB}, {t});
+                rec_gemm(0, 0, C.n, ka, kb, one(), Lb.V + B.c0, Lb.n, W, kb, zero(), Y, Lc.n, {t, rB}, {rC});
             }
         } else if (!dB) {
+            const int kb = lrb(B).K;
+            if (kb == 0) return;
+            width_lr_b += kb;
+            const int col = reserve(C, kb);
+            LR& Lc = lrb(C);
             LR& Lb = lrb(B);
-            const int rb = Lb.r;
-            if (rb == 0) return;
             int lda;
             cplx<T>* Ap = dptr(A, lda);
-            const int col = reserve(C, rb);
             cplx<T>* X = Lc.U + (int64_t)col * Lc.m + C.r0;
             cplx<T>* Y = Lc.V + (int64_t)col * Lc.n + C.c0;
-            g('N', 'N', C.m, rb, A.n, al, Ap, lda, Lb.U + B.r0, Lb.m, zero(), X, Lc.m);
-            copy_scale<T>(s, C.n, rb, one(), Lb.V + B.c0, Lb.n, Y, Lc.n);
-            ++launches;
-        } else {
+            rec_gemm(0, 0, C.m, kb, A.n, al, Ap, lda, Lb.U + B.r0, Lb.m, zero(), X, Lc.m, {rA, rB}, {rC});
+            rec_copy(0, C.n, kb, one(), Lb.V + B.c0, Lb.n, Y, Lc.n, {rB}, {rC});
+        } else if ((int64_t)lrb(C).m * lrb(C).n <= kDenseAccMax) {
             int lda, ldb;
             cplx<T>* Ap = dptr(A, lda);
             cplx<T>* Bp = dptr(B, ldb);
+            const int leaf = T_.blocks[C.blk].leaf_index;
+            cplx<T>* D = dacc(leaf);
+            const int m = lr[leaf].m;
+            rec_gemm(0, 0, C.m, C.n, A.n, al, Ap, lda, Bp, ldb, one(), D + (int64_t)C.c0 * m + C.r0, m, {rA, rB}, {rC});
+        } else {
             const int k = A.n;
+            width_dd += k;
             const int col = reserve(C, k);
+            LR& Lc = lrb(C);
+            int lda, ldb;
+            cplx<T>* Ap = dptr(A, lda);
+            cplx<T>* Bp = dptr(B, ldb);
             cplx<T>* X = Lc.U + (int64_t)col * Lc.m + C.r0;
             cplx<T>* Y = Lc.V + (int64_t)col * Lc.n + C.c0;
-            copy_scale<T>(s, C.m, k, al, Ap, lda, X, Lc.m);
-            transpose<T>(s, B.m, B.n, Bp, ldb, Y, Lc.n);
-            launches += 2;
+            rec_copy(0, C.m, k, al, Ap, lda, X, Lc.m, {rA}, {rC});
+            rec_copy(1, C.n, k, one(), Bp, ldb, Y, Lc.n, {rB}, {rC});
         }
     }
 
     // --------------------------------------------------- triangular solves
-    // X (|d| x ncol) := L_dd^{-1} X   (L includes the leaf pivots)
-    void solveL(int d, cplx<T>* X, int ldx, int ncol) {
+    // Leaf solves through the explicit inverses, out of place into a
+    // temporary and copied back:  'L': X := (L^{-1} P) X,  'U': X := U^{-1} X
+    // (X: n x k),  'R': X := X U^{-1} (X: k x n),  'T': X := U^{-T} X.
+    void apply_inverse(char which, int leaf, int n, cplx<T>* X, int ldx, int k, const Res& rx) {
+        if (k <= 0) return;
+        const cplx<T>* LP = inv.p + inv_off[leaf];
+        const cplx<T>* UI = LP + (int64_t)n * n;
+        const Res rl{0, leaf, 0, 0};
+        const Res t = temp();
+        cplx<T>* Tm = scratch.alloc((size_t)n * k);
+        if (which == 'R') {
+            rec_gemm(0, 0, k, n, n, one(), X, ldx, UI, n, zero(), Tm, k, {rx, rl}, {t});
+            rec_copy(0, k, n, one(), Tm, k, X, ldx, {t}, {rx});
+        } else {
+            const int ta = which == 'T' ? 1 : 0;
+            rec_gemm(ta, 0, n, k, n, one(), which == 'L' ? LP : UI, n, X, ldx, zero(), Tm, n, {rx, rl}, {t});
+            rec_copy(0, n, k, one(), Tm, n, X, ldx, {t}, {rx});
+        }
+    }
+    // X (|d| x ncol) := L_dd^{-1} X
+    void solveL(int d, const View& X) {
         const Block& D = T_.blocks[d];
+        int ldx;
+        cplx<T>* p = dptr(X, ldx);
         if (D.type == BLK_DENSE) {
-            const DenseBlockDev& db = c.dblk[D.leaf_index];
-            trsm_llnu_piv<T>(s, db.ld, ncol, dense.p + db.offset, db.ld, piv.p + piv_off[D.leaf_index], X, ldx);
-            ++launches;
-            flops += 4.0 * db.ld * db.ld * ncol;
+            apply_inverse('L', D.leaf_index, c.dblk[D.leaf_index].ld, p, ldx, X.n, res(X));
             return;
         }
-        const Cluster& ct = T_.clusters[D.t];
-        const int n1 = nunk(ct.child[0]), n2 = nunk(ct.child[1]);
-        solveL(D.child[0], X, ldx, ncol);
-        update(raw(X + n1, ldx, n2, ncol, ct.child[1], -1), full(D.child[2]), raw(X, ldx, n1, ncol, ct.child[0], -1),
-               neg());
-        solveL(D.child[3], X + n1, ldx, ncol);
+        const View X1 = sub(X, 0, -1), X2 = sub(X, 1, -1);
+        solveL(D.child[0], X1);
+        update(X2, full(D.child[2]), X1, neg());
+        solveL(D.child[3], X2);
     }
     // X (|d| x ncol) := U_dd^{-1} X
-    void solveU(int d, cplx<T>* X, int ldx, int ncol) {
+    void solveU(int d, const View& X) {
         const Block& D = T_.blocks[d];
+        int ldx;
+        cplx<T>* p = dptr(X, ldx);
         if (D.type == BLK_DENSE) {
-            const DenseBlockDev& db = c.dblk[D.leaf_index];
-            trsm_lunn<T>(s, db.ld, ncol, dense.p + db.offset, db.ld, X, ldx);
-            ++launches;
-            flops += 4.0 * db.ld * db.ld * ncol;
+            apply_inverse('U', D.leaf_index, c.dblk[D.leaf_index].ld, p, ldx, X.n, res(X));
             return;
         }
-        const Cluster& ct = T_.clusters[D.t];
-        const int n1 = nunk(ct.child[0]), n2 = nunk(ct.child[1]);
-        solveU(D.child[3], X + n1, ldx, ncol);
-        update(raw(X, ldx, n1, ncol, ct.child[0], -1), full(D.child[1]), raw(X + n1, ldx, n2, ncol, ct.child[1], -1),
-               neg());
-        solveU(D.child[0], X, ldx, ncol);
+        const View X1 = sub(X, 0, -1), X2 = sub(X, 1, -1);
+        solveU(D.child[3], X2);
+        update(X1, full(D.child[1]), X2, neg());
+        solveU(D.child[0], X1);
     }
     // X (nrow x |d|) := X U_dd^{-1}
-    void solveUr(int d, cplx<T>* X, int ldx, int nrow) {
+    void solveUr(int d, const View& X) {
         const Block& D = T_.blocks[d];
+        int ldx;
+        cplx<T>* p = dptr(X, ldx);
         if (D.type == BLK_DENSE) {
-            const DenseBlockDev& db = c.dblk[D.leaf_index];
-            trsm_runn<T>(s, nrow, db.ld, dense.p + db.offset, db.ld, X, ldx);
-            ++launches;
-            flops += 4.0 * db.ld * db.ld * nrow;
+            apply_inverse('R', D.leaf_index, c.dblk[D.leaf_index].ld, p, ldx, X.m, res(X));
             return;
         }
-        const Cluster& ct = T_.clusters[D.t];
-        const int n1 = nunk(ct.child[0]), n2 = nunk(ct.child[1]);
-        solveUr(D.child[0], X, ldx, nrow);
-        update(raw(X + (int64_t)n1 * ldx, ldx, nrow, n2, -1, ct.child[1]), raw(X, ldx, nrow, n1, -1, ct.child[0]),
-               full(D.child[1]), neg());
-        solveUr(D.child[3], X + (int64_t)n1 * ldx, ldx, nrow);
+        const View X1 = sub(X, -1, 0), X2 = sub(X, -1, 1);
+        solveUr(D.child[0], X1);
+        update(X2, X1, full(D.child[1]), neg());
+        solveUr(D.child[3], X2);
+    }
+    // X (|d| x ncol) := U_dd^{-T} X (the V factor of a low-rank block)
+    void solveUT(int d, const View& X) {
+        const Block& D = T_.blocks[d];
+        int ldx;
+        cplx<T>* p = dptr(X, ldx);
+        if (D.type == BLK_DENSE) {
+            apply_inverse('T', D.leaf_index, c.dblk[D.leaf_index].ld, p, ldx, X.n, res(X));
+            return;
+        }
+        // U^T = [[U11^T, 0], [U12^T, U22^T]]: X1 := U11^{-T} X1; X2 -= U12^T X1; X2 := U22^{-T} X2
+        const View X1 = sub(X, 0, -1), X2 = sub(X, 1, -1);
+        solveUT(D.child[0], X1);
+        updateT(X2, full(D.child[1]), X1, neg());
+        solveUT(D.child[3], X2);
+    }
+    // C += alpha B^T X for a block B (rows of X = rows of B): used with V factors
+    void updateT(const View& C, const View& B, const View& X, cplx<T> al) {
+        if (kind(B) == HIER) {
+            // (B^T)_{ij} = (B_{ji})^T
+            for (int i = 0; i < 2; ++i)
+                for (int k = 0; k < 2; ++k) updateT(sub(C, i, -1), sub(B, k, i), sub(X, k, -1), al);
+            return;
+        }
+        const Res rB = res(B), rX = res(X), rC = res(C);
+        int ldx, ldc;
+        cplx<T>* Xp = dptr(X, ldx);
+        cplx<T>* Cp = dptr(C, ldc);
+        if (kind(B) == DENSE) {
+            int ldb;
+            cplx<T>* Bp = dptr(B, ldb);
+            rec_gemm(1, 0, C.m, C.n, B.m, al, Bp, ldb, Xp, ldx, one(), Cp, ldc, {rB, rX}, {rC});
+        } else {
+            // (U V^T)^T X = V (U^T X)
+            LR& Lb = lrb(B);
+            const int kb = Lb.K;
+            if (kb == 0) return;
+            const Res t = temp();
+            cplx<T>* Tm = scratch.alloc((size_t)kb * C.n);
+            rec_gemm(1, 0, kb, C.n, B.m, one(), Lb.U + B.r0, Lb.m, Xp, ldx, zero(), Tm, kb, {rB, rX}, {t});
+            rec_gemm(0, 0, C.m, C.n, kb, al, Lb.V + B.c0, Lb.n, Tm, kb, one(), Cp, ldc, {rB, t}, {rC});
+        }
     }
 
     // block X (row cluster of d) := L_dd^{-1} X
     void trsmL(int d, const View& X) {
         const int k = kind(X);
         if (k == DENSE) {
-            int ld;
-            cplx<T>* p = dptr(X, ld);
-            solveL(d, p, ld, X.n);
+            solveL(d, X);
         } else if (k == LRK) {
-            flush(X);
             LR& L = lrb(X);
-            if (L.r > 0) solveL(d, L.U, L.m, L.r);
+            if (L.K > 0) solveL(d, raw(L.U, L.m, L.m, L.K, T_.blocks[X.blk].t, -1, res(X)));
+            if (L.dirty) solveL(d, raw(L.D, L.m, L.m, L.n, T_.blocks[X.blk].t, -1, res(X)));
         } else {
             const Block& D = T_.blocks[d];
             for (int j = 0; j < 2; ++j) {
@@ -407,22 +881,12 @@ template <typename T> struct HF {
     void trsmU(int d, const View& X) {
         const int k = kind(X);
         if (k == DENSE) {
-            int ld;
-            cplx<T>* p = dptr(X, ld);
-            solveUr(d, p, ld, X.m);
+            solveUr(d, X);
         } else if (k == LRK) {
-            flush(X);
+            // U (V^T U^{-1}) with V^T U^{-1} = (U^{-T} V)^T
             LR& L = lrb(X);
-            if (L.r > 0) {
-                // U (V^T U_dd^{-1}): solve on W = V^T, then V = W^T
-                auto mk = scratch.mark();
-                cplx<T>* W = scratch.alloc((size_t)L.r * L.n);
-                transpose<T>(s, L.n, L.r, L.V, L.n, W, L.r);
-                solveUr(d, W, L.r, L.r);
-                transpose<T>(s, L.r, L.n, W, L.r, L.V, L.n);
-                launches += 2;
-                scratch.release(mk);
-            }
+            if (L.K > 0) solveUT(d, raw(L.V, L.n, L.n, L.K, T_.blocks[X.blk].s, -1, res(X)));
+            if (L.dirty) solveUr(d, raw(L.D, L.m, L.m, L.n, -1, T_.blocks[X.blk].s, res(X)));
         } else {
             const Block& D = T_.blocks[d];
             for (int i = 0; i < 2; ++i) {
@@ -437,16 +901,19 @@ template <typename T> struct HF {
     void hlu(int d) {
         const Block& D = T_.blocks[d];
         if (D.type == BLK_DENSE) {
-            const DenseBlockDev& db = c.dblk[D.leaf_index];
-            getrf<T>(s, db.ld, dense.p + db.offset, db.ld, piv.p + piv_off[D.leaf_index], info.p + D.leaf_index);
-            ++launches;
-            flops += 8.0 / 3.0 * (double)db.ld * db.ld * db.ld;
+            rec_leaf(D.leaf_index);
             return;
         }
         CBIE_REQUIRE(D.type == BLK_HIER, -7, "low-rank diagonal block");
         hlu(D.child[0]);
         trsmL(D.child[0], full(D.child[1]));
         trsmU(D.child[0], full(D.child[2]));
+        // the factors L21 and U12 are final: recompress them before they
+        // multiply into the Schur complement
+        std::vector<int> ops;
+        collect_lr(D.child[1], ops);
+        collect_lr(D.child[2], ops);
+        flush_set(ops);
         update(full(D.child[3]), full(D.child[2]), full(D.child[1]), neg());
         hlu(D.child[3]);
     }
@@ -465,7 +932,6 @@ template <typename T> static std::shared_ptr<HF<T>> make_factor(Ctx& c) {
     auto f = std::make_shared<HF<T>>(c, c.aca_tol);
     hipStream_t s = c.stream;
     const Tree& T_ = c.tree;
-    // copy of the operator in the working precision
     f->dense.alloc(std::max<int64_t>(c.stats.dense_entries, 1));
     convert<double, T>(s, c.stats.dense_entries, c.dense.p, f->dense.p);
     f->lr.resize(c.lblk.size());
@@ -480,29 +946,28 @@ template <typename T> static std::shared_ptr<HF<T>> make_factor(Ctx& c) {
         convert<double, T>(s, (int64_t)L.m * L.r, c.lr.mem.p + c.lr.u_off[b], L.U);
         convert<double, T>(s, (int64_t)L.n * L.r, c.lr.mem.p + c.lr.v_off[b], L.V);
     }
-    // pivots of the diagonal leaves
     f->piv_off.assign(c.dblk.size(), -1);
-    int64_t np = 0;
+    f->inv_off.assign(c.dblk.size(), -1);
+    int64_t np = 0, ni = 0;
     for (size_t b = 0; b < T_.dense_blocks.size(); ++b) {
         const Block& B = T_.blocks[T_.dense_blocks[b]];
         if (B.t == B.s) {
             f->piv_off[b] = np;
             np += c.dblk[b].ld;
+            f->inv_off[b] = ni;
+            ni += 2 * (int64_t)c.dblk[b].ld * c.dblk[b].ld;
         }
     }
     f->piv.alloc(std::max<int64_t>(np, 1));
+    f->inv.alloc(std::max<int64_t>(ni, 1));
     f->info.alloc(std::max<size_t>(c.dblk.size(), 1));
     CBIE_HIP(hipMemsetAsync(f->info.p, 0, sizeof(int) * std::max<size_t>(c.dblk.size(), 1), s));
-    int maxm = 1;
-    for (auto& d : c.lblk) maxm = std::max(maxm, 2 * d.row_nodes);
-    f->used.alloc(maxm);
-    f->d_rank.alloc(1);
     return f;
 }
 
 template <typename T> static void run_factor(Ctx& c, HF<T>& f) {
     for (int root : c.tree.block_roots) f.hlu(root);
-    for (size_t b = 0; b < f.lr.size(); ++b) f.flush_block((int)b);
+    f.flush_all();
     std::vector<int> info(c.dblk.size());
     if (!info.empty()) f.info.download(info.data(), info.size(), c.stream);
     c.sync();
@@ -510,6 +975,10 @@ template <typename T> static void run_factor(Ctx& c, HF<T>& f) {
         CBIE_REQUIRE(info[b] == 0, CBIE_ESINGULAR, "zero pivot in diagonal leaf " + std::to_string(b));
     c.stats.factor_flops = (int64_t)f.flops;
     c.stats.n_kernel_launches = f.launches;
+    if (getenv("CBIE_DEBUG"))
+        fprintf(stderr, "[cbie] levels %lld flushes %lld rounds %lld widths lrA %.0f lrB %.0f dd %.0f flushK %.0f\n",
+                (long long)f.levels_run, (long long)f.flushes, (long long)f.recompress_rounds, f.width_lr_a,
+                f.width_lr_b, f.width_dd, f.flush_k);
 }
 
 void stage_factor(Ctx& c, int prec) {
@@ -531,11 +1000,13 @@ void stage_factor(Ctx& c, int prec) {
 template <typename T> static void lu_solve_tree(Ctx& c, HF<T>& f, cplx<T>* X, int nrhs) {
     const int ld = (int)c.n_unk;
     for (int root : c.tree.block_roots) {
-        const Cluster& cl = c.tree.clusters[c.tree.blocks[root].t];
-        cplx<T>* Xo = X + cl.unk0();
-        f.solveL(root, Xo, ld, nrhs);
-        f.solveU(root, Xo, ld, nrhs);
+        const int cl = c.tree.blocks[root].t;
+        const Cluster& C = c.tree.clusters[cl];
+        const auto v = f.raw(X + C.unk0(), ld, (int)C.nunk(), nrhs, cl, -1, Res{2, 0, C.unk0(), C.unk0() + C.nunk()});
+        f.solveL(root, v);
+        f.solveU(root, v);
     }
+    f.execute();
 }
 
 // column norms |r_j|^2 and |b_j|^2

@@ -310,10 +310,16 @@ void convert(hipStream_t s, int64_t n, const cplx<Tin>* a, cplx<Tout>* b) {
 // partial-pivot ACA as for the kernel blocks, entries formed as dot
 // products.  One work-group of 256 threads.
 template <typename T>
-__global__ __launch_bounds__(256) void k_aca_prod(int m, int n, int K, const cplx<T>* __restrict__ Uc,
-                                                  const cplx<T>* __restrict__ Vc, double tol, int cap,
-                                                  cplx<T>* __restrict__ U, cplx<T>* __restrict__ V,
-                                                  unsigned char* __restrict__ used, int* __restrict__ rank_out) {
+__global__ __launch_bounds__(256) void k_aca_prod(const AcaProdJob<T>* __restrict__ jobs, int njobs, double tol) {
+    if ((int)blockIdx.x >= njobs) return;
+    const AcaProdJob<T> J = jobs[blockIdx.x];
+    const int m = J.m, n = J.n, K = J.K, cap = J.cap;
+    const cplx<T>* __restrict__ Uc = J.Uc;
+    const cplx<T>* __restrict__ Vc = J.Vc;
+    cplx<T>* __restrict__ U = J.U;
+    cplx<T>* __restrict__ V = J.V;
+    unsigned char* __restrict__ used = J.used;
+    const cplx<T>* __restrict__ Dd = J.D;
     __shared__ AM sh_am[4];
     __shared__ double sh_s[4];
     __shared__ cplx<T> s_row[2048];   // Ucat[i, :] or Vcat[j, :] (K <= 2048)
@@ -331,7 +337,7 @@ __global__ __launch_bounds__(256) void k_aca_prod(int m, int n, int K, const cpl
         cplx<T>* vk = V + (int64_t)rank * n;
         AM am{-1.0, 0x7fffffff};
         for (int j = tid; j < n; j += 256) {
-            cplx<T> r = czero<T>();
+            cplx<T> r = Dd ? Dd[irow + (int64_t)j * m] : czero<T>();
             for (int l = 0; l < K; ++l) cfma(r, s_row[l], Vc[j + (int64_t)l * n]);
             for (int l = 0; l < rank; ++l) cfma(r, -s_coef[l], V[j + (int64_t)l * n]);
             vk[j] = r;
@@ -358,7 +364,7 @@ __global__ __launch_bounds__(256) void k_aca_prod(int m, int n, int K, const cpl
         AM nx{-1.0, 0x7fffffff};
         double nu2 = 0.0;
         for (int i = tid; i < m; i += 256) {
-            cplx<T> cc = czero<T>();
+            cplx<T> cc = Dd ? Dd[i + (int64_t)jp * m] : czero<T>();
             for (int l = 0; l < K; ++l) cfma(cc, Uc[i + (int64_t)l * m], s_row[l]);
             for (int l = 0; l < rank; ++l) cfma(cc, -s_coef[l], U[i + (int64_t)l * m]);
             uk[i] = cc;
@@ -400,15 +406,79 @@ __global__ __launch_bounds__(256) void k_aca_prod(int m, int n, int K, const cpl
         irow = nx.i;
         __syncthreads();
     }
-    if (tid == 0) rank_out[0] = rank;
+    if (tid == 0) J.rank_out[0] = rank;
 }
 
 template <typename T>
-void aca_product(hipStream_t s, int m, int n, int K, const cplx<T>* Ucat, const cplx<T>* Vcat, double tol, int cap,
-                 cplx<T>* U, cplx<T>* V, unsigned char* used, int* rank_out) {
-    CBIE_REQUIRE(K <= 2048 && cap <= 1024, -7, "low-rank accumulation wider than 2048 columns");
-    k_aca_prod<T><<<1, 256, 0, s>>>(m, n, K, Ucat, Vcat, tol, cap, U, V, used, rank_out);
+void aca_product_batched(hipStream_t s, int njobs, const AcaProdJob<T>* d_jobs, double tol) {
+    if (njobs <= 0) return;
+    k_aca_prod<T><<<njobs, 256, 0, s>>>(d_jobs, njobs, tol);
     check_launch("k_aca_prod");
+}
+
+// copy the first rank columns of the recompressed factors back (batched)
+template <typename T>
+__global__ void k_aca_copyback(const AcaProdJob<T>* __restrict__ jobs, int njobs) {
+    const int jb = blockIdx.y;
+    if (jb >= njobs) return;
+    const AcaProdJob<T> J = jobs[jb];
+    const int r = J.rank_out[0];
+    const int64_t mu = (int64_t)J.m * r, nv = (int64_t)J.n * r;
+    for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < mu + nv; e += (int64_t)gridDim.x * blockDim.x) {
+        if (e < mu) J.dstU[e] = J.U[e];
+        else J.dstV[e - mu] = J.V[e - mu];
+    }
+}
+
+template <typename T>
+void aca_copyback_batched(hipStream_t s, int njobs, const AcaProdJob<T>* d_jobs) {
+    if (njobs <= 0) return;
+    k_aca_copyback<T><<<dim3(16, njobs), 256, 0, s>>>(d_jobs, njobs);
+    check_launch("k_aca_copyback");
+}
+
+// ------------------------------------------------- leaf triangle inverses
+// After P A = L U: LP = L^{-1} P (column c = L^{-1} P e_c) and UI = U^{-1},
+// thread per column, loops uniform over rows so that the reads of L and U
+// are wave-wide broadcasts.
+template <typename T>
+__global__ __launch_bounds__(256) void k_leaf_inverse(int n, const cplx<T>* __restrict__ LU, int ld,
+                                                      const int* __restrict__ piv, cplx<T>* __restrict__ LP,
+                                                      cplx<T>* __restrict__ UI) {
+    __shared__ int perm[1024];
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < n; ++i) perm[i] = i;
+        for (int j = 0; j < n; ++j) {            // P e_c: row positions after the swaps
+            const int p = piv[j];
+            const int t = perm[j]; perm[j] = perm[p]; perm[p] = t;
+        }
+    }
+    __syncthreads();
+    for (int c = threadIdx.x; c < n; c += blockDim.x) {
+        // P e_c = e_s with s the position holding row c after the swaps
+        int sidx = 0;
+        for (int i = 0; i < n; ++i)
+            if (perm[i] == c) sidx = i;
+        cplx<T>* x = LP + (int64_t)c * n;
+        for (int i = 0; i < n; ++i) {
+            cplx<T> v = cplx<T>{(T)(i == sidx ? 1 : 0), (T)0};
+            for (int t = 0; t < i; ++t) cfma(v, -LU[i + (int64_t)t * ld], x[t]);
+            x[i] = (i < sidx) ? cplx<T>{(T)0, (T)0} : v;
+        }
+        cplx<T>* y = UI + (int64_t)c * n;
+        for (int i = n - 1; i >= 0; --i) {
+            cplx<T> v = cplx<T>{(T)(i == c ? 1 : 0), (T)0};
+            for (int t = i + 1; t < n; ++t) cfma(v, -LU[i + (int64_t)t * ld], y[t]);
+            y[i] = (i > c) ? cplx<T>{(T)0, (T)0} : cdiv(v, LU[i + (int64_t)i * ld]);
+        }
+    }
+}
+
+template <typename T>
+void leaf_inverse(hipStream_t s, int n, const cplx<T>* LU, int ld, const int* piv, cplx<T>* LP, cplx<T>* UI) {
+    CBIE_REQUIRE(n <= 1024, -7, "diagonal leaf larger than 1024 unknowns");
+    k_leaf_inverse<T><<<1, 256, 0, s>>>(n, LU, ld, piv, LP, UI);
+    check_launch("k_leaf_inverse");
 }
 
 // ----------------------------------------------------------- instances
@@ -421,8 +491,9 @@ void aca_product(hipStream_t s, int m, int n, int K, const cplx<T>* Ucat, const 
     template void trsm_runn<T>(hipStream_t, int, int, const cplx<T>*, int, cplx<T>*, int);                      \
     template void transpose<T>(hipStream_t, int, int, const cplx<T>*, int, cplx<T>*, int);                      \
     template void copy_scale<T>(hipStream_t, int, int, cplx<T>, const cplx<T>*, int, cplx<T>*, int);            \
-    template void aca_product<T>(hipStream_t, int, int, int, const cplx<T>*, const cplx<T>*, double, int,       \
-                                 cplx<T>*, cplx<T>*, unsigned char*, int*);
+    template void aca_product_batched<T>(hipStream_t, int, const AcaProdJob<T>*, double);                      \
+    template void aca_copyback_batched<T>(hipStream_t, int, const AcaProdJob<T>*);                             \
+    template void leaf_inverse<T>(hipStream_t, int, const cplx<T>*, int, const int*, cplx<T>*, cplx<T>*);
 CBIE_LINALG_INST(double)
 CBIE_LINALG_INST(float)
 template void convert<double, float>(hipStream_t, int64_t, const zd*, zf*);

@@ -36,11 +36,30 @@ void copy_scale(hipStream_t s, int m, int n, cplx<T> alpha, const cplx<T>* A, in
 template <typename Tin, typename Tout>
 void convert(hipStream_t s, int64_t n, const cplx<Tin>* a, cplx<Tout>* b);
 
-// ACA of the implicit product M = Ucat Vcat^T (m x n, inner K): writes
-// U (m x cap) and V (n x cap) with M ~ U V^T to relative Frobenius
-// tolerance tol; rank_out[0] gets the rank (device int).
+// ACA of an implicit product M = Uc Vc^T (m x n, inner K <= 2048): writes
+// U (m x cap) and V (n x cap), cap <= 1024, with M ~ U V^T to relative
+// Frobenius tolerance tol; rank_out[0] gets the rank.  One work-group per
+// job.  The copy-back moves U[:, :rank], V[:, :rank] to dstU, dstV.
+template <typename T> struct AcaProdJob {
+    int m, n, K, cap;
+    const cplx<T>* D;        // optional dense addend (m x n, leading dim m): M = D + Uc Vc^T
+    const cplx<T>* Uc;
+    const cplx<T>* Vc;
+    cplx<T>* U;
+    cplx<T>* V;
+    cplx<T>* dstU;
+    cplx<T>* dstV;
+    unsigned char* used;
+    int* rank_out;
+};
 template <typename T>
-void aca_product(hipStream_t s, int m, int n, int K, const cplx<T>* Ucat, const cplx<T>* Vcat, double tol,
-                 int cap, cplx<T>* U, cplx<T>* V, unsigned char* used, int* rank_out);
+void aca_product_batched(hipStream_t s, int njobs, const AcaProdJob<T>* d_jobs, double tol);
+template <typename T>
+void aca_copyback_batched(hipStream_t s, int njobs, const AcaProdJob<T>* d_jobs);
+
+// Explicit inverses of the factors of a diagonal leaf after getrf:
+// LP = L^{-1} P and UI = U^{-1} (both n x n, leading dimension n).
+template <typename T>
+void leaf_inverse(hipStream_t s, int n, const cplx<T>* LU, int ld, const int* piv, cplx<T>* LP, cplx<T>* UI);
 
 }  // namespace cbie
