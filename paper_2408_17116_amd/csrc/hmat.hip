@@ -91,7 +91,8 @@ template <typename T> struct HF {
     };
     static constexpr int64_t kDenseAccMax = int64_t(1) << 26;   // entries
     std::vector<LR> lr;
-    Arena<T> arena, scratch;
+    Arena<T> arena, scratch, rscratch;
+    int pin = 0;               // > 0: recorded temporaries are still referenced
     DBuf<AcaProdJob<T>> jobbuf;
     int64_t launches = 0;
     double flops = 0.0;
@@ -198,7 +199,7 @@ template <typename T> struct HF {
     // run everything recorded so far, level by level
     void execute() {
         if (max_level < 0) {
-            scratch.reset();
+            if (pin == 0) scratch.reset();
             return;
         }
         const int L = max_level + 1;
@@ -277,9 +278,12 @@ template <typename T> struct HF {
         st.clear();
         rhs_st.clear();
         max_level = -1;
-        next_temp = 0;
-        // temporaries of this program are dead once it has run (stream order)
-        scratch.reset();
+        // temporaries of this program are dead once it has run (stream
+        // order), unless an update in progress still refers to some of them
+        if (pin == 0) {
+            next_temp = 0;
+            scratch.reset();
+        }
     }
     DBuf<char> descbuf;
     int64_t levels_run = 0;
@@ -363,12 +367,12 @@ template <typename T> struct HF {
                 int cap;
             };
             std::vector<Tmp> tm(nb);
-            int* ints = reinterpret_cast<int*>(scratch.alloc(nb));     // ranks
-            int* ks = reinterpret_cast<int*>(scratch.alloc(nb));       // sample ranks
+            int* ints = reinterpret_cast<int*>(rscratch.alloc(nb));     // ranks
+            int* ks = reinterpret_cast<int*>(rscratch.alloc(nb));       // sample ranks
             std::vector<RandDesc<T>> rd;
             std::vector<GemmDesc<T>> g1, g2, g3, g4, g5, g6, h1, h2, h4, q1, q2;
             std::vector<PcholDesc<T>> pc, pc2;
-            int* ks2 = reinterpret_cast<int*>(scratch.alloc(nb));
+            int* ks2 = reinterpret_cast<int*>(rscratch.alloc(nb));
             std::vector<AcaProdJob<T>> aj;
             const cplx<T> o = one(), z = zero();
             for (size_t q = 0; q < nb; ++q) {
@@ -376,20 +380,20 @@ template <typename T> struct HF {
                 const int m = L.m, n = L.n, K = L.K, pp = pq[q];
                 Tmp& t = tm[q];
                 t.cap = std::min(pp, n);
-                t.Om = scratch.alloc((size_t)n * pp);
-                t.W = scratch.alloc((size_t)std::max(K, 1) * pp);
-                t.Y = scratch.alloc((size_t)m * pp);
-                t.G = scratch.alloc((size_t)pp * pp);
-                t.S = scratch.alloc((size_t)pp * pp);
-                t.Q1 = scratch.alloc((size_t)m * pp);
-                t.G2 = scratch.alloc((size_t)pp * pp);
-                t.S2 = scratch.alloc((size_t)pp * pp);
-                t.Q = scratch.alloc((size_t)m * pp);
-                t.Z = scratch.alloc((size_t)pp * std::max(K, 1));
-                t.B = scratch.alloc((size_t)pp * n);
-                t.Ub = scratch.alloc((size_t)pp * t.cap);
-                t.Vb = scratch.alloc((size_t)n * t.cap);
-                t.Uo = scratch.alloc((size_t)m * t.cap);
+                t.Om = rscratch.alloc((size_t)n * pp);
+                t.W = rscratch.alloc((size_t)std::max(K, 1) * pp);
+                t.Y = rscratch.alloc((size_t)m * pp);
+                t.G = rscratch.alloc((size_t)pp * pp);
+                t.S = rscratch.alloc((size_t)pp * pp);
+                t.Q1 = rscratch.alloc((size_t)m * pp);
+                t.G2 = rscratch.alloc((size_t)pp * pp);
+                t.S2 = rscratch.alloc((size_t)pp * pp);
+                t.Q = rscratch.alloc((size_t)m * pp);
+                t.Z = rscratch.alloc((size_t)pp * std::max(K, 1));
+                t.B = rscratch.alloc((size_t)pp * n);
+                t.Ub = rscratch.alloc((size_t)pp * t.cap);
+                t.Vb = rscratch.alloc((size_t)n * t.cap);
+                t.Uo = rscratch.alloc((size_t)m * t.cap);
                 rd.push_back(RandDesc<T>{t.Om, n, pp, n,
                                          (uint32_t)(0x9e3779b9u * (uint32_t)(flushes + 1) + 7919u * (uint32_t)todo[q] + (uint32_t)pp)});
                 if (K > 0) {
@@ -411,7 +415,7 @@ template <typename T> struct HF {
                 J.m = pp; J.n = n; J.K = 0; J.cap = t.cap;
                 J.D = t.B; J.Uc = nullptr; J.Vc = nullptr;
                 J.U = t.Ub; J.V = t.Vb;
-                J.used = reinterpret_cast<unsigned char*>(scratch.alloc(((size_t)pp + sizeof(cplx<T>) - 1) / sizeof(cplx<T>)));
+                J.used = reinterpret_cast<unsigned char*>(rscratch.alloc(((size_t)pp + sizeof(cplx<T>) - 1) / sizeof(cplx<T>)));
                 J.rank_out = ints + q;
                 aj.push_back(J);
                 h4.push_back(GemmDesc<T>{m, t.cap, pp, 0, 0, o, z, t.Q, t.Ub, t.Uo, m, pp, m, 0});
@@ -464,7 +468,7 @@ template <typename T> struct HF {
             }
             run_copies(cp);
             CBIE_HIP(hipStreamSynchronize(s));
-            scratch.reset();
+            rscratch.reset();
             todo = again;
             pq = again_p;
             ++recompress_rounds;
@@ -607,8 +611,77 @@ template <typename T> struct HF {
     }
 
     // ------------------------------------------------------ C += alpha A B
+    // C += X Y^T for dense X (|rows of C| x k) and Y (|cols of C| x k),
+    // distributed over the leaves of C
+    void add_lowrank(const View& C, const View& X, const View& Y, int k) {
+        if (k <= 0) return;
+        const int kc = kind(C);
+        if (kc == HIER) {
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j) add_lowrank(sub(C, i, j), sub(X, i, -1), sub(Y, j, -1), k);
+            return;
+        }
+        int ldx, ldy;
+        cplx<T>* Xp = dptr(X, ldx);
+        cplx<T>* Yp = dptr(Y, ldy);
+        const Res rX = res(X), rY = res(Y), rC = res(C);
+        if (kc != LRK) {
+            int ldc;
+            cplx<T>* Cp = dptr(C, ldc);
+            rec_gemm(0, 1, C.m, C.n, k, one(), Xp, ldx, Yp, ldy, one(), Cp, ldc, {rX, rY}, {rC});
+            return;
+        }
+        if (lrb(C).K + k > kmax) flush_all();
+        const int col = reserve(C, k);
+        LR& Lc = lrb(C);
+        rec_copy(0, C.m, k, one(), Xp, ldx, Lc.U + (int64_t)col * Lc.m + C.r0, Lc.m, {rX}, {rC});
+        rec_copy(0, C.n, k, one(), Yp, ldy, Lc.V + (int64_t)col * Lc.n + C.c0, Lc.n, {rY}, {rC});
+        width_lr_a += k;
+    }
+    // scratch matrix as a raw view (its own temporary resource), zeroed
+    View scratch_view(int m, int n, int rc, int cc) {
+        cplx<T>* p = scratch.alloc((size_t)m * n);
+        const Res t = temp();
+        rec_copy(0, m, n, zero(), nullptr, m, p, m, {}, {t});
+        return raw(p, m, m, n, rc, cc, t);
+    }
+
     void update(const View& C, const View& A, const View& B, cplx<T> al) {
         const bool hc = kind(C) == HIER, ha = kind(A) == HIER, hb = kind(B) == HIER;
+        // low-rank times hierarchical: the product has the operand's rank;
+        // form it through H-matvecs instead of splitting the factors
+        if (kind(A) == LRK && hb && lrb(A).K > 0) {
+            struct Pin {
+                int& p;
+                Pin(int& x) : p(x) { ++p; }
+                ~Pin() { --p; }
+            } pg(pin);
+            LR& La = lrb(A);
+            const int ka = La.K;
+            if (La.dirty) update(C, dense_part(A), B, al);
+            const View Tv = scratch_view(B.n, ka, B.cc, -1);                // B^T V_A
+            updateT(Tv, B, raw(La.V + A.c0, La.n, A.n, ka, A.cc, -1, res(A)), one());
+            const View X = scratch_view(A.m, ka, A.rc, -1);
+            rec_copy(0, A.m, ka, al, La.U + A.r0, La.m, X.p, A.m, {res(A)}, {X.own});
+            add_lowrank(C, X, Tv, ka);
+            return;
+        }
+        if (kind(B) == LRK && ha && lrb(B).K > 0) {
+            struct Pin {
+                int& p;
+                Pin(int& x) : p(x) { ++p; }
+                ~Pin() { --p; }
+            } pg(pin);
+            LR& Lb = lrb(B);
+            const int kb = Lb.K;
+            if (Lb.dirty) update(C, A, dense_part(B), al);
+            const View Tv = scratch_view(A.m, kb, A.rc, -1);                // alpha A U_B
+            update(Tv, A, raw(Lb.U + B.r0, Lb.m, B.m, kb, B.rc, -1, res(B)), al);
+            const View Y = scratch_view(B.n, kb, B.cc, -1);
+            rec_copy(0, B.n, kb, one(), Lb.V + B.c0, Lb.n, Y.p, B.n, {res(B)}, {Y.own});
+            add_lowrank(C, Tv, Y, kb);
+            return;
+        }
         if (hc || ha || hb) {
             const bool sr = hc || ha, sm = ha || hb, sc = hc || hb;
             for (int i = (sr ? 0 : -1); i < (sr ? 2 : 0); ++i)
@@ -847,8 +920,11 @@ template <typename T> struct HF {
             cplx<T>* Bp = dptr(B, ldb);
             rec_gemm(1, 0, C.m, C.n, B.m, al, Bp, ldb, Xp, ldx, one(), Cp, ldc, {rB, rX}, {rC});
         } else {
-            // (U V^T)^T X = V (U^T X)
+            // (U V^T + D)^T X = V (U^T X) + D^T X
             LR& Lb = lrb(B);
+            if (Lb.dirty)
+                rec_gemm(1, 0, C.m, C.n, B.m, al, Lb.D + (int64_t)B.c0 * Lb.m + B.r0, Lb.m, Xp, ldx, one(), Cp, ldc,
+                         {rB, rX}, {rC});
             const int kb = Lb.K;
             if (kb == 0) return;
             const Res t = temp();
