@@ -26,6 +26,7 @@ sys.path.insert(0, ROOT)
 
 def run_pipeline(cbie, spec, kh, pol, prec, ir_tol):
     s = cbie.Solver([spec])
+    s.set_profiling(True)
     s.build_tree(leaf_size=256, eta=1.0, near_delta=1.0)
     s.fill()
     s.compress(1e-6)
@@ -121,6 +122,17 @@ def main():
 
     name0 = "mixed" if "mixed" in results else list(results)[0]
     dt, st = results[name0]
+    # dominant kernel: the batched complex GEMM of the H-LU and its solves
+    # (8 m n k algorithmic flops per product), timed by HIP events on the
+    # library stream around every launch of the last timed step
+    peak = 157.3 if name0 == "mixed" else 78.6      # MI355X dense MFMA FP32 / FP64, TFLOP/s
+    achieved = st["gemm_flops"] / st["gemm_seconds"] / 1e12 if st["gemm_seconds"] > 0 else None
+    roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+                "frac": achieved / peak if achieved else None, "traffic": None,
+                "kernel": "k_zgemm (batched complex GEMM, %s)" % ("complex64" if name0 == "mixed" else "complex128"),
+                "launches": st["gemm_launches"], "avg_launch_us": 1e6 * st["gemm_seconds"] / max(st["gemm_launches"], 1),
+                "flops_per_launch": st["gemm_flops"] / max(st["gemm_launches"], 1),
+                "kernel_seconds": st["gemm_seconds"]}
     line = {
         "metric": "H build+factor+solve s & unknowns/s, mixed vs FP64 H-LU, at 1e-5 rel err",
         "value": N / dt, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -128,6 +140,7 @@ def main():
         "dtype": "c64+f64" if name0 == "mixed" else "c128", "data": "synthetic",
         "config": {"workload": "PEC sphere ka=20, 384 patches q=8, 49152 unknowns, leaf 256, eta 1, "
                                "ACA 1e-6, 16 plane waves", "pipeline": name0},
+        "roofline": roofline,
         "phases_s": {p: st["t_" + p] for p in ("tree", "fill", "compress", "factor", "solve")},
         "stats": {k: st[k] for k in ("n_lr_blocks", "n_dense_blocks", "max_rank", "compression_rate",
                                      "n_kernel_launches", "factor_flops", "ir_iterations", "quad_seconds")},

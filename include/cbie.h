@@ -161,8 +161,20 @@ typedef struct {
     int64_t n_kernel_launches;       /* launches in the last factor           */
     int64_t ir_iterations;           /* sweeps of the last solve              */
     double quad_seconds;             /* near/self quadrature kernel time      */
+    /* batched complex GEMM (the H-LU's dense contractions) since create:
+     * launches, algorithmic flops (8 m n k per product) and, with
+     * profiling on, the summed kernel time from HIP events recorded around
+     * each launch on the context stream (0 otherwise)                        */
+    int64_t gemm_launches;
+    double gemm_flops;
+    double gemm_seconds;
 } cbie_stats;
 cbie_status cbie_get_stats(cbie_ctx* ctx, void* stats_out, size_t bytes);
+
+/* Kernel timing: on != 0 brackets every batched GEMM launch with HIP events
+ * on the context stream (their sum is reported as gemm_seconds).  Costs a
+ * little host time per launch; off by default.  Errors: EINVAL, EHIP. */
+cbie_status cbie_set_profiling(cbie_ctx* ctx, int on);
 
 /* Parity hooks (small problems; no effect on the solver state).
  * Near pairs after build_tree: for each pair, target node and patch index

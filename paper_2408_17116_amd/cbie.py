@@ -23,7 +23,8 @@ RANK_ADAPTIVE, RANK_PREDICTED = 0, 1
 
 EXPORTED = ["cbie_create", "cbie_build_tree", "cbie_fill", "cbie_compress", "cbie_factor",
             "cbie_solve", "cbie_matvec", "cbie_rhs_planewave", "cbie_farfield", "cbie_get_stats",
-            "cbie_get_near_pairs", "cbie_export_dense", "cbie_last_error", "cbie_destroy"]
+            "cbie_set_profiling", "cbie_get_near_pairs", "cbie_export_dense", "cbie_last_error",
+            "cbie_destroy"]
 
 
 class CbieError(RuntimeError):
@@ -50,7 +51,8 @@ class Stats(C.Structure):
         ("compression_rate", C.c_double), ("t_tree", C.c_double), ("t_fill", C.c_double),
         ("t_compress", C.c_double), ("t_factor", C.c_double), ("t_solve", C.c_double),
         ("factor_flops", C.c_int64), ("n_kernel_launches", C.c_int64),
-        ("ir_iterations", C.c_int64), ("quad_seconds", C.c_double)]
+        ("ir_iterations", C.c_int64), ("quad_seconds", C.c_double),
+        ("gemm_launches", C.c_int64), ("gemm_flops", C.c_double), ("gemm_seconds", C.c_double)]
 
 
 _lib = None
@@ -76,6 +78,7 @@ def load(path: str = LIB_PATH):
         "cbie_rhs_planewave": ([vp, i32, vp, vp, vp, C.c_long], i32),
         "cbie_farfield": ([vp, i32, vp, C.c_long, i32, vp, vp], i32),
         "cbie_get_stats": ([vp, vp, C.c_size_t], i32),
+        "cbie_set_profiling": ([vp, i32], i32),
         "cbie_get_near_pairs": ([vp, i64, vp, vp, C.POINTER(i64)], i32),
         "cbie_export_dense": ([vp, vp, C.c_long], i32),
         "cbie_last_error": ([vp], C.c_char_p),
@@ -194,6 +197,10 @@ class Solver:
         self._check(self.lib.cbie_farfield(self.h, xc.shape[0], _ptr(xc), self.n, rhat.shape[0],
                                            rhat.ctypes.data_as(C.c_void_p), out.ctypes.data_as(C.c_void_p)))
         return out
+
+    def set_profiling(self, on=True):
+        """Time every batched GEMM launch with HIP events (gemm_seconds)."""
+        self._check(self.lib.cbie_set_profiling(self.h, 1 if on else 0))
 
     def stats(self) -> dict:
         s = Stats()

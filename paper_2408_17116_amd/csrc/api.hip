@@ -194,6 +194,10 @@ cbie_status cbie_get_stats(cbie_ctx* ctx, void* stats_out, size_t bytes) {
     return CBIE_OK;
 }
 
+cbie_status cbie_set_profiling(cbie_ctx* ctx, int on) {
+    return guarded(ctx, [&](Ctx& c) { c.gemm_timer.on = on != 0; });
+}
+
 cbie_status cbie_get_near_pairs(cbie_ctx* ctx, int64_t cap, int32_t* targets, int32_t* patches,
                                 int64_t* count_out) {
     return guarded(ctx, [&](Ctx& c) {

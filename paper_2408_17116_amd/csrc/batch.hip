@@ -6,77 +6,155 @@ namespace cbie {
 template <typename T> __device__ inline cplx<T> bz() { return cplx<T>{(T)0, (T)0}; }
 
 // ---------------------------------------------------------------- GEMM
-// One work-group per 64 x 64 output tile of one descriptor; K staged in
-// LDS by 16; thread (tx, ty) owns rows tx + 16 i, columns ty + 16 j.
-template <typename T>
-__global__ __launch_bounds__(256) void k_gemm_b(const GemmDesc<T>* __restrict__ descs,
-                                                const GemmTile* __restrict__ tiles, int ntiles) {
-    constexpr int BM = 64, BN = 64, BK = 16;
-    __shared__ cplx<T> As[BK][BM + 1];
-    __shared__ cplx<T> Bs[BK][BN + 1];
-    if ((int)blockIdx.x >= ntiles) return;
-    const GemmTile tl = tiles[blockIdx.x];
+// Complex GEMM on the matrix cores.  A complex product is four real
+// 16x16x4 MFMAs into separate real and imaginary accumulators:
+//   Cr += Ar Br - Ai Bi,   Ci += Ar Bi + Ai Br.
+// Operand layout of v_mfma_*_16x16x4 (wave64): lane l supplies A[l%16][l/16]
+// and B[l/16][l%16]; its v-th result (v = 0..3) is D[row(l, v)][l%16] with
+// row = 4 (l/16) + v for f32 and row = l/16 + 4 v for f64 (measured).
+template <typename T> struct Mfma;
+template <> struct Mfma<float> {
+    typedef float v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline v4 op(float a, float b, v4 c) { return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0); }
+    static __device__ inline int row(int g, int v) { return 4 * g + v; }
+};
+template <> struct Mfma<double> {
+    typedef double v4 __attribute__((ext_vector_type(4)));
+    static __device__ inline v4 op(double a, double b, v4 c) { return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0); }
+    static __device__ inline int row(int g, int v) { return g + 4 * v; }
+};
+
+// One work-group (4 waves) per BM x BN output tile; op(A) and op(B) are
+// staged through LDS by BK-deep slices with the next slice prefetched into
+// registers.  Waves split the tile WGM x (4 / WGM).  A work-group reads
+// only the rows of op(A) and columns of op(B) of its own tile and stores
+// after its last read, so a tile that spans all rows (or all columns) of
+// C may overwrite its own operand: X := M X and X := X M in place.
+template <typename T, int BM, int BN, int WGM, int BK>
+__global__ __launch_bounds__(256) void k_zgemm(const GemmDesc<T>* __restrict__ descs,
+                                               const GemmTile* __restrict__ tiles, int ntiles) {
+    constexpr int WGN = 4 / WGM, WM = BM / WGM, WN = BN / WGN, FM = WM / 16, FN = WN / 16;
+    constexpr int PAD = sizeof(T) == 4 ? 16 : 2;
+    constexpr int NA = BM * BK / 256, NB = BK * BN / 256;
+    static_assert(NA >= 1 && NB >= 1 && FM >= 1 && FN >= 1, "tile shape");
+    typedef typename Mfma<T>::v4 v4;
+    __shared__ cplx<T> As[BK][BM + PAD];
+    __shared__ cplx<T> Bs[BK][BN + PAD];
+    // consecutive tiles (which share operand panels) go to one XCD: the
+    // hardware deals work-groups round-robin over the 8 XCDs
+    const int per = (int)gridDim.x >> 3;
+    const int t = ((int)blockIdx.x & 7) * per + ((int)blockIdx.x >> 3);
+    if (t >= ntiles) return;
+    const GemmTile tl = tiles[t];
     const GemmDesc<T> D = descs[tl.desc];
     const int m = D.m, n = D.n, k = D.k;
-    const int bm = tl.m0, bn = tl.n0;
-    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
-    cplx<T> acc[4][4];
-    for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 4; ++j) acc[i][j] = bz<T>();
-    for (int k0 = 0; k0 < k; k0 += BK) {
-        for (int e = tid; e < BM * BK; e += 256) {
+    const int m0 = tl.m0, n0 = tl.n0;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int wm = wave % WGM, wn = wave / WGM;
+    const int r = lane & 15, kq = lane >> 4;
+
+    v4 cr[FM][FN], ci[FM][FN];
+    for (int i = 0; i < FM; ++i)
+        for (int j = 0; j < FN; ++j)
+            for (int v = 0; v < 4; ++v) { cr[i][j][v] = (T)0; ci[i][j][v] = (T)0; }
+
+    cplx<T> ra[NA], rb[NB];
+    auto load = [&](int k0) {
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+            const int e = tid + 256 * q;
             int i, kk;
-            if (!D.ta) { i = e % BM; kk = e / BM; } else { kk = e % BK; i = e / BK; }
-            const int gi = bm + i, gk = k0 + kk;
-            cplx<T> v = bz<T>();
+            if (D.ta == 0) { i = e % BM; kk = e / BM; } else { kk = e % BK; i = e / BK; }
+            const int gi = m0 + i, gk = k0 + kk;
+            cplx<T> v{(T)0, (T)0};
             if (gi < m && gk < k) {
-                v = D.ta ? D.A[gk + (int64_t)gi * D.lda] : D.A[gi + (int64_t)gk * D.lda];
+                v = D.ta == 0 ? D.A[gi + (int64_t)gk * D.lda] : D.A[gk + (int64_t)gi * D.lda];
                 if (D.ta == 2) v.im = -v.im;
             }
-            As[kk][i] = v;
+            ra[q] = v;
         }
-        for (int e = tid; e < BK * BN; e += 256) {
-            int kk, j;
-            if (!D.tb) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
-            const int gj = bn + j, gk = k0 + kk;
-            cplx<T> v = bz<T>();
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int e = tid + 256 * q;
+            int j, kk;
+            if (D.tb == 0) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
+            const int gj = n0 + j, gk = k0 + kk;
+            cplx<T> v{(T)0, (T)0};
             if (gj < n && gk < k) {
-                v = D.tb ? D.B[gj + (int64_t)gk * D.ldb] : D.B[gk + (int64_t)gj * D.ldb];
+                v = D.tb == 0 ? D.B[gk + (int64_t)gj * D.ldb] : D.B[gj + (int64_t)gk * D.ldb];
                 if (D.tb == 2) v.im = -v.im;
             }
-            Bs[kk][j] = v;
+            rb[q] = v;
+        }
+    };
+    load(0);
+    for (int k0 = 0; k0 < k; k0 += BK) {
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < NA; ++q) {
+            const int e = tid + 256 * q;
+            if (D.ta == 0) As[e / BM][e % BM] = ra[q]; else As[e % BK][e / BK] = ra[q];
+        }
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const int e = tid + 256 * q;
+            if (D.tb == 0) Bs[e % BK][e / BK] = rb[q]; else Bs[e / BN][e % BN] = rb[q];
         }
         __syncthreads();
-#pragma unroll 4
-        for (int kk = 0; kk < BK; ++kk) {
-            cplx<T> a[4], b[4];
-            for (int i = 0; i < 4; ++i) a[i] = As[kk][tx + 16 * i];
-            for (int j = 0; j < 4; ++j) b[j] = Bs[kk][ty + 16 * j];
-            for (int i = 0; i < 4; ++i)
-                for (int j = 0; j < 4; ++j) cfma(acc[i][j], a[i], b[j]);
+        if (k0 + BK < k) load(k0 + BK);
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            cplx<T> a[FM], b[FN];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) a[i] = As[kk + kq][wm * WM + 16 * i + r];
+#pragma unroll
+            for (int j = 0; j < FN; ++j) b[j] = Bs[kk + kq][wn * WN + 16 * j + r];
+#pragma unroll
+            for (int i = 0; i < FM; ++i) {
+                const T nai = -a[i].im;
+#pragma unroll
+                for (int j = 0; j < FN; ++j) {
+                    cr[i][j] = Mfma<T>::op(a[i].re, b[j].re, cr[i][j]);
+                    cr[i][j] = Mfma<T>::op(nai, b[j].im, cr[i][j]);
+                    ci[i][j] = Mfma<T>::op(a[i].re, b[j].im, ci[i][j]);
+                    ci[i][j] = Mfma<T>::op(a[i].im, b[j].re, ci[i][j]);
+                }
+            }
         }
-        __syncthreads();
     }
     const bool zb = (D.beta.re == (T)0 && D.beta.im == (T)0);
-    for (int j = 0; j < 4; ++j) {
-        const int col = bn + ty + 16 * j;
+#pragma unroll
+    for (int j = 0; j < FN; ++j) {
+        const int col = n0 + wn * WN + 16 * j + r;
         if (col >= n) continue;
-        for (int i = 0; i < 4; ++i) {
-            const int row = bm + tx + 16 * i;
-            if (row >= m) continue;
-            cplx<T>* cp = D.C + row + (int64_t)col * D.ldc;
-            cplx<T> v = D.alpha * acc[i][j];
-            if (!zb) cfma(v, D.beta, *cp);
-            *cp = v;
+#pragma unroll
+        for (int i = 0; i < FM; ++i) {
+            const int row0 = m0 + wm * WM + 16 * i;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int row = row0 + Mfma<T>::row(kq, v);
+                if (row >= m) continue;
+                cplx<T>* cp = D.C + row + (int64_t)col * D.ldc;
+                cplx<T> o = D.alpha * cplx<T>{cr[i][j][v], ci[i][j][v]};
+                if (!zb) cfma(o, D.beta, *cp);
+                *cp = o;
+            }
         }
     }
 }
 
 template <typename T>
-void gemm_batched(hipStream_t s, const GemmDesc<T>* d_desc, const GemmTile* d_tiles, int ntiles) {
+void gemm_batched(hipStream_t s, const GemmDesc<T>* d_desc, const GemmTile* d_tiles, int ntiles, int shape) {
     if (ntiles <= 0) return;
-    k_gemm_b<T><<<ntiles, 256, 0, s>>>(d_desc, d_tiles, ntiles);
-    check_launch("k_gemm_b");
+    const int grid = (ntiles + 7) / 8 * 8;
+    constexpr int BKW = sizeof(T) == 4 ? 16 : 8;   // deep slices of the wide tiles fit LDS
+    switch (shape) {
+        case kTile64x64: k_zgemm<T, 64, 64, 2, 16><<<grid, 256, 0, s>>>(d_desc, d_tiles, ntiles); break;
+        case kTile256x32: k_zgemm<T, 256, 32, 4, BKW><<<grid, 256, 0, s>>>(d_desc, d_tiles, ntiles); break;
+        case kTile32x256: k_zgemm<T, 32, 256, 1, BKW><<<grid, 256, 0, s>>>(d_desc, d_tiles, ntiles); break;
+        default: throw Error{-7, "gemm_batched: unknown tile shape"};
+    }
+    check_launch("k_zgemm");
 }
 
 // ---------------------------------------------------------------- copies
@@ -517,7 +595,7 @@ void eig_batched(hipStream_t s, const EigDesc<T>* d_desc, int n) {
 }
 
 #define CBIE_BATCH_INST(T)                                                                    \
-    template void gemm_batched<T>(hipStream_t, const GemmDesc<T>*, const GemmTile*, int);      \
+    template void gemm_batched<T>(hipStream_t, const GemmDesc<T>*, const GemmTile*, int, int); \
     template void copy_batched<T>(hipStream_t, const CopyDesc<T>*, const CopyTile*, int);      \
     template void leaf_batched<T>(hipStream_t, const LeafDesc<T>*, int);                       \
     template void rand_batched<T>(hipStream_t, const RandDesc<T>*, int);                       \

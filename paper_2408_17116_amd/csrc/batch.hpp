@@ -18,6 +18,10 @@ template <typename T> struct GemmDesc {
 struct GemmTile {
     int desc, m0, n0, pad;
 };
+// output tile shapes of the batched GEMM (rows x columns of C)
+enum { kTile64x64 = 0, kTile256x32 = 1, kTile32x256 = 2 };
+inline int tile_rows(int shape) { return shape == kTile64x64 ? 64 : (shape == kTile256x32 ? 256 : 32); }
+inline int tile_cols(int shape) { return shape == kTile64x64 ? 64 : (shape == kTile256x32 ? 32 : 256); }
 
 // B = alpha op(A) (A == nullptr: B = 0); op 'N' or 'T'
 template <typename T> struct CopyDesc {
@@ -87,7 +91,7 @@ template <typename T>
 void eig_batched(hipStream_t s, const EigDesc<T>* d_desc, int n);
 
 template <typename T>
-void gemm_batched(hipStream_t s, const GemmDesc<T>* d_desc, const GemmTile* d_tiles, int ntiles);
+void gemm_batched(hipStream_t s, const GemmDesc<T>* d_desc, const GemmTile* d_tiles, int ntiles, int shape);
 template <typename T>
 void copy_batched(hipStream_t s, const CopyDesc<T>* d_desc, const CopyTile* d_tiles, int ntiles);
 template <typename T>

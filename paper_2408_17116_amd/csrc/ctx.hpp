@@ -85,6 +85,19 @@ struct Ctx {
     // statistics
     cbie_stats stats{};
 
+    // Event pairs around timed launches; times are harvested when the pool
+    // fills and at the end of each stage.
+    struct KernelTimer {
+        bool on = false;
+        std::vector<hipEvent_t> ev;
+        size_t used = 0;
+        double seconds = 0.0;
+        void begin(hipStream_t s);
+        void end(hipStream_t s);
+        void harvest();
+        ~KernelTimer();
+    } gemm_timer;
+
     Ctx();
     ~Ctx();
     void sync() { CBIE_HIP(hipStreamSynchronize(stream)); }

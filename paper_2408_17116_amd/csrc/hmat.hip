@@ -62,12 +62,25 @@ template <typename T> struct Arena {
     }
 };
 
-// owner of the memory a task touches, for dependency tracking
-struct Res {
-    int kind;          // 0 dense block, 1 low-rank block, 2 right-hand-side rows, 3 temporary
-    int id;
-    int64_t a, b;      // row interval (kind 2)
+// Memory a task touches, for dependency tracking: an owner and the
+// rectangle of rows x columns touched, in the owner's own coordinates.
+constexpr int64_t kAll = int64_t(1) << 40;
+enum ResKind {
+    RES_DENSE = 0,   // dense block (rows x columns of the block)
+    RES_U = 1,       // U factor of a low-rank block (rows x factor columns)
+    RES_RHS = 2,     // right-hand sides (unknowns x right-hand sides)
+    RES_TEMP = 3,    // temporary
+    RES_V = 4,       // V factor of a low-rank block (columns of the block x factor columns)
+    RES_D = 5        // dense accumulator of a low-rank block
 };
+struct Res {
+    int kind;
+    int id;
+    int64_t r0 = 0, r1 = kAll, c0 = 0, c1 = kAll;
+};
+inline Res rect(int kind, int id, int64_t r0, int64_t m, int64_t c0, int64_t n) {
+    return Res{kind, id, r0, r0 + m, c0, c0 + n};
+}
 
 template <typename T> struct HF {
     Ctx& c;
@@ -91,6 +104,9 @@ template <typename T> struct HF {
     };
     static constexpr int64_t kDenseAccMax = int64_t(1) << 26;   // entries
     std::vector<LR> lr;
+    // > 0 while an update holds views of the block's factors or dense part:
+    // a recompression triggered meanwhile leaves the block as it is
+    std::vector<int> lr_busy;
     Arena<T> arena, scratch, rscratch;
     int pin = 0;               // > 0: recorded temporaries are still referenced
     DBuf<AcaProdJob<T>> jobbuf;
@@ -98,6 +114,8 @@ template <typename T> struct HF {
     double flops = 0.0;
     int kmax = 768;            // accumulated width that triggers recompression
     bool debug = getenv("CBIE_DEBUG") != nullptr;
+    bool audit = getenv("CBIE_CHECK_DEPS") != nullptr;
+    int64_t audit_conflicts = 0;
     double t_start = now_s();
 
     // ------------------------------------------------------ task program
@@ -107,15 +125,15 @@ template <typename T> struct HF {
     std::vector<int> clev;
     std::vector<LeafDesc<T>> ld;
     std::vector<int> llev;
-    struct St {
-        int w = -1, r = -1;
-    };
-    std::unordered_map<int64_t, St> st;
-    struct Iv {
-        int64_t a, b;
+    std::vector<int64_t> gseq, cseq, lseq;   // recording order
+    int64_t seq = 0;
+    std::vector<int> gshape;            // forced tile shape or -1
+    // per owner: rectangles with the last level that wrote or read them
+    struct Ent {
+        int64_t r0, r1, c0, c1;
         int w, r;
     };
-    std::vector<Iv> rhs_st;
+    std::unordered_map<int64_t, std::vector<Ent>> st;
     int next_temp = 0;
     int max_level = -1;
     void* pinned = nullptr;
@@ -129,54 +147,64 @@ template <typename T> struct HF {
 
     static int64_t key(const Res& r) { return ((int64_t)r.kind << 40) | (int64_t)(uint32_t)r.id; }
 
+    static bool overlap(const Ent& e, const Res& r) {
+        return e.r0 < r.r1 && r.r0 < e.r1 && e.c0 < r.c1 && r.c0 < e.c1;
+    }
+    // Earliest level after every conflicting task: reads wait for writes,
+    // writes for reads and writes of overlapping rectangles.  (Accumulations
+    // into one rectangle are ordered like writes: the results do not depend
+    // on the schedule.)
     int level_of(const std::vector<Res>& rd, const std::vector<Res>& wr) {
         int lv = 0;
-        for (const Res& r : rd) {
-            if (r.kind == 2) {
-                for (const Iv& v : rhs_st)
-                    if (v.a < r.b && r.a < v.b) lv = std::max(lv, v.w + 1);
-            } else {
-                auto it = st.find(key(r));
-                if (it != st.end()) lv = std::max(lv, it->second.w + 1);
+        for (const Res& x : rd) {
+            auto it = st.find(key(x));
+            if (it == st.end()) continue;
+            for (const Ent& e : it->second)
+                if (overlap(e, x)) lv = std::max(lv, e.w + 1);
+        }
+        for (const Res& x : wr) {
+            auto it = st.find(key(x));
+            if (it == st.end()) continue;
+            for (const Ent& e : it->second)
+                if (overlap(e, x)) lv = std::max(lv, std::max(e.w, e.r) + 1);
+        }
+        auto note = [&](const Res& x, int mode) {
+            std::vector<Ent>& v = st[key(x)];
+            Ent* e = nullptr;
+            for (Ent& y : v)
+                if (y.r0 == x.r0 && y.r1 == x.r1 && y.c0 == x.c0 && y.c1 == x.c1) { e = &y; break; }
+            if (!e) {
+                v.push_back(Ent{x.r0, x.r1, x.c0, x.c1, -1, -1});
+                e = &v.back();
             }
-        }
-        for (const Res& r : wr) {
-            if (r.kind == 2) {
-                for (const Iv& v : rhs_st)
-                    if (v.a < r.b && r.a < v.b) lv = std::max(lv, std::max(v.w, v.r) + 1);
-            } else {
-                auto it = st.find(key(r));
-                if (it != st.end()) lv = std::max(lv, std::max(it->second.w, it->second.r) + 1);
-            }
-        }
-        for (const Res& r : rd) {
-            if (r.kind == 2) rhs_st.push_back(Iv{r.a, r.b, -1, lv});
-            else {
-                St& x = st[key(r)];
-                x.r = std::max(x.r, lv);
-            }
-        }
-        for (const Res& r : wr) {
-            if (r.kind == 2) rhs_st.push_back(Iv{r.a, r.b, lv, -1});
-            else st[key(r)].w = lv;
-        }
+            int& f = mode == 0 ? e->r : e->w;
+            f = std::max(f, lv);
+        };
+        for (const Res& x : rd) note(x, 0);
+        for (const Res& x : wr) note(x, 1);
         max_level = std::max(max_level, lv);
         return lv;
     }
-    Res temp() { return Res{3, next_temp++, 0, 0}; }
+    Res temp() { return Res{RES_TEMP, next_temp++}; }
 
+    // C = al op(A) op(B) + be C; shape forces a tile shape (in-place
+    // products need full-height or full-width tiles)
     void rec_gemm(int ta, int tb, int m, int n, int k, cplx<T> al, const cplx<T>* A, int lda, const cplx<T>* B,
-                  int ldb, cplx<T> be, cplx<T>* C, int ldc, const std::vector<Res>& rd, const std::vector<Res>& wr) {
+                  int ldb, cplx<T> be, cplx<T>* C, int ldc, const std::vector<Res>& rd, const std::vector<Res>& wr,
+                  int shape = -1) {
         if (m <= 0 || n <= 0) return;
+        const bool b0 = be.re == (T)0 && be.im == (T)0, b1 = be.re == (T)1 && be.im == (T)0;
         if (k <= 0) {
-            if (be.re == (T)1 && be.im == (T)0) return;
-            rec_copy(0, m, n, be, (be.re == (T)0 && be.im == (T)0) ? nullptr : C, ldc, C, ldc, rd, wr);
+            if (b1) return;
+            rec_copy(0, m, n, be, b0 ? nullptr : C, ldc, C, ldc, rd, wr);
             return;
         }
         GemmDesc<T> g{m, n, k, ta, tb, al, be, A, B, C, lda, ldb, ldc, 0};
         std::vector<Res> rr = rd;
-        if (!(be.re == (T)0 && be.im == (T)0)) rr.insert(rr.end(), wr.begin(), wr.end());
+        if (!b0) rr.insert(rr.end(), wr.begin(), wr.end());
         glev.push_back(level_of(rr, wr));
+        gshape.push_back(shape);
+        gseq.push_back(seq++);
         gd.push_back(g);
         flops += 8.0 * m * n * k;
     }
@@ -185,15 +213,116 @@ template <typename T> struct HF {
         if (m <= 0 || n <= 0) return;
         cd.push_back(CopyDesc<T>{m, n, trans, lda, ldb, al, A, B});
         clev.push_back(level_of(rd, wr));
+        cseq.push_back(seq++);
     }
     void rec_leaf(int leaf) {
         const DenseBlockDev& db = c.dblk[leaf];
         cplx<T>* LP = inv.p + inv_off[leaf];
         ld.push_back(LeafDesc<T>{db.ld, db.ld, dense.p + db.offset, piv.p + piv_off[leaf], info.p + leaf, LP,
                                  LP + (int64_t)db.ld * db.ld});
-        const Res r{0, leaf, 0, 0};
+        const Res r{RES_DENSE, leaf};
         llev.push_back(level_of({r}, {r}));
+        lseq.push_back(seq++);
         flops += 16.0 / 3.0 * (double)db.ld * db.ld * db.ld;
+    }
+
+    // tile shape with the least padding; the square tile on ties
+    static int pick_shape(int m, int n) {
+        auto area = [&](int sh) {
+            const int64_t br = tile_rows(sh), bc = tile_cols(sh);
+            return ((m + br - 1) / br * br) * ((n + bc - 1) / bc * bc);
+        };
+        int best = kTile64x64;
+        for (int sh : {kTile256x32, kTile32x256})
+            if (area(sh) < area(best)) best = sh;
+        return best;
+    }
+    static void add_tiles(std::vector<GemmTile>& t, int di, const GemmDesc<T>& d, int sh) {
+        for (int m0 = 0; m0 < d.m; m0 += tile_rows(sh))
+            for (int n0 = 0; n0 < d.n; n0 += tile_cols(sh)) t.push_back(GemmTile{di, m0, n0, 0});
+    }
+    // one batched GEMM launch of algorithmic flops fl, timed when profiling
+    void launch_gemm(const GemmDesc<T>* d, const GemmTile* t, int ntiles, int sh, double fl) {
+        Ctx::KernelTimer& tm = c.gemm_timer;
+        if (tm.on) tm.begin(s);
+        gemm_batched<T>(s, d, t, ntiles, sh);
+        if (tm.on) tm.end(s);
+        ++launches;
+        ++c.stats.gemm_launches;
+        c.stats.gemm_flops += fl;
+    }
+
+    // Dependency audit (CBIE_CHECK_DEPS).  From the memory each recorded
+    // task touches (column by column): two tasks that touch the same memory,
+    // unless both only read it, must run in recording order at different
+    // levels.
+    struct Span {
+        uintptr_t a, b;
+        int task, mode;   // mode 0 read, 1 write
+    };
+    static void spans_of(std::vector<Span>& out, const void* base, int64_t rows, int64_t cols, int64_t ld, int task,
+                         int mode) {
+        if (!base || rows <= 0 || cols <= 0) return;
+        const uintptr_t p = (uintptr_t)base, es = sizeof(cplx<T>);
+        if (rows == ld) {
+            out.push_back(Span{p, p + (uintptr_t)(rows * cols) * es, task, mode});
+            return;
+        }
+        for (int64_t j = 0; j < cols; ++j)
+            out.push_back(Span{p + (uintptr_t)(j * ld) * es, p + (uintptr_t)(j * ld + rows) * es, task, mode});
+    }
+    void audit_program() {
+        struct Task {
+            int64_t seq;
+            int level;
+            std::string what;
+        };
+        std::vector<Task> tk;
+        std::vector<Span> sp;
+        for (size_t i = 0; i < gd.size(); ++i) {
+            const GemmDesc<T>& d = gd[i];
+            const int t = (int)tk.size();
+            tk.push_back(Task{gseq[i], glev[i],
+                              "gemm " + std::to_string(d.m) + "x" + std::to_string(d.n) + "x" + std::to_string(d.k) +
+                                  " ta" + std::to_string(d.ta) + " tb" + std::to_string(d.tb)});
+            spans_of(sp, d.A, d.ta ? d.k : d.m, d.ta ? d.m : d.k, d.lda, t, 0);
+            spans_of(sp, d.B, d.tb ? d.n : d.k, d.tb ? d.k : d.n, d.ldb, t, 0);
+            spans_of(sp, d.C, d.m, d.n, d.ldc, t, 1);
+        }
+        for (size_t i = 0; i < cd.size(); ++i) {
+            const CopyDesc<T>& d = cd[i];
+            const int t = (int)tk.size();
+            tk.push_back(Task{cseq[i], clev[i],
+                              "copy " + std::to_string(d.m) + "x" + std::to_string(d.n) + " trans" + std::to_string(d.trans)});
+            spans_of(sp, d.A, d.trans ? d.n : d.m, d.trans ? d.m : d.n, d.lda, t, 0);
+            spans_of(sp, d.B, d.m, d.n, d.ldb, t, 1);
+        }
+        for (size_t i = 0; i < ld.size(); ++i) {
+            const LeafDesc<T>& d = ld[i];
+            const int t = (int)tk.size();
+            tk.push_back(Task{lseq[i], llev[i], "leaf " + std::to_string(d.n)});
+            spans_of(sp, d.A, d.n, d.n, d.lda, t, 1);
+            spans_of(sp, d.LP, d.n, d.n, d.n, t, 1);
+            spans_of(sp, d.UI, d.n, d.n, d.n, t, 1);
+        }
+        std::sort(sp.begin(), sp.end(), [](const Span& x, const Span& y) { return x.a < y.a; });
+        std::vector<Span> act;
+        for (const Span& x : sp) {
+            size_t w = 0;
+            for (size_t q = 0; q < act.size(); ++q)
+                if (act[q].b > x.a) act[w++] = act[q];
+            act.resize(w);
+            for (const Span& y : act) {
+                if (y.task == x.task || (x.mode == 0 && y.mode == 0)) continue;
+                const Task &X = tk[x.task], &Y = tk[y.task];
+                const bool bad = (X.seq < Y.seq) ? !(X.level < Y.level) : !(Y.level < X.level);
+                if (bad && audit_conflicts++ < 20)
+                    fprintf(stderr, "[cbie] dependency audit: %s (seq %lld, level %d, mode %d) vs %s (seq %lld, level %d, mode %d)\n",
+                            X.what.c_str(), (long long)X.seq, X.level, x.mode, Y.what.c_str(), (long long)Y.seq, Y.level,
+                            y.mode);
+            }
+            act.push_back(x);
+        }
     }
 
     // run everything recorded so far, level by level
@@ -207,10 +336,12 @@ template <typename T> struct HF {
         for (size_t i = 0; i < gd.size(); ++i) gl[glev[i]].push_back((int)i);
         for (size_t i = 0; i < cd.size(); ++i) cl[clev[i]].push_back((int)i);
         for (size_t i = 0; i < ld.size(); ++i) ll[llev[i]].push_back((int)i);
-        // one pinned staging buffer: per level [gemm descs][gemm tiles][copy descs][copy tiles][leaf descs]
+        // one pinned staging buffer: per level and tile shape [gemm descs][gemm
+        // tiles], then [copy descs][copy tiles][leaf descs]
         struct Seg {
-            size_t g, gt, c, ct, l;
-            int ng, ngt, nc, nct, nl;
+            size_t g[3], gt[3], c, ct, l;
+            int ng[3], ngt[3], nc, nct, nl;
+            double fl[3];
         };
         std::vector<Seg> seg(L);
         std::vector<char> host;
@@ -222,14 +353,23 @@ template <typename T> struct HF {
         };
         for (int lv = 0; lv < L; ++lv) {
             Seg& sg = seg[lv];
-            std::vector<GemmDesc<T>> g;
-            std::vector<GemmTile> gt;
-            for (int i : gl[lv]) {
-                const GemmDesc<T>& d = gd[i];
-                const int di = (int)g.size();
-                g.push_back(d);
-                for (int m0 = 0; m0 < d.m; m0 += 64)
-                    for (int n0 = 0; n0 < d.n; n0 += 64) gt.push_back(GemmTile{di, m0, n0, 0});
+            for (int sh = 0; sh < 3; ++sh) {
+                std::vector<GemmDesc<T>> g;
+                std::vector<GemmTile> gt;
+                sg.fl[sh] = 0.0;
+                for (int i : gl[lv]) {
+                    const GemmDesc<T>& d = gd[i];
+                    const int shi = gshape[i] >= 0 ? gshape[i] : pick_shape(d.m, d.n);
+                    if (shi != sh) continue;
+                    const int di = (int)g.size();
+                    g.push_back(d);
+                    add_tiles(gt, di, d, sh);
+                    sg.fl[sh] += 8.0 * d.m * d.n * d.k;
+                }
+                sg.g[sh] = put(g.data(), g.size() * sizeof(GemmDesc<T>));
+                sg.gt[sh] = put(gt.data(), gt.size() * sizeof(GemmTile));
+                sg.ng[sh] = (int)g.size();
+                sg.ngt[sh] = (int)gt.size();
             }
             std::vector<CopyDesc<T>> cc;
             std::vector<CopyTile> ct;
@@ -241,15 +381,13 @@ template <typename T> struct HF {
             }
             std::vector<LeafDesc<T>> lf;
             for (int i : ll[lv]) lf.push_back(ld[i]);
-            sg.g = put(g.data(), g.size() * sizeof(GemmDesc<T>));
-            sg.gt = put(gt.data(), gt.size() * sizeof(GemmTile));
             sg.c = put(cc.data(), cc.size() * sizeof(CopyDesc<T>));
             sg.ct = put(ct.data(), ct.size() * sizeof(CopyTile));
             sg.l = put(lf.data(), lf.size() * sizeof(LeafDesc<T>));
-            sg.ng = (int)g.size(); sg.ngt = (int)gt.size();
             sg.nc = (int)cc.size(); sg.nct = (int)ct.size();
             sg.nl = (int)lf.size();
         }
+        if (audit) audit_program();
         if (host.size() > pinned_bytes) {
             if (pinned) CBIE_HIP(hipHostFree(pinned));
             pinned_bytes = std::max(host.size(), pinned_bytes * 2);
@@ -264,19 +402,19 @@ template <typename T> struct HF {
         for (int lv = 0; lv < L; ++lv) {
             const Seg& sg = seg[lv];
             if (sg.nl) { leaf_batched<T>(s, (const LeafDesc<T>*)(dev.p + sg.l), sg.nl); ++launches; }
-            if (sg.ngt) {
-                gemm_batched<T>(s, (const GemmDesc<T>*)(dev.p + sg.g), (const GemmTile*)(dev.p + sg.gt), sg.ngt);
-                ++launches;
-            }
+            for (int sh = 0; sh < 3; ++sh)
+                if (sg.ngt[sh])
+                    launch_gemm((const GemmDesc<T>*)(dev.p + sg.g[sh]), (const GemmTile*)(dev.p + sg.gt[sh]),
+                                sg.ngt[sh], sh, sg.fl[sh]);
             if (sg.nct) {
                 copy_batched<T>(s, (const CopyDesc<T>*)(dev.p + sg.c), (const CopyTile*)(dev.p + sg.ct), sg.nct);
                 ++launches;
             }
         }
         levels_run += L;
-        gd.clear(); glev.clear(); cd.clear(); clev.clear(); ld.clear(); llev.clear();
+        gd.clear(); glev.clear(); gshape.clear(); gseq.clear();
+        cd.clear(); clev.clear(); ld.clear(); llev.clear(); cseq.clear(); lseq.clear();
         st.clear();
-        rhs_st.clear();
         max_level = -1;
         // temporaries of this program are dead once it has run (stream
         // order), unless an update in progress still refers to some of them
@@ -316,16 +454,22 @@ template <typename T> struct HF {
     }
     void run_gemms(const std::vector<GemmDesc<T>>& g) {
         if (g.empty()) return;
-        std::vector<GemmTile> tiles;
-        for (size_t i = 0; i < g.size(); ++i) {
-            flops += 8.0 * g[i].m * g[i].n * g[i].k;
-            for (int m0 = 0; m0 < g[i].m; m0 += 64)
-                for (int n0 = 0; n0 < g[i].n; n0 += 64) tiles.push_back(GemmTile{(int)i, m0, n0, 0});
+        for (int sh = 0; sh < 3; ++sh) {
+            std::vector<GemmDesc<T>> gs;
+            std::vector<GemmTile> tiles;
+            double fl = 0.0;
+            for (size_t i = 0; i < g.size(); ++i) {
+                if (pick_shape(g[i].m, g[i].n) != sh) continue;
+                fl += 8.0 * g[i].m * g[i].n * g[i].k;
+                add_tiles(tiles, (int)gs.size(), g[i], sh);
+                gs.push_back(g[i]);
+            }
+            if (tiles.empty()) continue;
+            flops += fl;
+            const GemmDesc<T>* dg = stage_upload(gs);
+            const GemmTile* dt = stage_upload(tiles);
+            launch_gemm(dg, dt, (int)tiles.size(), sh, fl);
         }
-        const GemmDesc<T>* dg = stage_upload(g);
-        const GemmTile* dt = stage_upload(tiles);
-        gemm_batched<T>(s, dg, dt, (int)tiles.size());
-        ++launches;
     }
     void run_copies(const std::vector<CopyDesc<T>>& c2) {
         if (c2.empty()) return;
@@ -482,7 +626,7 @@ template <typename T> struct HF {
         execute();
         std::vector<int> todo;
         for (int b : leaves)
-            if (lr[b].pending()) todo.push_back(b);
+            if (lr[b].pending() && lr_busy[b] == 0) todo.push_back(b);
         if (todo.empty()) return;
         for (int b : todo) flush_k += lr[b].K;
         recompress(todo);
@@ -508,8 +652,7 @@ template <typename T> struct HF {
         LR& L = lr[leaf];
         if (!L.D) {
             L.D = arena.alloc((size_t)L.m * L.n);
-            const Res rs{1, leaf, 0, 0};
-            rec_copy(0, L.m, L.n, zero(), nullptr, L.m, L.D, L.m, {}, {rs});
+            rec_copy(0, L.m, L.n, zero(), nullptr, L.m, L.D, L.m, {}, {Res{RES_D, leaf}});
         }
         L.dirty = true;
         return L.D;
@@ -523,7 +666,7 @@ template <typename T> struct HF {
         int rc = -1, cc = -1;   // row / column cluster (-1: not split)
         cplx<T>* p = nullptr;   // raw buffer (already offset)
         int ld = 0;
-        Res own{2, 0, 0, 0};    // owner of a raw buffer
+        Res own{RES_TEMP, -1};  // owner of a raw buffer and the rectangle it covers
     };
     enum Kind { RAW, DENSE, LRK, HIER };
     int kind(const View& v) const {
@@ -542,9 +685,13 @@ template <typename T> struct HF {
         v.n = nunk(b.s);
         return v;
     }
-    View raw(cplx<T>* p, int ldp, int m, int n, int rc, int cc, Res own) const {
+    // raw buffer p (m x n, leading dimension ldp) that covers rows
+    // [r0, r0 + m) and columns [c0, c0 + n) of the owner (kind, id)
+    View raw(cplx<T>* p, int ldp, int m, int n, int rc, int cc, int kind, int id, int64_t r0 = 0,
+             int64_t c0 = 0) const {
         View v;
-        v.p = p; v.ld = ldp; v.m = m; v.n = n; v.rc = rc; v.cc = cc; v.own = own;
+        v.p = p; v.ld = ldp; v.m = m; v.n = n; v.rc = rc; v.cc = cc;
+        v.own = rect(kind, id, r0, m, c0, n);
         return v;
     }
     View sub(const View& v, int ri, int ci) const {
@@ -557,7 +704,8 @@ template <typename T> struct HF {
             w.m = nunk(w.rc);
             if (v.blk < 0) {
                 w.p += off;
-                if (w.own.kind == 2) { w.own.a = v.own.a + off; w.own.b = w.own.a + w.m; }
+                w.own.r0 = v.own.r0 + off;
+                w.own.r1 = w.own.r0 + w.m;
             } else w.r0 += off;
         }
         if (ci >= 0) {
@@ -565,14 +713,30 @@ template <typename T> struct HF {
             const int off = ci == 0 ? 0 : nunk(cl.child[0]);
             w.cc = cl.child[ci];
             w.n = nunk(w.cc);
-            if (v.blk < 0) w.p += (int64_t)off * v.ld; else w.c0 += off;
+            if (v.blk < 0) {
+                w.p += (int64_t)off * v.ld;
+                w.own.c0 = v.own.c0 + off;
+                w.own.c1 = w.own.c0 + w.n;
+            } else w.c0 += off;
         }
         return w;
     }
-    Res res(const View& v) const {
-        if (v.blk < 0) return v.own;
+    // what reading or writing a view touches: a raw rectangle, a part of a
+    // dense block, or the rows of both factors of a low-rank block (all
+    // factor columns) and, when it holds one, its dense accumulator
+    std::vector<Res> res(const View& v) const {
+        if (v.blk < 0) return {v.own};
         const Block& b = T_.blocks[v.blk];
-        return Res{b.type == BLK_DENSE ? 0 : 1, b.leaf_index, 0, 0};
+        const int id = b.leaf_index;
+        if (b.type == BLK_DENSE) return {rect(RES_DENSE, id, v.r0, v.m, v.c0, v.n)};
+        std::vector<Res> r{rect(RES_U, id, v.r0, v.m, 0, kAll), rect(RES_V, id, v.c0, v.n, 0, kAll)};
+        if (lr[id].D) r.push_back(rect(RES_D, id, v.r0, v.m, v.c0, v.n));
+        return r;
+    }
+    static std::vector<Res> cat(std::initializer_list<std::vector<Res>> l) {
+        std::vector<Res> o;
+        for (const auto& v : l) o.insert(o.end(), v.begin(), v.end());
+        return o;
     }
     cplx<T>* dptr(const View& v, int& ldp) const {
         if (v.blk < 0) { ldp = v.ld; return v.p; }
@@ -585,101 +749,120 @@ template <typename T> struct HF {
     static cplx<T> zero() { return cplx<T>{(T)0, (T)0}; }
     static cplx<T> neg() { return cplx<T>{(T)-1, (T)0}; }
 
-    // room for k more columns of low-rank block C (zeroed); returns the
-    // first new column
+    int leaf_of(const View& v) const { return T_.blocks[v.blk].leaf_index; }
+    // the factor rows of a low-rank view (all factor columns)
+    std::vector<Res> fac(const View& v) const {
+        const int id = leaf_of(v);
+        return {rect(RES_U, id, v.r0, v.m, 0, kAll), rect(RES_V, id, v.c0, v.n, 0, kAll)};
+    }
+
+    // room for k more columns of low-rank block C: returns the first new
+    // column.  The new columns are zeroed where the product written into
+    // them covers only some of the block's rows (or columns).
     int reserve(const View& C, int k) {
-        const int leaf = T_.blocks[C.blk].leaf_index;
+        const int leaf = leaf_of(C);
         LR& L = lr[leaf];
-        const Res rs{1, leaf, 0, 0};
         if (L.K + k > L.cap) {
             const int nc = std::max(L.K + k, 2 * L.cap);
             cplx<T>* U = arena.alloc((size_t)L.m * nc);
             cplx<T>* V = arena.alloc((size_t)L.n * nc);
             if (L.K > 0) {
-                rec_copy(0, L.m, L.K, one(), L.U, L.m, U, L.m, {rs}, {rs});
-                rec_copy(0, L.n, L.K, one(), L.V, L.n, V, L.n, {rs}, {rs});
+                const Res ru = rect(RES_U, leaf, 0, L.m, 0, L.K), rv = rect(RES_V, leaf, 0, L.n, 0, L.K);
+                rec_copy(0, L.m, L.K, one(), L.U, L.m, U, L.m, {ru}, {ru});
+                rec_copy(0, L.n, L.K, one(), L.V, L.n, V, L.n, {rv}, {rv});
             }
             L.U = U;
             L.V = V;
             L.cap = nc;
         }
         const int col = L.K;
-        rec_copy(0, L.m, k, zero(), nullptr, L.m, L.U + (int64_t)col * L.m, L.m, {}, {rs});
-        rec_copy(0, L.n, k, zero(), nullptr, L.n, L.V + (int64_t)col * L.n, L.n, {}, {rs});
+        if (C.m < L.m)
+            rec_copy(0, L.m, k, zero(), nullptr, L.m, L.U + (int64_t)col * L.m, L.m, {},
+                     {rect(RES_U, leaf, 0, L.m, col, k)});
+        if (C.n < L.n)
+            rec_copy(0, L.n, k, zero(), nullptr, L.n, L.V + (int64_t)col * L.n, L.n, {},
+                     {rect(RES_V, leaf, 0, L.n, col, k)});
         L.K += k;
         return col;
     }
 
     // ------------------------------------------------------ C += alpha A B
-    // C += X Y^T for dense X (|rows of C| x k) and Y (|cols of C| x k),
+    // C += alpha X Y^T for dense X (|rows of C| x k) and Y (|cols of C| x k),
     // distributed over the leaves of C
-    void add_lowrank(const View& C, const View& X, const View& Y, int k) {
+    void add_lowrank(const View& C, const View& X, const View& Y, int k, cplx<T> al) {
         if (k <= 0) return;
         const int kc = kind(C);
         if (kc == HIER) {
             for (int i = 0; i < 2; ++i)
-                for (int j = 0; j < 2; ++j) add_lowrank(sub(C, i, j), sub(X, i, -1), sub(Y, j, -1), k);
+                for (int j = 0; j < 2; ++j) add_lowrank(sub(C, i, j), sub(X, i, -1), sub(Y, j, -1), k, al);
             return;
         }
         int ldx, ldy;
         cplx<T>* Xp = dptr(X, ldx);
         cplx<T>* Yp = dptr(Y, ldy);
-        const Res rX = res(X), rY = res(Y), rC = res(C);
         if (kc != LRK) {
             int ldc;
             cplx<T>* Cp = dptr(C, ldc);
-            rec_gemm(0, 1, C.m, C.n, k, one(), Xp, ldx, Yp, ldy, one(), Cp, ldc, {rX, rY}, {rC});
+            rec_gemm(0, 1, C.m, C.n, k, al, Xp, ldx, Yp, ldy, one(), Cp, ldc, cat({res(X), res(Y)}), res(C));
             return;
         }
         if (lrb(C).K + k > kmax) flush_all();
         const int col = reserve(C, k);
-        LR& Lc = lrb(C);
-        rec_copy(0, C.m, k, one(), Xp, ldx, Lc.U + (int64_t)col * Lc.m + C.r0, Lc.m, {rX}, {rC});
-        rec_copy(0, C.n, k, one(), Yp, ldy, Lc.V + (int64_t)col * Lc.n + C.c0, Lc.n, {rY}, {rC});
+        const int leaf = leaf_of(C);
+        LR& Lc = lr[leaf];
+        rec_copy(0, C.m, k, al, Xp, ldx, Lc.U + (int64_t)col * Lc.m + C.r0, Lc.m, res(X),
+                 {rect(RES_U, leaf, C.r0, C.m, col, k)});
+        rec_copy(0, C.n, k, one(), Yp, ldy, Lc.V + (int64_t)col * Lc.n + C.c0, Lc.n, res(Y),
+                 {rect(RES_V, leaf, C.c0, C.n, col, k)});
         width_lr_a += k;
     }
     // scratch matrix as a raw view (its own temporary resource), zeroed
     View scratch_view(int m, int n, int rc, int cc) {
         cplx<T>* p = scratch.alloc((size_t)m * n);
-        const Res t = temp();
-        rec_copy(0, m, n, zero(), nullptr, m, p, m, {}, {t});
-        return raw(p, m, m, n, rc, cc, t);
+        const View v = raw(p, m, m, n, rc, cc, RES_TEMP, temp().id);
+        rec_copy(0, m, n, zero(), nullptr, m, p, m, {}, {v.own});
+        return v;
     }
 
+    // marks a low-rank operand busy for the lifetime of the guard
+    struct Busy {
+        std::vector<int>& v;
+        int b;
+        Busy(std::vector<int>& vv, int bb) : v(vv), b(bb) {
+            if (b >= 0) ++v[b];
+        }
+        ~Busy() {
+            if (b >= 0) --v[b];
+        }
+    };
     void update(const View& C, const View& A, const View& B, cplx<T> al) {
         const bool hc = kind(C) == HIER, ha = kind(A) == HIER, hb = kind(B) == HIER;
+        const Busy busy_a(lr_busy, kind(A) == LRK ? leaf_of(A) : -1), busy_b(lr_busy, kind(B) == LRK ? leaf_of(B) : -1);
         // low-rank times hierarchical: the product has the operand's rank;
         // form it through H-matvecs instead of splitting the factors
+        struct Pin {
+            int& p;
+            Pin(int& x) : p(x) { ++p; }
+            ~Pin() { --p; }
+        };
         if (kind(A) == LRK && hb && lrb(A).K > 0) {
-            struct Pin {
-                int& p;
-                Pin(int& x) : p(x) { ++p; }
-                ~Pin() { --p; }
-            } pg(pin);
-            LR& La = lrb(A);
-            const int ka = La.K;
-            if (La.dirty) update(C, dense_part(A), B, al);
+            Pin pg(pin);
+            const int la = leaf_of(A);
+            const int ka = lr[la].K;
+            if (lr[la].dirty) update(C, dense_part(A), B, al);
             const View Tv = scratch_view(B.n, ka, B.cc, -1);                // B^T V_A
-            updateT(Tv, B, raw(La.V + A.c0, La.n, A.n, ka, A.cc, -1, res(A)), one());
-            const View X = scratch_view(A.m, ka, A.rc, -1);
-            rec_copy(0, A.m, ka, al, La.U + A.r0, La.m, X.p, A.m, {res(A)}, {X.own});
-            add_lowrank(C, X, Tv, ka);
+            updateT(Tv, B, raw(lr[la].V + A.c0, lr[la].n, A.n, ka, A.cc, -1, RES_V, la, A.c0, 0), one());
+            add_lowrank(C, raw(lr[la].U + A.r0, lr[la].m, A.m, ka, A.rc, -1, RES_U, la, A.r0, 0), Tv, ka, al);
             return;
         }
         if (kind(B) == LRK && ha && lrb(B).K > 0) {
-            struct Pin {
-                int& p;
-                Pin(int& x) : p(x) { ++p; }
-                ~Pin() { --p; }
-            } pg(pin);
-            LR& Lb = lrb(B);
-            const int kb = Lb.K;
-            if (Lb.dirty) update(C, A, dense_part(B), al);
-            const View Tv = scratch_view(A.m, kb, A.rc, -1);                // alpha A U_B
-            update(Tv, A, raw(Lb.U + B.r0, Lb.m, B.m, kb, B.rc, -1, res(B)), al);
-            const View Y = scratch_view(B.n, kb, B.cc, -1);
-            rec_copy(0, B.n, kb, one(), Lb.V + B.c0, Lb.n, Y.p, B.n, {res(B)}, {Y.own});
-            add_lowrank(C, Tv, Y, kb);
+            Pin pg(pin);
+            const int lb = leaf_of(B);
+            const int kb = lr[lb].K;
+            if (lr[lb].dirty) update(C, A, dense_part(B), al);
+            const View Tv = scratch_view(A.m, kb, A.rc, -1);                // A U_B
+            update(Tv, A, raw(lr[lb].U + B.r0, lr[lb].m, B.m, kb, B.rc, -1, RES_U, lb, B.r0, 0), one());
+            add_lowrank(C, Tv, raw(lr[lb].V + B.c0, lr[lb].n, B.n, kb, B.cc, -1, RES_V, lb, B.c0, 0), kb, al);
             return;
         }
         if (hc || ha || hb) {
@@ -715,23 +898,25 @@ template <typename T> struct HF {
                 update_parts(C, pa == 1 ? dense_part(A) : A, pb == 1 ? dense_part(B) : B, al);
     }
     View dense_part(const View& X) {
-        LR& L = lrb(X);
-        return raw(L.D + (int64_t)X.c0 * L.m + X.r0, L.m, X.m, X.n, X.rc, X.cc, res(X));
+        const int id = leaf_of(X);
+        const LR& L = lr[id];
+        return raw(L.D + (int64_t)X.c0 * L.m + X.r0, L.m, X.m, X.n, X.rc, X.cc, RES_D, id, X.r0, X.c0);
     }
     // C += alpha A B for leaf-level views; low-rank operands contribute their
     // factor columns only (their dense parts are passed separately)
     void update_parts(const View& C, const View& A, const View& B, cplx<T> al) {
         const int kA = kind(A), kB = kind(B), kC = kind(C);
         const bool dA = kA != LRK, dB = kB != LRK;
-        const Res rA = res(A), rB = res(B), rC = res(C);
+        const std::vector<Res> rA = dA ? res(A) : fac(A), rB = dB ? res(B) : fac(B);
         if (kC != LRK) {
+            const std::vector<Res> rC = res(C);
             int ldc;
             cplx<T>* Cp = dptr(C, ldc);
             if (dA && dB) {
                 int lda, ldb;
                 cplx<T>* Ap = dptr(A, lda);
                 cplx<T>* Bp = dptr(B, ldb);
-                rec_gemm(0, 0, C.m, C.n, A.n, al, Ap, lda, Bp, ldb, one(), Cp, ldc, {rA, rB}, {rC});
+                rec_gemm(0, 0, C.m, C.n, A.n, al, Ap, lda, Bp, ldb, one(), Cp, ldc, cat({rA, rB}), rC);
             } else if (!dA) {
                 LR& La = lrb(A);
                 const int ka = La.K;
@@ -741,18 +926,18 @@ template <typename T> struct HF {
                 if (dB) {
                     int ldb;
                     cplx<T>* Bp = dptr(B, ldb);
-                    rec_gemm(1, 0, ka, C.n, B.m, one(), La.V + A.c0, La.n, Bp, ldb, zero(), Tm, ka, {rA, rB}, {t});
+                    rec_gemm(1, 0, ka, C.n, B.m, one(), La.V + A.c0, La.n, Bp, ldb, zero(), Tm, ka, cat({rA, rB}), {t});
                 } else {
                     LR& Lb = lrb(B);
                     const int kb = Lb.K;
                     if (kb == 0) return;
                     const Res t2 = temp();
                     cplx<T>* W = scratch.alloc((size_t)ka * kb);
-                    rec_gemm(1, 0, ka, kb, B.m, one(), La.V + A.c0, La.n, Lb.U + B.r0, Lb.m, zero(), W, ka, {rA, rB},
-                             {t2});
-                    rec_gemm(0, 1, ka, C.n, kb, one(), W, ka, Lb.V + B.c0, Lb.n, zero(), Tm, ka, {t2, rB}, {t});
+                    rec_gemm(1, 0, ka, kb, B.m, one(), La.V + A.c0, La.n, Lb.U + B.r0, Lb.m, zero(), W, ka,
+                             cat({rA, rB}), {t2});
+                    rec_gemm(0, 1, ka, C.n, kb, one(), W, ka, Lb.V + B.c0, Lb.n, zero(), Tm, ka, cat({{t2}, rB}), {t});
                 }
-                rec_gemm(0, 0, C.m, C.n, ka, al, La.U + A.r0, La.m, Tm, ka, one(), Cp, ldc, {rA, t}, {rC});
+                rec_gemm(0, 0, C.m, C.n, ka, al, La.U + A.r0, La.m, Tm, ka, one(), Cp, ldc, cat({rA, {t}}), rC);
             } else {
                 LR& Lb = lrb(B);
                 const int kb = Lb.K;
@@ -761,89 +946,91 @@ template <typename T> struct HF {
                 cplx<T>* Ap = dptr(A, lda);
                 const Res t = temp();
                 cplx<T>* Tm = scratch.alloc((size_t)C.m * kb);
-                rec_gemm(0, 0, C.m, kb, A.n, one(), Ap, lda, Lb.U + B.r0, Lb.m, zero(), Tm, C.m, {rA, rB}, {t});
-                rec_gemm(0, 1, C.m, C.n, kb, al, Tm, C.m, Lb.V + B.c0, Lb.n, one(), Cp, ldc, {t, rB}, {rC});
+                rec_gemm(0, 0, C.m, kb, A.n, one(), Ap, lda, Lb.U + B.r0, Lb.m, zero(), Tm, C.m, cat({rA, rB}), {t});
+                rec_gemm(0, 1, C.m, C.n, kb, al, Tm, C.m, Lb.V + B.c0, Lb.n, one(), Cp, ldc, cat({{t}, rB}), rC);
             }
             return;
         }
         // C low rank: append the product as new columns [X | Y]
+        const int lc = leaf_of(C);
         if (!dA) {
             const int ka = lrb(A).K;
             if (ka == 0) return;
             if (!dB && lrb(B).K == 0) return;
             width_lr_a += ka;
             const int col = reserve(C, ka);
-            LR& Lc = lrb(C);
+            LR& Lc = lr[lc];
             LR& La = lrb(A);
             cplx<T>* X = Lc.U + (int64_t)col * Lc.m + C.r0;
             cplx<T>* Y = Lc.V + (int64_t)col * Lc.n + C.c0;
-            rec_copy(0, C.m, ka, al, La.U + A.r0, La.m, X, Lc.m, {rA}, {rC});
+            const Res rX = rect(RES_U, lc, C.r0, C.m, col, ka), rY = rect(RES_V, lc, C.c0, C.n, col, ka);
+            rec_copy(0, C.m, ka, al, La.U + A.r0, La.m, X, Lc.m, rA, {rX});
             if (dB) {
                 int ldb;
                 cplx<T>* Bp = dptr(B, ldb);
-                rec_gemm(1, 0, C.n, ka, B.m, one(), Bp, ldb, La.V + A.c0, La.n, zero(), Y, Lc.n, {rA, rB}, {rC});
+                rec_gemm(1, 0, C.n, ka, B.m, one(), Bp, ldb, La.V + A.c0, La.n, zero(), Y, Lc.n, cat({rA, rB}), {rY});
             } else {
                 LR& Lb = lrb(B);
                 const int kb = Lb.K;
                 const Res t = temp();
                 cplx<T>* W = scratch.alloc((size_t)kb * ka);
-                rec_gemm(1, 0, kb, ka, B.m, one(), Lb.U + B.r0, Lb.m, La.V + A.c0, La.n, zero(), W, kb, {rA, rB}, {t});
-                rec_gemm(0, 0, C.n, ka, kb, one(), Lb.V + B.c0, Lb.n, W, kb, zero(), Y, Lc.n, {t, rB}, {rC});
+                rec_gemm(1, 0, kb, ka, B.m, one(), Lb.U + B.r0, Lb.m, La.V + A.c0, La.n, zero(), W, kb, cat({rA, rB}),
+                         {t});
+                rec_gemm(0, 0, C.n, ka, kb, one(), Lb.V + B.c0, Lb.n, W, kb, zero(), Y, Lc.n, cat({{t}, rB}), {rY});
             }
         } else if (!dB) {
             const int kb = lrb(B).K;
             if (kb == 0) return;
             width_lr_b += kb;
             const int col = reserve(C, kb);
-            LR& Lc = lrb(C);
+            LR& Lc = lr[lc];
             LR& Lb = lrb(B);
             int lda;
             cplx<T>* Ap = dptr(A, lda);
             cplx<T>* X = Lc.U + (int64_t)col * Lc.m + C.r0;
             cplx<T>* Y = Lc.V + (int64_t)col * Lc.n + C.c0;
-            rec_gemm(0, 0, C.m, kb, A.n, al, Ap, lda, Lb.U + B.r0, Lb.m, zero(), X, Lc.m, {rA, rB}, {rC});
-            rec_copy(0, C.n, kb, one(), Lb.V + B.c0, Lb.n, Y, Lc.n, {rB}, {rC});
+            const Res rX = rect(RES_U, lc, C.r0, C.m, col, kb), rY = rect(RES_V, lc, C.c0, C.n, col, kb);
+            rec_gemm(0, 0, C.m, kb, A.n, al, Ap, lda, Lb.U + B.r0, Lb.m, zero(), X, Lc.m, cat({rA, rB}), {rX});
+            rec_copy(0, C.n, kb, one(), Lb.V + B.c0, Lb.n, Y, Lc.n, rB, {rY});
         } else if ((int64_t)lrb(C).m * lrb(C).n <= kDenseAccMax) {
             int lda, ldb;
             cplx<T>* Ap = dptr(A, lda);
             cplx<T>* Bp = dptr(B, ldb);
-            const int leaf = T_.blocks[C.blk].leaf_index;
-            cplx<T>* D = dacc(leaf);
-            const int m = lr[leaf].m;
-            rec_gemm(0, 0, C.m, C.n, A.n, al, Ap, lda, Bp, ldb, one(), D + (int64_t)C.c0 * m + C.r0, m, {rA, rB}, {rC});
+            cplx<T>* D = dacc(lc);
+            const int m = lr[lc].m;
+            rec_gemm(0, 0, C.m, C.n, A.n, al, Ap, lda, Bp, ldb, one(), D + (int64_t)C.c0 * m + C.r0, m, cat({rA, rB}),
+                     {rect(RES_D, lc, C.r0, C.m, C.c0, C.n)});
         } else {
             const int k = A.n;
             width_dd += k;
             const int col = reserve(C, k);
-            LR& Lc = lrb(C);
+            LR& Lc = lr[lc];
             int lda, ldb;
             cplx<T>* Ap = dptr(A, lda);
             cplx<T>* Bp = dptr(B, ldb);
             cplx<T>* X = Lc.U + (int64_t)col * Lc.m + C.r0;
             cplx<T>* Y = Lc.V + (int64_t)col * Lc.n + C.c0;
-            rec_copy(0, C.m, k, al, Ap, lda, X, Lc.m, {rA}, {rC});
-            rec_copy(1, C.n, k, one(), Bp, ldb, Y, Lc.n, {rB}, {rC});
+            rec_copy(0, C.m, k, al, Ap, lda, X, Lc.m, rA, {rect(RES_U, lc, C.r0, C.m, col, k)});
+            rec_copy(1, C.n, k, one(), Bp, ldb, Y, Lc.n, rB, {rect(RES_V, lc, C.c0, C.n, col, k)});
         }
     }
 
     // --------------------------------------------------- triangular solves
-    // Leaf solves through the explicit inverses, out of place into a
-    // temporary and copied back:  'L': X := (L^{-1} P) X,  'U': X := U^{-1} X
-    // (X: n x k),  'R': X := X U^{-1} (X: k x n),  'T': X := U^{-T} X.
-    void apply_inverse(char which, int leaf, int n, cplx<T>* X, int ldx, int k, const Res& rx) {
+    // Leaf solves through the explicit inverses, in place (a full-height or
+    // full-width GEMM tile owns every entry it overwrites):
+    // 'L': X := (L^{-1} P) X,  'U': X := U^{-1} X  (X: n x k),
+    // 'R': X := X U^{-1}  (X: k x n),  'T': X := U^{-T} X.
+    void apply_inverse(char which, int leaf, int n, cplx<T>* X, int ldx, int k, const std::vector<Res>& rx) {
         if (k <= 0) return;
+        CBIE_REQUIRE(n <= 256, -7, "diagonal leaf above 256 unknowns");
         const cplx<T>* LP = inv.p + inv_off[leaf];
         const cplx<T>* UI = LP + (int64_t)n * n;
-        const Res rl{0, leaf, 0, 0};
-        const Res t = temp();
-        cplx<T>* Tm = scratch.alloc((size_t)n * k);
+        const std::vector<Res> rd = cat({rx, {Res{RES_DENSE, leaf}}});
         if (which == 'R') {
-            rec_gemm(0, 0, k, n, n, one(), X, ldx, UI, n, zero(), Tm, k, {rx, rl}, {t});
-            rec_copy(0, k, n, one(), Tm, k, X, ldx, {t}, {rx});
+            rec_gemm(0, 0, k, n, n, one(), X, ldx, UI, n, zero(), X, ldx, rd, rx, kTile32x256);
         } else {
             const int ta = which == 'T' ? 1 : 0;
-            rec_gemm(ta, 0, n, k, n, one(), which == 'L' ? LP : UI, n, X, ldx, zero(), Tm, n, {rx, rl}, {t});
-            rec_copy(0, n, k, one(), Tm, n, X, ldx, {t}, {rx});
+            rec_gemm(ta, 0, n, k, n, one(), which == 'L' ? LP : UI, n, X, ldx, zero(), X, ldx, rd, rx, kTile256x32);
         }
     }
     // X (|d| x ncol) := L_dd^{-1} X
@@ -905,32 +1092,34 @@ template <typename T> struct HF {
     }
     // C += alpha B^T X for a block B (rows of X = rows of B): used with V factors
     void updateT(const View& C, const View& B, const View& X, cplx<T> al) {
+        const Busy busy_b(lr_busy, kind(B) == LRK ? leaf_of(B) : -1);
         if (kind(B) == HIER) {
             // (B^T)_{ij} = (B_{ji})^T
             for (int i = 0; i < 2; ++i)
                 for (int k = 0; k < 2; ++k) updateT(sub(C, i, -1), sub(B, k, i), sub(X, k, -1), al);
             return;
         }
-        const Res rB = res(B), rX = res(X), rC = res(C);
+        const std::vector<Res> rX = res(X), rC = res(C);
         int ldx, ldc;
         cplx<T>* Xp = dptr(X, ldx);
         cplx<T>* Cp = dptr(C, ldc);
         if (kind(B) == DENSE) {
             int ldb;
             cplx<T>* Bp = dptr(B, ldb);
-            rec_gemm(1, 0, C.m, C.n, B.m, al, Bp, ldb, Xp, ldx, one(), Cp, ldc, {rB, rX}, {rC});
+            rec_gemm(1, 0, C.m, C.n, B.m, al, Bp, ldb, Xp, ldx, one(), Cp, ldc, cat({res(B), rX}), rC);
         } else {
             // (U V^T + D)^T X = V (U^T X) + D^T X
-            LR& Lb = lrb(B);
+            const int lb = leaf_of(B);
+            LR& Lb = lr[lb];
             if (Lb.dirty)
                 rec_gemm(1, 0, C.m, C.n, B.m, al, Lb.D + (int64_t)B.c0 * Lb.m + B.r0, Lb.m, Xp, ldx, one(), Cp, ldc,
-                         {rB, rX}, {rC});
+                         cat({{rect(RES_D, lb, B.r0, B.m, B.c0, B.n)}, rX}), rC);
             const int kb = Lb.K;
             if (kb == 0) return;
             const Res t = temp();
             cplx<T>* Tm = scratch.alloc((size_t)kb * C.n);
-            rec_gemm(1, 0, kb, C.n, B.m, one(), Lb.U + B.r0, Lb.m, Xp, ldx, zero(), Tm, kb, {rB, rX}, {t});
-            rec_gemm(0, 0, C.m, C.n, kb, al, Lb.V + B.c0, Lb.n, Tm, kb, one(), Cp, ldc, {rB, t}, {rC});
+            rec_gemm(1, 0, kb, C.n, B.m, one(), Lb.U + B.r0, Lb.m, Xp, ldx, zero(), Tm, kb, cat({fac(B), rX}), {t});
+            rec_gemm(0, 0, C.m, C.n, kb, al, Lb.V + B.c0, Lb.n, Tm, kb, one(), Cp, ldc, cat({fac(B), {t}}), rC);
         }
     }
 
@@ -941,8 +1130,10 @@ template <typename T> struct HF {
             solveL(d, X);
         } else if (k == LRK) {
             LR& L = lrb(X);
-            if (L.K > 0) solveL(d, raw(L.U, L.m, L.m, L.K, T_.blocks[X.blk].t, -1, res(X)));
-            if (L.dirty) solveL(d, raw(L.D, L.m, L.m, L.n, T_.blocks[X.blk].t, -1, res(X)));
+            const int id = leaf_of(X);
+            const Busy busy_x(lr_busy, id);
+            if (L.K > 0) solveL(d, raw(L.U, L.m, L.m, L.K, T_.blocks[X.blk].t, -1, RES_U, id));
+            if (L.dirty) solveL(d, raw(L.D, L.m, L.m, L.n, T_.blocks[X.blk].t, -1, RES_D, id));
         } else {
             const Block& D = T_.blocks[d];
             for (int j = 0; j < 2; ++j) {
@@ -961,8 +1152,10 @@ template <typename T> struct HF {
         } else if (k == LRK) {
             // U (V^T U^{-1}) with V^T U^{-1} = (U^{-T} V)^T
             LR& L = lrb(X);
-            if (L.K > 0) solveUT(d, raw(L.V, L.n, L.n, L.K, T_.blocks[X.blk].s, -1, res(X)));
-            if (L.dirty) solveUr(d, raw(L.D, L.m, L.m, L.n, -1, T_.blocks[X.blk].s, res(X)));
+            const int id = leaf_of(X);
+            const Busy busy_x(lr_busy, id);
+            if (L.K > 0) solveUT(d, raw(L.V, L.n, L.n, L.K, T_.blocks[X.blk].s, -1, RES_V, id));
+            if (L.dirty) solveUr(d, raw(L.D, L.m, L.m, L.n, -1, T_.blocks[X.blk].s, RES_D, id));
         } else {
             const Block& D = T_.blocks[d];
             for (int i = 0; i < 2; ++i) {
@@ -995,6 +1188,36 @@ template <typename T> struct HF {
     }
 };
 
+// ------------------------------------------------------------ kernel timer
+void Ctx::KernelTimer::begin(hipStream_t s) {
+    if (used + 2 > ev.size()) {
+        if (ev.size() >= 4096) harvest();
+        while (used + 2 > ev.size()) {
+            hipEvent_t e;
+            CBIE_HIP(hipEventCreate(&e));
+            ev.push_back(e);
+        }
+    }
+    CBIE_HIP(hipEventRecord(ev[used], s));
+}
+void Ctx::KernelTimer::end(hipStream_t s) {
+    CBIE_HIP(hipEventRecord(ev[used + 1], s));
+    used += 2;
+}
+void Ctx::KernelTimer::harvest() {
+    if (used == 0) return;
+    CBIE_HIP(hipEventSynchronize(ev[used - 1]));
+    for (size_t i = 0; i < used; i += 2) {
+        float ms = 0.f;
+        CBIE_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+        seconds += 1e-3 * ms;
+    }
+    used = 0;
+}
+Ctx::KernelTimer::~KernelTimer() {
+    for (hipEvent_t e : ev) (void)hipEventDestroy(e);
+}
+
 struct HMat {
     int prec = 0;
     std::shared_ptr<HF<double>> f64;
@@ -1011,6 +1234,7 @@ template <typename T> static std::shared_ptr<HF<T>> make_factor(Ctx& c) {
     f->dense.alloc(std::max<int64_t>(c.stats.dense_entries, 1));
     convert<double, T>(s, c.stats.dense_entries, c.dense.p, f->dense.p);
     f->lr.resize(c.lblk.size());
+    f->lr_busy.assign(c.lblk.size(), 0);
     for (size_t b = 0; b < c.lblk.size(); ++b) {
         auto& L = f->lr[b];
         L.m = 2 * c.lblk[b].row_nodes;
@@ -1049,8 +1273,12 @@ template <typename T> static void run_factor(Ctx& c, HF<T>& f) {
     c.sync();
     for (size_t b = 0; b < info.size(); ++b)
         CBIE_REQUIRE(info[b] == 0, CBIE_ESINGULAR, "zero pivot in diagonal leaf " + std::to_string(b));
+    CBIE_REQUIRE(f.audit_conflicts == 0, -7,
+                 "dependency audit: " + std::to_string(f.audit_conflicts) + " conflicting task pairs in one level");
     c.stats.factor_flops = (int64_t)f.flops;
     c.stats.n_kernel_launches = f.launches;
+    c.gemm_timer.harvest();
+    c.stats.gemm_seconds = c.gemm_timer.seconds;
     if (getenv("CBIE_DEBUG"))
         fprintf(stderr, "[cbie] levels %lld flushes %lld rounds %lld widths lrA %.0f lrB %.0f dd %.0f flushK %.0f\n",
                 (long long)f.levels_run, (long long)f.flushes, (long long)f.recompress_rounds, f.width_lr_a,
@@ -1059,6 +1287,7 @@ template <typename T> static void run_factor(Ctx& c, HF<T>& f) {
 
 void stage_factor(Ctx& c, int prec) {
     const double t0 = now_s();
+    c.hm.reset();   // release an earlier factorization before building this one
     auto hm = std::make_shared<HMat>();
     hm->prec = prec;
     if (prec == CBIE_PREC_C128) {
@@ -1078,7 +1307,7 @@ template <typename T> static void lu_solve_tree(Ctx& c, HF<T>& f, cplx<T>* X, in
     for (int root : c.tree.block_roots) {
         const int cl = c.tree.blocks[root].t;
         const Cluster& C = c.tree.clusters[cl];
-        const auto v = f.raw(X + C.unk0(), ld, (int)C.nunk(), nrhs, cl, -1, Res{2, 0, C.unk0(), C.unk0() + C.nunk()});
+        const auto v = f.raw(X + C.unk0(), ld, (int)C.nunk(), nrhs, cl, -1, RES_RHS, 0, C.unk0(), 0);
         f.solveL(root, v);
         f.solveU(root, v);
     }
@@ -1157,6 +1386,8 @@ void stage_solve(Ctx& c, int nrhs, const zd* b, zd* x, long ld, double tol, int 
     k_from_tree<double><<<g, 256, 0, s>>>(c.d_tree_node.p, N, nrhs, xt.p, x, ld);
     check_launch("k_from_tree");
     c.sync();
+    c.gemm_timer.harvest();
+    c.stats.gemm_seconds = c.gemm_timer.seconds;
     if (iters) *iters = it;
     c.stats.ir_iterations = it;
     c.stats.t_solve = now_s() - t0;
