@@ -181,6 +181,33 @@ void copy_batched(hipStream_t s, const CopyDesc<T>* d_desc, const CopyTile* d_ti
     check_launch("k_copy_b");
 }
 
+// ------------------------------------------------------ split-k reduction
+template <typename T>
+__global__ __launch_bounds__(256) void k_reduce_b(const ReduceDesc<T>* __restrict__ descs,
+                                                  const CopyTile* __restrict__ tiles, int ntiles) {
+    if ((int)blockIdx.x >= ntiles) return;
+    const CopyTile tl = tiles[blockIdx.x];
+    const ReduceDesc<T> D = descs[tl.desc];
+    const int64_t tot = (int64_t)D.m * D.n;
+    const int64_t e1 = min(tot, (int64_t)tl.e0 + kCopyChunk);
+    const bool zb = D.beta.re == (T)0 && D.beta.im == (T)0;
+    for (int64_t e = tl.e0 + threadIdx.x; e < e1; e += 256) {
+        cplx<T> acc = bz<T>();
+        for (int q = 0; q < D.nsplit; ++q) acc = acc + D.W[e + q * tot];
+        const int i = (int)(e % D.m), j = (int)(e / D.m);
+        cplx<T>* cp = D.C + i + (int64_t)j * D.ldc;
+        cplx<T> o = D.alpha * acc;
+        if (!zb) cfma(o, D.beta, *cp);
+        *cp = o;
+    }
+}
+template <typename T>
+void reduce_batched(hipStream_t s, const ReduceDesc<T>* d_desc, const CopyTile* d_tiles, int ntiles) {
+    if (ntiles <= 0) return;
+    k_reduce_b<T><<<ntiles, 256, 0, s>>>(d_desc, d_tiles, ntiles);
+    check_launch("k_reduce_b");
+}
+
 // ------------------------------------------------------- leaf LU + inverse
 struct AMx {
     double v;
@@ -188,16 +215,20 @@ struct AMx {
 };
 __device__ inline AMx amx_better(AMx a, AMx b) { return (b.v > a.v || (b.v == a.v && b.i < a.i)) ? b : a; }
 
-// One work-group of 256 threads per leaf.  Right-looking LU with partial
-// pivoting by panels of 16 columns; the U12 panel row is staged in LDS for
-// the trailing update (leaves of at most 256 unknowns).  Then
-// LP = L^{-1} P and UI = U^{-1} by one thread per column.
+// One work-group of 256 threads per diagonal leaf (n <= 256).
+// LU with partial pivoting, right-looking by 16-column panels: the panel
+// is factored in LDS (column-major, one row per thread), its row swaps are
+// applied to the other columns as one permutation of the rows they touch,
+// U12 := L11^{-1} A12 by one thread per column, and A22 -= L21 U12 reads
+// both factors from LDS with the global loads of 8 entries in flight.
 template <typename T>
-__global__ __launch_bounds__(256) void k_leaf(const LeafDesc<T>* __restrict__ descs, int nd) {
-    constexpr int NB = 16, RMAX = 240;
-    __shared__ AMx sh[4];
-    __shared__ cplx<T> su[NB][RMAX];
-    __shared__ int perm[1024];
+__global__ __launch_bounds__(256) void k_leaf_lu(const LeafDesc<T>* __restrict__ descs, int nd) {
+    constexpr int NB = 16, NMAX = 256, UNR = 8;
+    __shared__ cplx<T> PT[NB * NMAX];   // PT[t * NMAX + r] = A[j0 + r, j0 + t]
+    __shared__ cplx<T> S[NB * NMAX];    // S[t * NMAX + c] = U12[t, c]
+    __shared__ unsigned wmax[4];
+    __shared__ int spiv[NB];
+    __shared__ int aff[2 * NB], src[2 * NB];
     if ((int)blockIdx.x >= nd) return;
     const LeafDesc<T> D = descs[blockIdx.x];
     const int n = D.n, lda = D.lda;
@@ -205,119 +236,276 @@ __global__ __launch_bounds__(256) void k_leaf(const LeafDesc<T>* __restrict__ de
     const int tid = threadIdx.x;
     int first_zero = 0;
     for (int j0 = 0; j0 < n; j0 += NB) {
-        const int jb = min(NB, n - j0);
-        for (int j = j0; j < j0 + jb; ++j) {
-            AMx a{-1.0, 0x7fffffff};
-            for (int i = j + tid; i < n; i += 256) a = amx_better(a, AMx{(double)abs2(A[i + (int64_t)j * lda]), i});
-            for (int off = 32; off > 0; off >>= 1) {
-                AMx o{__shfl_xor(a.v, off), __shfl_xor(a.i, off)};
-                a = amx_better(a, o);
-            }
-            __syncthreads();
-            if ((tid & 63) == 0) sh[tid >> 6] = a;
-            __syncthreads();
-            a = sh[0];
-            for (int w = 1; w < 4; ++w) a = amx_better(a, sh[w]);
-            const int p = a.i;
-            if (tid == 0) D.piv[j] = p;
-            if (a.v <= 0.0 && first_zero == 0) first_zero = j + 1;
-            if (p != j)
-                for (int c = j0 + tid; c < j0 + jb; c += 256) {
-                    const cplx<T> t = A[j + (int64_t)c * lda];
-                    A[j + (int64_t)c * lda] = A[p + (int64_t)c * lda];
-                    A[p + (int64_t)c * lda] = t;
-                }
-            __syncthreads();
-            const cplx<T> d = A[j + (int64_t)j * lda];
-            if (a.v > 0.0)
-                for (int i = j + 1 + tid; i < n; i += 256) A[i + (int64_t)j * lda] = cdiv(A[i + (int64_t)j * lda], d);
-            __syncthreads();
-            for (int i = j + 1 + tid; i < n; i += 256) {
-                const cplx<T> l = A[i + (int64_t)j * lda];
-                for (int c = j + 1; c < j0 + jb; ++c) {
-                    cplx<T> v = A[i + (int64_t)c * lda];
-                    cfma(v, -l, A[j + (int64_t)c * lda]);
-                    A[i + (int64_t)c * lda] = v;
-                }
-            }
-            __syncthreads();
-        }
-        for (int j = j0; j < j0 + jb; ++j) {
-            const int p = D.piv[j];
-            if (p != j)
-                for (int c = tid; c < n; c += 256) {
-                    if (c >= j0 && c < j0 + jb) continue;
-                    const cplx<T> t = A[j + (int64_t)c * lda];
-                    A[j + (int64_t)c * lda] = A[p + (int64_t)c * lda];
-                    A[p + (int64_t)c * lda] = t;
-                }
-            __syncthreads();
-        }
-        for (int c = j0 + jb + tid; c < n; c += 256) {
-            for (int r = j0 + 1; r < j0 + jb; ++r) {
-                cplx<T> v = A[r + (int64_t)c * lda];
-                for (int t = j0; t < r; ++t) cfma(v, -A[r + (int64_t)t * lda], A[t + (int64_t)c * lda]);
-                A[r + (int64_t)c * lda] = v;
-            }
+        const int jb = min(NB, n - j0), R0 = n - j0, R1 = R0 - jb;
+        for (int e = tid; e < R0 * jb; e += 256) {
+            const int r = e % R0, t = e / R0;
+            PT[t * NMAX + r] = A[j0 + r + (int64_t)(j0 + t) * lda];
         }
         __syncthreads();
-        const int r0 = j0 + jb, R = n - r0;
-        if (R > 0 && R <= RMAX) {
-            for (int e = tid; e < jb * R; e += 256) {
-                const int t = e % jb, c = e / jb;
-                su[t][c] = A[j0 + t + (int64_t)(r0 + c) * lda];
+        for (int jj = 0; jj < jb; ++jj) {
+            // pivot: the largest |a|^2 in column jj; key = the top 24 bits of
+            // its double (sign, exponent, 12 mantissa bits) above the
+            // complemented row, so one wave maximum picks it (lowest row on
+            // ties)
+            unsigned key = 0u;
+            if (tid >= jj && tid < R0) {
+                const double v = (double)abs2(PT[jj * NMAX + tid]);
+                key = ((unsigned)(__double_as_longlong(v) >> 40) << 8) | (unsigned)(255 - tid);
+            }
+            key = __ockl_wfred_max_u32(key);
+            if ((tid & 63) == 0) wmax[tid >> 6] = key;
+            __syncthreads();
+            const unsigned best = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+            const int p = 255 - (int)(best & 255u);
+            if (tid == 0) spiv[jj] = j0 + p;   // global stores stall a barrier: written per panel
+            if (p != jj && tid < jb) {
+                const cplx<T> x = PT[tid * NMAX + jj];
+                PT[tid * NMAX + jj] = PT[tid * NMAX + p];
+                PT[tid * NMAX + p] = x;
             }
             __syncthreads();
-            for (int64_t e = tid; e < (int64_t)R * R; e += 256) {
-                const int i = (int)(e % R), c = (int)(e / R);
-                cplx<T> v = A[r0 + i + (int64_t)(r0 + c) * lda];
-                for (int t = 0; t < jb; ++t) cfma(v, -A[r0 + i + (int64_t)(j0 + t) * lda], su[t][c]);
-                A[r0 + i + (int64_t)(r0 + c) * lda] = v;
+            const cplx<T> d = PT[jj * NMAX + jj];
+            const bool nz = d.re != (T)0 || d.im != (T)0;
+            if (!nz && first_zero == 0) first_zero = j0 + jj + 1;
+            if (tid > jj && tid < R0 && nz) {
+                const cplx<T> l = cdiv(PT[jj * NMAX + tid], d);
+                cplx<T> pr[NB], my[NB];
+#pragma unroll
+                for (int t = 0; t < NB; ++t)
+                    if (t > jj && t < jb) {
+                        pr[t] = PT[t * NMAX + jj];
+                        my[t] = PT[t * NMAX + tid];
+                    }
+                PT[jj * NMAX + tid] = l;
+#pragma unroll
+                for (int t = 0; t < NB; ++t)
+                    if (t > jj && t < jb) {
+                        cfma(my[t], -l, pr[t]);
+                        PT[t * NMAX + tid] = my[t];
+                    }
             }
-        } else {
-            for (int64_t e = tid; e < (int64_t)R * R; e += 256) {
-                const int i = r0 + (int)(e % R), c = r0 + (int)(e / R);
-                cplx<T> v = A[i + (int64_t)c * lda];
-                for (int t = j0; t < j0 + jb; ++t) cfma(v, -A[i + (int64_t)t * lda], A[t + (int64_t)c * lda]);
-                A[i + (int64_t)c * lda] = v;
+            __syncthreads();
+        }
+        // the panel's swaps as one permutation of the rows they touch: slot q
+        // moves original row src[q] to row aff[q] (src[q] < 0: unused); the
+        // candidates are the panel rows and the first use of each pivot row
+        // below the panel
+        if (tid < 2 * NB) {
+            int o = -1;
+            if (tid < jb) {
+                o = j0 + tid;
+            } else if (tid >= NB && tid - NB < jb) {
+                const int q = tid - NB, r = spiv[q];
+                bool first = r >= j0 + jb;
+                for (int u = 0; u < q; ++u)
+                    if (spiv[u] == r) first = false;
+                if (first) o = r;
+            }
+            int pos = o;
+            if (o >= 0)
+                for (int u = 0; u < jb; ++u) {
+                    const int ra = j0 + u, rb = spiv[u];
+                    if (pos == ra) pos = rb;
+                    else if (pos == rb) pos = ra;
+                }
+            src[tid] = o;
+            aff[tid] = pos;
+        }
+        for (int e = tid; e < R0 * jb; e += 256) {
+            const int r = e % R0, t = e / R0;
+            A[j0 + r + (int64_t)(j0 + t) * lda] = PT[t * NMAX + r];
+        }
+        if (tid < jb) D.piv[j0 + tid] = spiv[tid];
+        __syncthreads();
+        for (int c = tid; c < n; c += 256) {
+            if (c >= j0 && c < j0 + jb) continue;
+            cplx<T> v[2 * NB];
+#pragma unroll
+            for (int q = 0; q < 2 * NB; ++q)
+                if (src[q] >= 0) v[q] = A[src[q] + (int64_t)c * lda];
+#pragma unroll
+            for (int q = 0; q < 2 * NB; ++q)
+                if (src[q] >= 0) A[aff[q] + (int64_t)c * lda] = v[q];
+        }
+        __syncthreads();
+        // U12 := L11^{-1} A12, one column per thread
+        if (tid < R1) {
+            const int c = j0 + jb + tid;
+            cplx<T> v[NB];
+#pragma unroll
+            for (int t = 0; t < NB; ++t)
+                if (t < jb) v[t] = A[j0 + t + (int64_t)c * lda];
+#pragma unroll
+            for (int t = 1; t < NB; ++t)
+#pragma unroll
+                for (int u = 0; u < t; ++u)
+                    if (t < jb) cfma(v[t], -PT[u * NMAX + t], v[u]);
+#pragma unroll
+            for (int t = 0; t < NB; ++t)
+                if (t < jb) {
+                    S[t * NMAX + tid] = v[t];
+                    A[j0 + t + (int64_t)c * lda] = v[t];
+                }
+        }
+        __syncthreads();
+        // A22 -= L21 U12 on the matrix cores: 16 x 16 tiles, operands from
+        // LDS, each wave updating 4 tiles at a time (their loads in flight
+        // together)
+        {
+            typedef typename Mfma<T>::v4 v4;
+            const int lane = tid & 63, wave = tid >> 6, g = lane >> 4, cl = lane & 15;
+            const int nt = (R1 + 15) / 16, ntt = nt * nt;
+            for (int tb = 4 * wave; tb < ntt; tb += 16) {
+                cplx<T> cv[4][4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int tile = tb + q, r0 = 16 * (tile % nt), col = 16 * (tile / nt) + cl;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = r0 + Mfma<T>::row(g, v);
+                        cv[q][v] = (tile < ntt && row < R1 && col < R1)
+                                       ? A[j0 + jb + row + (int64_t)(j0 + jb + col) * lda]
+                                       : bz<T>();
+                    }
+                }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    const int tile = tb + q;
+                    if (tile >= ntt) break;
+                    const int r0 = 16 * (tile % nt), c0 = 16 * (tile / nt), col = c0 + cl;
+                    v4 cr, ci;
+                    for (int v = 0; v < 4; ++v) { cr[v] = (T)0; ci[v] = (T)0; }
+#pragma unroll
+                    for (int k0 = 0; k0 < NB; k0 += 4) {
+                        const int kk = k0 + g;
+                        const cplx<T> x = (kk < jb && r0 + cl < R1) ? PT[kk * NMAX + jb + r0 + cl] : bz<T>();
+                        const cplx<T> y = (kk < jb && col < R1) ? S[kk * NMAX + col] : bz<T>();
+                        cr = Mfma<T>::op(x.re, y.re, cr);
+                        cr = Mfma<T>::op(-x.im, y.im, cr);
+                        ci = Mfma<T>::op(x.re, y.im, ci);
+                        ci = Mfma<T>::op(x.im, y.re, ci);
+                    }
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int row = r0 + Mfma<T>::row(g, v);
+                        if (row < R1 && col < R1)
+                            A[j0 + jb + row + (int64_t)(j0 + jb + col) * lda] =
+                                cplx<T>{cv[q][v].re - cr[v], cv[q][v].im - ci[v]};
+                    }
+                }
             }
         }
         __syncthreads();
     }
     if (tid == 0) D.info[0] = first_zero;
-    // inverses
+}
+
+// Explicit inverses of a factored leaf, one work-group per column chunk:
+// blockIdx.y = 0: chunk of UI = U^{-1} (column c is zero below row c);
+// blockIdx.y = 1: chunk of LP = L^{-1} P (column j of L^{-1}, zero above
+// row j, goes to column perm[j], perm = the row swaps applied to 0..n-1).
+// The chunk is held row-major in LDS and built by block substitution over
+// 16-row blocks: an update of all chunk columns by the finished blocks,
+// then a 16 x 16 triangular solve per column; the 16 rows of the triangle
+// in use are staged in LDS.
+template <typename T, int CH>
+__global__ __launch_bounds__(256) void k_leaf_inv(const LeafDesc<T>* __restrict__ descs, int nd) {
+    constexpr int NMAX = 256;
+    __shared__ cplx<T> X[NMAX * CH];   // X[i * CH + cc]
+    __shared__ cplx<T> B[16 * NMAX];   // B[r * NMAX + k]
+    __shared__ int perm[NMAX];
+    const int leaf = (int)blockIdx.x / (NMAX / CH), chunk = (int)blockIdx.x % (NMAX / CH);
+    if (leaf >= nd) return;
+    const LeafDesc<T> D = descs[leaf];
+    const int n = D.n, lda = D.lda, c0 = chunk * CH;
+    if (c0 >= n) return;
+    const cplx<T>* A = D.A;
+    const int tid = threadIdx.x, cw = min(CH, n - c0);
+    for (int e = tid; e < n * CH; e += 256) X[e] = bz<T>();
+    if (blockIdx.y == 0) {
+        const int rows = min(n, c0 + cw);
+        for (int I = (rows - 1) / 16; I >= 0; --I) {
+            const int i0 = 16 * I, i1 = min(i0 + 16, rows);
+            __syncthreads();
+            for (int e = tid; e < 16 * (rows - i0); e += 256) {
+                const int r = e % 16, k = i0 + e / 16;
+                if (i0 + r < i1) B[r * NMAX + k] = A[i0 + r + (int64_t)k * lda];
+            }
+            __syncthreads();
+            for (int e = tid; e < 16 * CH; e += 256) {
+                const int r = e / CH, cc = e % CH, i = i0 + r;
+                if (i >= i1 || cc >= cw) continue;
+                cplx<T> v = cplx<T>{(T)(i == c0 + cc ? 1 : 0), (T)0};
+                for (int k = i1; k < rows; ++k) cfma(v, -B[r * NMAX + k], X[k * CH + cc]);
+                X[i * CH + cc] = v;
+            }
+            __syncthreads();
+            if (tid < cw) {
+                for (int i = i1 - 1; i >= i0; --i) {
+                    const int r = i - i0;
+                    cplx<T> v = X[i * CH + tid];
+                    for (int k = i + 1; k < i1; ++k) cfma(v, -B[r * NMAX + k], X[k * CH + tid]);
+                    X[i * CH + tid] = cdiv(v, B[r * NMAX + i]);
+                }
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < n * cw; e += 256) {
+            const int i = e % n, cc = e / n;
+            D.UI[i + (int64_t)(c0 + cc) * n] = X[i * CH + cc];
+        }
+        return;
+    }
     if (tid == 0) {
         for (int i = 0; i < n; ++i) perm[i] = i;
         for (int j = 0; j < n; ++j) {
             const int p = D.piv[j];
-            const int t = perm[j]; perm[j] = perm[p]; perm[p] = t;
+            const int t = perm[j];
+            perm[j] = perm[p];
+            perm[p] = t;
+        }
+    }
+    const int nblk = (n + 15) / 16;
+    for (int I = c0 / 16; I < nblk; ++I) {
+        const int i0 = 16 * I, i1 = min(i0 + 16, n);
+        __syncthreads();
+        for (int e = tid; e < 16 * (i1 - c0); e += 256) {
+            const int r = e % 16, k = c0 + e / 16;
+            if (i0 + r < i1) B[r * NMAX + k] = A[i0 + r + (int64_t)k * lda];
+        }
+        __syncthreads();
+        for (int e = tid; e < 16 * CH; e += 256) {
+            const int r = e / CH, cc = e % CH, i = i0 + r;
+            if (i >= i1 || cc >= cw) continue;
+            cplx<T> v = cplx<T>{(T)(i == c0 + cc ? 1 : 0), (T)0};
+            for (int k = c0; k < i0; ++k) cfma(v, -B[r * NMAX + k], X[k * CH + cc]);
+            X[i * CH + cc] = v;
+        }
+        __syncthreads();
+        if (tid < cw) {
+            for (int i = i0 + 1; i < i1; ++i) {
+                const int r = i - i0;
+                cplx<T> v = X[i * CH + tid];
+                for (int k = i0; k < i; ++k) cfma(v, -B[r * NMAX + k], X[k * CH + tid]);
+                X[i * CH + tid] = v;
+            }
         }
     }
     __syncthreads();
-    for (int c = tid; c < n; c += 256) {
-        int sidx = 0;
-        for (int i = 0; i < n; ++i)
-            if (perm[i] == c) sidx = i;
-        cplx<T>* x = D.LP + (int64_t)c * n;
-        for (int i = 0; i < n; ++i) {
-            cplx<T> v = cplx<T>{(T)(i == sidx ? 1 : 0), (T)0};
-            for (int t = sidx; t < i; ++t) cfma(v, -A[i + (int64_t)t * lda], x[t]);
-            x[i] = (i < sidx) ? bz<T>() : v;
-        }
-        cplx<T>* y = D.UI + (int64_t)c * n;
-        for (int i = n - 1; i >= 0; --i) {
-            cplx<T> v = cplx<T>{(T)(i == c ? 1 : 0), (T)0};
-            for (int t = i + 1; t <= c; ++t) cfma(v, -A[i + (int64_t)t * lda], y[t]);
-            y[i] = (i > c) ? bz<T>() : cdiv(v, A[i + (int64_t)i * lda]);
-        }
+    for (int e = tid; e < n * cw; e += 256) {
+        const int i = e % n, cc = e / n;
+        D.LP[i + (int64_t)perm[c0 + cc] * n] = X[i * CH + cc];
     }
 }
 
 template <typename T>
-void leaf_batched(hipStream_t s, const LeafDesc<T>* d_desc, int nd) {
-    if (nd <= 0) return;
-    k_leaf<T><<<nd, 256, 0, s>>>(d_desc, nd);
-    check_launch("k_leaf");
+void leaf_batched(hipStream_t s, const LeafDesc<T>* d_desc, int n) {
+    if (n <= 0) return;
+    constexpr int CH = sizeof(T) == 4 ? 32 : 16;
+    k_leaf_lu<T><<<n, 256, 0, s>>>(d_desc, n);
+    check_launch("k_leaf_lu");
+    k_leaf_inv<T, CH><<<dim3(n * (256 / CH), 2), 256, 0, s>>>(d_desc, n);
+    check_launch("k_leaf_inv");
 }
 
 // --------------------------------------------------------------- random
@@ -347,6 +535,89 @@ void rand_batched(hipStream_t s, const RandDesc<T>* d_desc, int n) {
 }
 
 // ------------------------------------------------------ pivoted Cholesky
+// LDS path (p <= PL): the Gram matrix is copied to LDS and factored
+// there; pivoting permutes logical indices (perm) instead of moving data;
+// pivots are chosen by one wave maximum of packed keys.  R^{-1} is then
+// formed one column per wave: back substitution with lane-parallel sums.
+template <typename T> struct PcholLds {
+    static constexpr int PL = sizeof(T) == 4 ? 128 : 90;
+};
+template <typename T>
+__device__ void pchol_lds(const PcholDesc<T>& D, cplx<T>* G, int* perm, unsigned* wmax, double* red,
+                          cplx<T>* xs) {
+    const int p = D.p, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    for (int e = tid; e < p * p; e += 256) G[e] = D.G[e];
+    for (int i = tid; i < p; i += 256) perm[i] = i;
+    double m0 = 0.0;
+    for (int i = tid; i < p; i += 256) m0 = fmax(m0, (double)D.G[i + (int64_t)i * p].re);
+    for (int off = 32; off > 0; off >>= 1) m0 = fmax(m0, __shfl_xor(m0, off));
+    if (lane == 0) red[wave] = m0;
+    __syncthreads();
+    const double dmax0 = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+    int k = p;
+    for (int j = 0; j < p; ++j) {
+        unsigned key = 0u;
+        for (int t = j + tid; t < p; t += 256) {
+            const double v = fmax((double)G[perm[t] * (p + 1)].re, 0.0);
+            key = max(key, ((unsigned)(__double_as_longlong(v) >> 40) << 8) | (unsigned)(255 - t));
+        }
+        key = __ockl_wfred_max_u32(key);
+        if (lane == 0) wmax[wave] = key;
+        __syncthreads();
+        const unsigned best = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
+        const int bi = 255 - (int)(best & 255u);
+        const int pj = perm[bi], pjo = perm[j];
+        const double bv = (double)G[pj * (p + 1)].re;
+        if (!(bv > D.thr * dmax0) || bv <= 0.0) {
+            k = j;
+            break;
+        }
+        __syncthreads();   // every thread has read perm[j] and perm[bi]
+        if (tid == 0) {
+            perm[bi] = pjo;
+            perm[j] = pj;
+        }
+        const T rjj = sqrt((T)bv);
+        // row j of R (logical), stored in place; thread 0 changes only
+        // perm[j] and perm[bi], so logical t > j maps to q below
+        for (int t = j + 1 + tid; t < p; t += 256) {
+            const int q = bi == t ? pjo : perm[t];
+            G[pj + q * p] = (T(1) / rjj) * G[pj + q * p];
+        }
+        if (tid == 0) G[pj * (p + 1)] = cplx<T>{rjj, (T)0};
+        __syncthreads();
+        const int R = p - j - 1;
+        for (int e = tid; e < R * R; e += 256) {
+            const int pt = perm[j + 1 + e % R], pu = perm[j + 1 + e / R];
+            cfma(G[pt + pu * p], -conj(G[pj + pt * p]), G[pj + pu * p]);
+        }
+        __syncthreads();
+    }
+    // S = Pi R^{-1}: column j of R^{-1} solves R x = e_j (x zero below j)
+    cplx<T>* x = xs + wave * PcholLds<T>::PL;
+    for (int e = tid; e < p * p; e += 256) D.S[e] = bz<T>();
+    __syncthreads();
+    for (int j = wave; j < k; j += 4) {
+        for (int t = j; t >= 0; --t) {
+            cplx<T> acc = bz<T>();
+            const int pt = perm[t];
+            for (int u = t + 1 + lane; u <= j; u += 64) cfma(acc, G[pt + perm[u] * p], x[u]);
+            for (int off = 32; off > 0; off >>= 1) {
+                acc.re += __shfl_xor(acc.re, off);
+                acc.im += __shfl_xor(acc.im, off);
+            }
+            const cplx<T> num = cplx<T>{(T)(t == j ? 1 : 0), (T)0} - acc;
+            const cplx<T> xt = cdiv(num, G[pt * (p + 1)]);
+            if (lane == 0) x[t] = xt;
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        }
+        for (int t = lane; t <= j; t += 64) D.S[perm[t] + (int64_t)j * p] = x[t];
+        __builtin_amdgcn_wave_barrier();
+    }
+    if (tid == 0) D.k_out[0] = k;
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_pchol_b(const PcholDesc<T>* __restrict__ descs, int nd) {
     if ((int)blockIdx.x >= nd) return;
@@ -354,6 +625,17 @@ __global__ __launch_bounds__(256) void k_pchol_b(const PcholDesc<T>* __restrict_
     const int p = D.p;
     cplx<T>* G = D.G;
     __shared__ int perm[512];
+    {
+        constexpr int PL = PcholLds<T>::PL;
+        __shared__ cplx<T> Gl[PL * PL];
+        __shared__ cplx<T> xs[4 * PL];
+        __shared__ unsigned wmax[4];
+        __shared__ double red[4];
+        if (p <= PL) {
+            pchol_lds<T>(D, Gl, perm, wmax, red, xs);
+            return;
+        }
+    }
     __shared__ double dv[4];
     __shared__ int di[4];
     __shared__ double dmax0;
@@ -597,6 +879,7 @@ void eig_batched(hipStream_t s, const EigDesc<T>* d_desc, int n) {
 #define CBIE_BATCH_INST(T)                                                                    \
     template void gemm_batched<T>(hipStream_t, const GemmDesc<T>*, const GemmTile*, int, int); \
     template void copy_batched<T>(hipStream_t, const CopyDesc<T>*, const CopyTile*, int);      \
+    template void reduce_batched<T>(hipStream_t, const ReduceDesc<T>*, const CopyTile*, int);  \
     template void leaf_batched<T>(hipStream_t, const LeafDesc<T>*, int);                       \
     template void rand_batched<T>(hipStream_t, const RandDesc<T>*, int);                       \
     template void pchol_batched<T>(hipStream_t, const PcholDesc<T>*, int);                     \

@@ -36,6 +36,18 @@ struct CopyTile {
     int desc, e0;            // element chunk start
 };
 
+// Second phase of a split-k product: C = alpha sum_s W_s + beta C, where
+// W_s (m x n, leading dimension m, stored one after another) are the
+// partial products over consecutive k ranges.  Tiles are CopyTile chunks.
+template <typename T> struct ReduceDesc {
+    int m, n, nsplit, ldc;
+    cplx<T> alpha, beta;
+    const cplx<T>* W;
+    cplx<T>* C;
+};
+template <typename T>
+void reduce_batched(hipStream_t s, const ReduceDesc<T>* d_desc, const CopyTile* d_tiles, int ntiles);
+
 // LU with partial pivoting of a diagonal leaf followed by the explicit
 // inverses LP = L^{-1} P and UI = U^{-1} (n x n each, leading dimension n)
 template <typename T> struct LeafDesc {

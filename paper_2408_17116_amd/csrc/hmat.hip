@@ -62,6 +62,48 @@ template <typename T> struct Arena {
     }
 };
 
+// Device storage of the factors: power-of-two size classes (at least 4096
+// elements) carved from a bump arena, with free lists.  A released buffer
+// may still be read or written by tasks recorded before its release, so it
+// is reused only after the stream has completed them: released while a
+// program is being recorded -> waiting for that program's launch ->
+// free once the stream has been synchronized after the launch.
+template <typename T> struct Pool {
+    Arena<T> bump;
+    std::vector<std::vector<cplx<T>*>> free_cls = std::vector<std::vector<cplx<T>*>>(64);
+    std::vector<std::pair<cplx<T>*, int>> rec, run;
+    size_t live = 0;
+    static int cls(size_t n) {
+        int c = 12;
+        while (((size_t)1 << c) < n) ++c;
+        return c;
+    }
+    cplx<T>* alloc(size_t n) {
+        const int c = cls(n);
+        live += (size_t)1 << c;
+        if (!free_cls[c].empty()) {
+            cplx<T>* p = free_cls[c].back();
+            free_cls[c].pop_back();
+            return p;
+        }
+        return bump.alloc((size_t)1 << c);
+    }
+    // n: the size passed to alloc
+    void release(cplx<T>* p, size_t n) {
+        if (!p) return;
+        rec.push_back({p, cls(n)});
+        live -= (size_t)1 << cls(n);
+    }
+    void launched() {
+        run.insert(run.end(), rec.begin(), rec.end());
+        rec.clear();
+    }
+    void completed() {
+        for (auto& x : run) free_cls[x.second].push_back(x.first);
+        run.clear();
+    }
+};
+
 // Memory a task touches, for dependency tracking: an owner and the
 // rectangle of rows x columns touched, in the owner's own coordinates.
 constexpr int64_t kAll = int64_t(1) << 40;
@@ -107,12 +149,14 @@ template <typename T> struct HF {
     // > 0 while an update holds views of the block's factors or dense part:
     // a recompression triggered meanwhile leaves the block as it is
     std::vector<int> lr_busy;
-    Arena<T> arena, scratch, rscratch;
+    Pool<T> store;            // factors and dense accumulators of the low-rank blocks
+    Arena<T> scratch, rscratch;
     int pin = 0;               // > 0: recorded temporaries are still referenced
     DBuf<AcaProdJob<T>> jobbuf;
     int64_t launches = 0;
     double flops = 0.0;
-    int kmax = 768;            // accumulated width that triggers recompression
+    // accumulated width that triggers recompression (tuning: CBIE_KMAX)
+    int kmax = getenv("CBIE_KMAX") ? std::max(64, atoi(getenv("CBIE_KMAX"))) : 3072;
     bool debug = getenv("CBIE_DEBUG") != nullptr;
     bool audit = getenv("CBIE_CHECK_DEPS") != nullptr;
     int64_t audit_conflicts = 0;
@@ -141,8 +185,18 @@ template <typename T> struct HF {
 
     HF(Ctx& cc, double t) : c(cc), s(cc.stream), T_(cc.tree), tol(t) {}
     ~HF() {
+        if (rank_pinned) (void)hipHostFree(rank_pinned);
         if (pinned) (void)hipHostFree(pinned);
         if (imm_pinned) (void)hipHostFree(imm_pinned);
+    }
+
+    // host time spent waiting for the stream (debug statistics)
+    double t_wait = 0.0;
+    void wait_stream() {
+        const double t0 = now_s();
+        CBIE_HIP(hipStreamSynchronize(s));
+        t_wait += now_s() - t0;
+        store.completed();
     }
 
     static int64_t key(const Res& r) { return ((int64_t)r.kind << 40) | (int64_t)(uint32_t)r.id; }
@@ -154,22 +208,38 @@ template <typename T> struct HF {
     // writes for reads and writes of overlapping rectangles.  (Accumulations
     // into one rectangle are ordered like writes: the results do not depend
     // on the schedule.)
+    double t_level = 0.0, t_exec = 0.0, t_recomp = 0.0;
+    int64_t n_level_calls = 0, n_scanned = 0;
     int level_of(const std::vector<Res>& rd, const std::vector<Res>& wr) {
+        const double t0 = debug ? now_s() : 0.0;
+        ++n_level_calls;
         int lv = 0;
         for (const Res& x : rd) {
             auto it = st.find(key(x));
             if (it == st.end()) continue;
+            n_scanned += (int64_t)it->second.size();
             for (const Ent& e : it->second)
                 if (overlap(e, x)) lv = std::max(lv, e.w + 1);
         }
         for (const Res& x : wr) {
             auto it = st.find(key(x));
             if (it == st.end()) continue;
+            n_scanned += (int64_t)it->second.size();
             for (const Ent& e : it->second)
                 if (overlap(e, x)) lv = std::max(lv, std::max(e.w, e.r) + 1);
         }
         auto note = [&](const Res& x, int mode) {
             std::vector<Ent>& v = st[key(x)];
+            if (mode == 1) {
+                // a write at lv follows every access to the rectangles it
+                // covers: their entries can no longer constrain anything
+                size_t w = 0;
+                for (size_t q = 0; q < v.size(); ++q) {
+                    const Ent& y = v[q];
+                    if (!(x.r0 <= y.r0 && y.r1 <= x.r1 && x.c0 <= y.c0 && y.c1 <= x.c1)) v[w++] = y;
+                }
+                v.resize(w);
+            }
             Ent* e = nullptr;
             for (Ent& y : v)
                 if (y.r0 == x.r0 && y.r1 == x.r1 && y.c0 == x.c0 && y.c1 == x.c1) { e = &y; break; }
@@ -183,6 +253,7 @@ template <typename T> struct HF {
         for (const Res& x : rd) note(x, 0);
         for (const Res& x : wr) note(x, 1);
         max_level = std::max(max_level, lv);
+        if (debug) t_level += now_s() - t0;
         return lv;
     }
     Res temp() { return Res{RES_TEMP, next_temp++}; }
@@ -217,6 +288,7 @@ template <typename T> struct HF {
     }
     void rec_leaf(int leaf) {
         const DenseBlockDev& db = c.dblk[leaf];
+        CBIE_REQUIRE(db.ld <= 256, CBIE_EINVAL, "diagonal leaf above 256 unknowns: use leaf_size <= 256");
         cplx<T>* LP = inv.p + inv_off[leaf];
         ld.push_back(LeafDesc<T>{db.ld, db.ld, dense.p + db.offset, piv.p + piv_off[leaf], info.p + leaf, LP,
                                  LP + (int64_t)db.ld * db.ld});
@@ -241,6 +313,57 @@ template <typename T> struct HF {
         for (int m0 = 0; m0 < d.m; m0 += tile_rows(sh))
             for (int n0 = 0; n0 < d.n; n0 += tile_cols(sh)) t.push_back(GemmTile{di, m0, n0, 0});
     }
+    // Long inner dimension and few output tiles: the k range is split over
+    // several work-groups that write partial products to a workspace, and a
+    // reduction launch forms C (deterministic; no atomics).
+    static int nsplit(const GemmDesc<T>& d, int sh) {
+        if (d.k < 768) return 1;
+        const int64_t tiles = (int64_t)((d.m + tile_rows(sh) - 1) / tile_rows(sh)) *
+                              ((d.n + tile_cols(sh) - 1) / tile_cols(sh));
+        if (tiles >= 128) return 1;
+        const int64_t cap = std::max<int64_t>(1, (int64_t(1) << 22) / ((int64_t)d.m * d.n));   // <= 4M partial entries
+        return (int)std::min<int64_t>({(d.k + 255) / 256, 32, cap});
+    }
+    // the GEMMs of one launch per tile shape, plus the split-k reductions
+    struct Batch {
+        std::vector<GemmDesc<T>> g[3];
+        std::vector<GemmTile> t[3];
+        double fl[3] = {0.0, 0.0, 0.0};
+        std::vector<ReduceDesc<T>> rd;
+        std::vector<CopyTile> rt;
+    };
+    void add_gemm(Batch& b, const GemmDesc<T>& d, int sh, Arena<T>& ws) {
+        b.fl[sh] += 8.0 * d.m * d.n * d.k;
+        const int S = nsplit(d, sh);
+        if (S <= 1) {
+            add_tiles(b.t[sh], (int)b.g[sh].size(), d, sh);
+            b.g[sh].push_back(d);
+            return;
+        }
+        const int64_t mn = (int64_t)d.m * d.n;
+        cplx<T>* W = ws.alloc((size_t)(mn * S));
+        const int kc = (d.k + S - 1) / S;
+        for (int q = 0; q < S; ++q) {
+            const int k0 = q * kc, k1 = std::min(d.k, k0 + kc);
+            CBIE_REQUIRE(k1 > k0, -7, "empty split-k range");
+            GemmDesc<T> e = d;
+            e.k = k1 - k0;
+            e.A = d.ta == 0 ? d.A + (int64_t)k0 * d.lda : d.A + k0;
+            e.B = d.tb == 0 ? d.B + k0 : d.B + (int64_t)k0 * d.ldb;
+            e.alpha = one();
+            e.beta = zero();
+            e.C = W + q * mn;
+            e.ldc = d.m;
+            add_tiles(b.t[sh], (int)b.g[sh].size(), e, sh);
+            b.g[sh].push_back(e);
+        }
+        const int ri = (int)b.rd.size();
+        b.rd.push_back(ReduceDesc<T>{d.m, d.n, S, d.ldc, d.alpha, d.beta, W, d.C});
+        for (int64_t e0 = 0; e0 < mn; e0 += kCopyChunk) b.rt.push_back(CopyTile{ri, (int)e0});
+    }
+    Arena<T> wsp[2];   // split-k workspaces of the recorded programs (alternating)
+    int wsp_cur = 0;
+
     // one batched GEMM launch of algorithmic flops fl, timed when profiling
     void launch_gemm(const GemmDesc<T>* d, const GemmTile* t, int ntiles, int sh, double fl) {
         Ctx::KernelTimer& tm = c.gemm_timer;
@@ -327,6 +450,11 @@ template <typename T> struct HF {
 
     // run everything recorded so far, level by level
     void execute() {
+        const double t0 = now_s(), w0 = t_wait;
+        execute_();
+        t_exec += now_s() - t0 - (t_wait - w0);
+    }
+    void execute_() {
         if (max_level < 0) {
             if (pin == 0) scratch.reset();
             return;
@@ -339,10 +467,15 @@ template <typename T> struct HF {
         // one pinned staging buffer: per level and tile shape [gemm descs][gemm
         // tiles], then [copy descs][copy tiles][leaf descs]
         struct Seg {
-            size_t g[3], gt[3], c, ct, l;
-            int ng[3], ngt[3], nc, nct, nl;
+            size_t g[3], gt[3], r, rt, c, ct, l;
+            int ng[3], ngt[3], nr, nrt, nc, nct, nl;
             double fl[3];
         };
+        // the program that last used this workspace finished before the
+        // previous program was staged
+        wsp_cur ^= 1;
+        Arena<T>& ws = wsp[wsp_cur];
+        ws.reset();
         std::vector<Seg> seg(L);
         std::vector<char> host;
         auto put = [&](const void* src, size_t bytes) {
@@ -353,24 +486,22 @@ template <typename T> struct HF {
         };
         for (int lv = 0; lv < L; ++lv) {
             Seg& sg = seg[lv];
-            for (int sh = 0; sh < 3; ++sh) {
-                std::vector<GemmDesc<T>> g;
-                std::vector<GemmTile> gt;
-                sg.fl[sh] = 0.0;
-                for (int i : gl[lv]) {
-                    const GemmDesc<T>& d = gd[i];
-                    const int shi = gshape[i] >= 0 ? gshape[i] : pick_shape(d.m, d.n);
-                    if (shi != sh) continue;
-                    const int di = (int)g.size();
-                    g.push_back(d);
-                    add_tiles(gt, di, d, sh);
-                    sg.fl[sh] += 8.0 * d.m * d.n * d.k;
-                }
-                sg.g[sh] = put(g.data(), g.size() * sizeof(GemmDesc<T>));
-                sg.gt[sh] = put(gt.data(), gt.size() * sizeof(GemmTile));
-                sg.ng[sh] = (int)g.size();
-                sg.ngt[sh] = (int)gt.size();
+            Batch bt;
+            for (int i : gl[lv]) {
+                const GemmDesc<T>& d = gd[i];
+                add_gemm(bt, d, gshape[i] >= 0 ? gshape[i] : pick_shape(d.m, d.n), ws);
             }
+            for (int sh = 0; sh < 3; ++sh) {
+                sg.g[sh] = put(bt.g[sh].data(), bt.g[sh].size() * sizeof(GemmDesc<T>));
+                sg.gt[sh] = put(bt.t[sh].data(), bt.t[sh].size() * sizeof(GemmTile));
+                sg.ng[sh] = (int)bt.g[sh].size();
+                sg.ngt[sh] = (int)bt.t[sh].size();
+                sg.fl[sh] = bt.fl[sh];
+            }
+            sg.r = put(bt.rd.data(), bt.rd.size() * sizeof(ReduceDesc<T>));
+            sg.rt = put(bt.rt.data(), bt.rt.size() * sizeof(CopyTile));
+            sg.nr = (int)bt.rd.size();
+            sg.nrt = (int)bt.rt.size();
             std::vector<CopyDesc<T>> cc;
             std::vector<CopyTile> ct;
             for (int i : cl[lv]) {
@@ -394,7 +525,7 @@ template <typename T> struct HF {
             CBIE_HIP(hipHostMalloc(&pinned, pinned_bytes));
         }
         // the previous use of the staging buffers must be complete
-        CBIE_HIP(hipStreamSynchronize(s));
+        wait_stream();
         std::memcpy(pinned, host.data(), host.size());
         DBuf<char>& dev = descbuf;
         if (dev.n < host.size()) dev.alloc(std::max(host.size(), (size_t)1 << 20));
@@ -406,12 +537,17 @@ template <typename T> struct HF {
                 if (sg.ngt[sh])
                     launch_gemm((const GemmDesc<T>*)(dev.p + sg.g[sh]), (const GemmTile*)(dev.p + sg.gt[sh]),
                                 sg.ngt[sh], sh, sg.fl[sh]);
+            if (sg.nrt) {
+                reduce_batched<T>(s, (const ReduceDesc<T>*)(dev.p + sg.r), (const CopyTile*)(dev.p + sg.rt), sg.nrt);
+                ++launches;
+            }
             if (sg.nct) {
                 copy_batched<T>(s, (const CopyDesc<T>*)(dev.p + sg.c), (const CopyTile*)(dev.p + sg.ct), sg.nct);
                 ++launches;
             }
         }
         levels_run += L;
+        store.launched();
         gd.clear(); glev.clear(); gshape.clear(); gseq.clear();
         cd.clear(); clev.clear(); ld.clear(); llev.clear(); cseq.clear(); lseq.clear();
         st.clear();
@@ -443,7 +579,7 @@ template <typename T> struct HF {
         return (const D*)(imm_dev.p + off);
     }
     void imm_begin(size_t bytes) {
-        CBIE_HIP(hipStreamSynchronize(s));   // earlier uploads from the pinned buffer are done
+        wait_stream();   // earlier uploads from the pinned buffer are done
         if (bytes > imm_pinned_bytes) {
             if (imm_pinned) CBIE_HIP(hipHostFree(imm_pinned));
             imm_pinned_bytes = std::max(bytes, 2 * imm_pinned_bytes);
@@ -452,23 +588,24 @@ template <typename T> struct HF {
         }
         imm_off = 0;
     }
+    // independent products, split-k workspaces from the recompression's
+    // scratch (valid until its round ends)
     void run_gemms(const std::vector<GemmDesc<T>>& g) {
         if (g.empty()) return;
+        Batch bt;
+        for (const GemmDesc<T>& d : g) add_gemm(bt, d, pick_shape(d.m, d.n), rscratch);
         for (int sh = 0; sh < 3; ++sh) {
-            std::vector<GemmDesc<T>> gs;
-            std::vector<GemmTile> tiles;
-            double fl = 0.0;
-            for (size_t i = 0; i < g.size(); ++i) {
-                if (pick_shape(g[i].m, g[i].n) != sh) continue;
-                fl += 8.0 * g[i].m * g[i].n * g[i].k;
-                add_tiles(tiles, (int)gs.size(), g[i], sh);
-                gs.push_back(g[i]);
-            }
-            if (tiles.empty()) continue;
-            flops += fl;
-            const GemmDesc<T>* dg = stage_upload(gs);
-            const GemmTile* dt = stage_upload(tiles);
-            launch_gemm(dg, dt, (int)tiles.size(), sh, fl);
+            if (bt.t[sh].empty()) continue;
+            flops += bt.fl[sh];
+            const GemmDesc<T>* dg = stage_upload(bt.g[sh]);
+            const GemmTile* dt = stage_upload(bt.t[sh]);
+            launch_gemm(dg, dt, (int)bt.t[sh].size(), sh, bt.fl[sh]);
+        }
+        if (!bt.rt.empty()) {
+            const ReduceDesc<T>* dr = stage_upload(bt.rd);
+            const CopyTile* dt = stage_upload(bt.rt);
+            reduce_batched<T>(s, dr, dt, (int)bt.rt.size());
+            ++launches;
         }
     }
     void run_copies(const std::vector<CopyDesc<T>>& c2) {
@@ -492,6 +629,11 @@ template <typename T> struct HF {
     // block is redone with twice the sample size.  Every product is a
     // batched GEMM over the whole GPU.
     void recompress(std::vector<int> todo) {
+        const double t0 = now_s(), w0 = t_wait;
+        recompress_(std::move(todo));
+        t_recomp += now_s() - t0 - (t_wait - w0);
+    }
+    void recompress_(std::vector<int> todo) {
         std::vector<int> pq(todo.size());
         for (size_t q = 0; q < todo.size(); ++q) {
             const LR& L = lr[todo[q]];
@@ -583,10 +725,15 @@ template <typename T> struct HF {
             aca_product_batched<T>(s, (int)aj.size(), stage_upload(aj), tol);
             ++launches;
             run_gemms(h4);
-            std::vector<int> r(nb), kq(nb);
-            CBIE_HIP(hipMemcpyAsync(r.data(), ints, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
-            CBIE_HIP(hipMemcpyAsync(kq.data(), ks, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
-            CBIE_HIP(hipStreamSynchronize(s));
+            if (rank_pinned_n < 2 * nb) {
+                if (rank_pinned) CBIE_HIP(hipHostFree(rank_pinned));
+                rank_pinned_n = std::max<size_t>(2 * nb, 2 * rank_pinned_n);
+                CBIE_HIP(hipHostMalloc((void**)&rank_pinned, sizeof(int) * rank_pinned_n));
+            }
+            CBIE_HIP(hipMemcpyAsync(rank_pinned, ints, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+            CBIE_HIP(hipMemcpyAsync(rank_pinned + nb, ks, sizeof(int) * nb, hipMemcpyDeviceToHost, s));
+            wait_stream();
+            const std::vector<int> r(rank_pinned, rank_pinned + nb), kq(rank_pinned + nb, rank_pinned + 2 * nb);
             std::vector<int> again, again_p;
             std::vector<CopyDesc<T>> cp;
             for (size_t q = 0; q < nb; ++q) {
@@ -599,11 +746,12 @@ template <typename T> struct HF {
                     continue;
                 }
                 const int rr = r[q];
-                if (rr > L.cap) {
-                    L.cap = rr;
-                    L.U = arena.alloc((size_t)L.m * L.cap);
-                    L.V = arena.alloc((size_t)L.n * L.cap);
-                }
+                // fresh storage sized to the new rank plus room for appends
+                store.release(L.U, (size_t)L.m * L.cap);
+                store.release(L.V, (size_t)L.n * L.cap);
+                L.cap = std::max(rr, 1) + 64;
+                L.U = store.alloc((size_t)L.m * L.cap);
+                L.V = store.alloc((size_t)L.n * L.cap);
                 cp.push_back(CopyDesc<T>{L.m, rr, 0, L.m, L.m, o, tm[q].Uo, L.U});
                 cp.push_back(CopyDesc<T>{L.n, rr, 0, L.n, L.n, o, tm[q].Vb, L.V});
                 if (L.dirty) cp.push_back(CopyDesc<T>{L.m, L.n, 0, L.m, L.m, z, nullptr, L.D});
@@ -611,7 +759,7 @@ template <typename T> struct HF {
                 L.dirty = false;
             }
             run_copies(cp);
-            CBIE_HIP(hipStreamSynchronize(s));
+            wait_stream();
             rscratch.reset();
             todo = again;
             pq = again_p;
@@ -619,6 +767,8 @@ template <typename T> struct HF {
         }
     }
     int64_t recompress_rounds = 0;
+    int* rank_pinned = nullptr;   // rank readback (pinned host memory)
+    size_t rank_pinned_n = 0;
 
     // run the program, then recompress the given low-rank blocks that hold
     // pending columns or a dirty dense accumulator
@@ -645,13 +795,13 @@ template <typename T> struct HF {
         else if (b.type == BLK_HIER)
             for (int k = 0; k < 4; ++k) collect_lr(b.child[k], out);
     }
-    int64_t flushes = 0;
+    int64_t flushes = 0, flush_overflow = 0;
     double width_lr_a = 0, width_lr_b = 0, width_dd = 0, flush_k = 0;
     // the dense accumulator of a block, allocated and cleared on first use
     cplx<T>* dacc(int leaf) {
         LR& L = lr[leaf];
         if (!L.D) {
-            L.D = arena.alloc((size_t)L.m * L.n);
+            L.D = store.alloc((size_t)L.m * L.n);
             rec_copy(0, L.m, L.n, zero(), nullptr, L.m, L.D, L.m, {}, {Res{RES_D, leaf}});
         }
         L.dirty = true;
@@ -764,13 +914,15 @@ template <typename T> struct HF {
         LR& L = lr[leaf];
         if (L.K + k > L.cap) {
             const int nc = std::max(L.K + k, 2 * L.cap);
-            cplx<T>* U = arena.alloc((size_t)L.m * nc);
-            cplx<T>* V = arena.alloc((size_t)L.n * nc);
+            cplx<T>* U = store.alloc((size_t)L.m * nc);
+            cplx<T>* V = store.alloc((size_t)L.n * nc);
             if (L.K > 0) {
                 const Res ru = rect(RES_U, leaf, 0, L.m, 0, L.K), rv = rect(RES_V, leaf, 0, L.n, 0, L.K);
                 rec_copy(0, L.m, L.K, one(), L.U, L.m, U, L.m, {ru}, {ru});
                 rec_copy(0, L.n, L.K, one(), L.V, L.n, V, L.n, {rv}, {rv});
             }
+            store.release(L.U, (size_t)L.m * L.cap);
+            store.release(L.V, (size_t)L.n * L.cap);
             L.U = U;
             L.V = V;
             L.cap = nc;
@@ -806,7 +958,10 @@ template <typename T> struct HF {
             rec_gemm(0, 1, C.m, C.n, k, al, Xp, ldx, Yp, ldy, one(), Cp, ldc, cat({res(X), res(Y)}), res(C));
             return;
         }
-        if (lrb(C).K + k > kmax) flush_all();
+        if (lrb(C).K + k > kmax) {
+            ++flush_overflow;
+            flush_all();
+        }
         const int col = reserve(C, k);
         const int leaf = leaf_of(C);
         LR& Lc = lr[leaf];
@@ -890,7 +1045,10 @@ template <typename T> struct HF {
             for (int pa = 0; pa < (da ? 2 : 1); ++pa)
                 for (int pb = 0; pb < (db ? 2 : 1); ++pb)
                     need += pair_w(pa == 0 ? wa : -1, pb == 0 ? wb : -1);
-            if (lrb(C).K + need > kmax) flush_all();
+            if (lrb(C).K + need > kmax) {
+                ++flush_overflow;
+                flush_all();
+            }
         }
         const bool dirtyA = kind(A) == LRK && lrb(A).dirty, dirtyB = kind(B) == LRK && lrb(B).dirty;
         for (int pa = 0; pa < (dirtyA ? 2 : 1); ++pa)
@@ -1241,8 +1399,8 @@ template <typename T> static std::shared_ptr<HF<T>> make_factor(Ctx& c) {
         L.n = 2 * c.lblk[b].col_nodes;
         L.r = L.K = c.lr.rank[b];
         L.cap = std::max(L.r, 1);
-        L.U = f->arena.alloc((size_t)L.m * L.cap);
-        L.V = f->arena.alloc((size_t)L.n * L.cap);
+        L.U = f->store.alloc((size_t)L.m * L.cap);
+        L.V = f->store.alloc((size_t)L.n * L.cap);
         convert<double, T>(s, (int64_t)L.m * L.r, c.lr.mem.p + c.lr.u_off[b], L.U);
         convert<double, T>(s, (int64_t)L.n * L.r, c.lr.mem.p + c.lr.v_off[b], L.V);
     }
@@ -1280,9 +1438,15 @@ template <typename T> static void run_factor(Ctx& c, HF<T>& f) {
     c.gemm_timer.harvest();
     c.stats.gemm_seconds = c.gemm_timer.seconds;
     if (getenv("CBIE_DEBUG"))
-        fprintf(stderr, "[cbie] levels %lld flushes %lld rounds %lld widths lrA %.0f lrB %.0f dd %.0f flushK %.0f\n",
-                (long long)f.levels_run, (long long)f.flushes, (long long)f.recompress_rounds, f.width_lr_a,
-                f.width_lr_b, f.width_dd, f.flush_k);
+        fprintf(stderr,
+                "[cbie] levels %lld flushes %lld (width overflows %lld) rounds %lld widths lrA %.0f lrB %.0f dd %.0f flushK %.0f; "
+                "host waited %.2f s of %.2f s; host in level_of %.2f s (%lld calls, %lld entries scanned), "
+                "execute %.2f s, recompress %.2f s; factor storage %.2f GB\n",
+                (long long)f.levels_run, (long long)f.flushes, (long long)f.flush_overflow,
+                (long long)f.recompress_rounds, f.width_lr_a,
+                f.width_lr_b, f.width_dd, f.flush_k, f.t_wait, now_s() - f.t_start, f.t_level,
+                (long long)f.n_level_calls, (long long)f.n_scanned, f.t_exec, f.t_recomp,
+                1e-9 * (double)f.store.bump.live * sizeof(cplx<T>));
 }
 
 void stage_factor(Ctx& c, int prec) {

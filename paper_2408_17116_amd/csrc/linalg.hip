@@ -326,6 +326,14 @@ __global__ __launch_bounds__(256) void k_aca_prod(const AcaProdJob<T>* __restric
     __shared__ cplx<T> s_coef[1024];  // U[i, :rank] or V[j, :rank]
     const int tid = threadIdx.x;
     for (int i = tid; i < m; i += 256) used[i] = 0;
+    // a plain dense input (K = 0): its Frobenius norm is computed exactly once
+    // and stands in for the running estimate of the approximation's norm
+    double dn2 = -1.0;
+    if (K == 0 && Dd) {
+        double a2 = 0.0;
+        for (int64_t e = tid; e < (int64_t)m * n; e += 256) a2 += (double)abs2(Dd[e]);
+        dn2 = sum_block(a2, sh_s);
+    }
     __syncthreads();
     int irow = 0, rank = 0;
     double s2 = 0.0;
@@ -377,7 +385,7 @@ __global__ __launch_bounds__(256) void k_aca_prod(const AcaProdJob<T>* __restric
         nv2 = sum_block(nv2, sh_s);
         nx = am_block(nx, sh_am);
         double cross = 0.0;
-        {
+        if (dn2 < 0.0) {
             const int w = tid >> 6, lane = tid & 63;
             for (int l = w; l < rank; l += 4) {
                 double ur = 0, ui = 0, vr = 0, vi = 0;
@@ -399,7 +407,7 @@ __global__ __launch_bounds__(256) void k_aca_prod(const AcaProdJob<T>* __restric
             }
             cross = sum_block(lane == 0 ? cross : 0.0, sh_s);
         }
-        s2 += 2.0 * cross + nu2 * nv2;
+        s2 = dn2 >= 0.0 ? dn2 : s2 + 2.0 * cross + nu2 * nv2;
         ++rank;
         if (nu2 * nv2 <= tol * tol * fabs(s2)) break;
         if (nx.v < 0.0) break;
