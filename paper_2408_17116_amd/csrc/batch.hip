@@ -164,10 +164,11 @@ __global__ __launch_bounds__(256) void k_copy_b(const CopyDesc<T>* __restrict__ 
     if ((int)blockIdx.x >= ntiles) return;
     const CopyTile tl = tiles[blockIdx.x];
     const CopyDesc<T> D = descs[tl.desc];
-    const int64_t tot = (int64_t)D.m * D.n;
-    const int64_t e1 = min(tot, (int64_t)tl.e0 + kCopyChunk);
-    for (int64_t e = tl.e0 + threadIdx.x; e < e1; e += 256) {
-        const int i = (int)(e % D.m), j = (int)(e / D.m);
+    // sizes stay below 2^31 entries: 32-bit index arithmetic
+    const unsigned m = (unsigned)D.m, tot = m * (unsigned)D.n;
+    const unsigned e1 = min(tot, (unsigned)tl.e0 + (unsigned)kCopyChunk);
+    for (unsigned e = (unsigned)tl.e0 + threadIdx.x; e < e1; e += 256) {
+        const int i = (int)(e % m), j = (int)(e / m);
         cplx<T> v = bz<T>();
         if (D.A) v = D.alpha * (D.trans ? D.A[j + (int64_t)i * D.lda] : D.A[i + (int64_t)j * D.lda]);
         D.B[i + (int64_t)j * D.ldb] = v;
@@ -188,13 +189,13 @@ __global__ __launch_bounds__(256) void k_reduce_b(const ReduceDesc<T>* __restric
     if ((int)blockIdx.x >= ntiles) return;
     const CopyTile tl = tiles[blockIdx.x];
     const ReduceDesc<T> D = descs[tl.desc];
-    const int64_t tot = (int64_t)D.m * D.n;
-    const int64_t e1 = min(tot, (int64_t)tl.e0 + kCopyChunk);
+    const unsigned m = (unsigned)D.m, tot = m * (unsigned)D.n;   // below 2^31 entries
+    const unsigned e1 = min(tot, (unsigned)tl.e0 + (unsigned)kCopyChunk);
     const bool zb = D.beta.re == (T)0 && D.beta.im == (T)0;
-    for (int64_t e = tl.e0 + threadIdx.x; e < e1; e += 256) {
+    for (unsigned e = (unsigned)tl.e0 + threadIdx.x; e < e1; e += 256) {
         cplx<T> acc = bz<T>();
-        for (int q = 0; q < D.nsplit; ++q) acc = acc + D.W[e + q * tot];
-        const int i = (int)(e % D.m), j = (int)(e / D.m);
+        for (int q = 0; q < D.nsplit; ++q) acc = acc + D.W[e + (size_t)q * tot];
+        const int i = (int)(e % m), j = (int)(e / m);
         cplx<T>* cp = D.C + i + (int64_t)j * D.ldc;
         cplx<T> o = D.alpha * acc;
         if (!zb) cfma(o, D.beta, *cp);

@@ -22,6 +22,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <unordered_map>
 
 #include "batch.hpp"
@@ -185,6 +186,8 @@ template <typename T> struct HF {
 
     HF(Ctx& cc, double t) : c(cc), s(cc.stream), T_(cc.tree), tol(t) {}
     ~HF() {
+        for (auto e : dev_ev)
+            if (e) (void)hipEventDestroy(e);
         if (rank_pinned) (void)hipHostFree(rank_pinned);
         if (pinned) (void)hipHostFree(pinned);
         if (imm_pinned) (void)hipHostFree(imm_pinned);
@@ -282,6 +285,7 @@ template <typename T> struct HF {
     void rec_copy(int trans, int m, int n, cplx<T> al, const cplx<T>* A, int lda, cplx<T>* B, int ldb,
                   const std::vector<Res>& rd, const std::vector<Res>& wr) {
         if (m <= 0 || n <= 0) return;
+        CBIE_REQUIRE((int64_t)m * n < (int64_t(1) << 31), -7, "copy above 2^31 entries");
         cd.push_back(CopyDesc<T>{m, n, trans, lda, ldb, al, A, B});
         clev.push_back(level_of(rd, wr));
         cseq.push_back(seq++);
@@ -316,13 +320,19 @@ template <typename T> struct HF {
     // Long inner dimension and few output tiles: the k range is split over
     // several work-groups that write partial products to a workspace, and a
     // reduction launch forms C (deterministic; no atomics).
-    static int nsplit(const GemmDesc<T>& d, int sh) {
-        if (d.k < 768) return 1;
-        const int64_t tiles = (int64_t)((d.m + tile_rows(sh) - 1) / tile_rows(sh)) *
-                              ((d.n + tile_cols(sh) - 1) / tile_cols(sh));
-        if (tiles >= 128) return 1;
+    // A launch with few tiles in all takes as long as its slowest tile, a
+    // walk over the whole k range: then every product with k >= 128 is
+    // split too, into about 64-deep ranges, aiming at ~512 work-groups.
+    static int64_t ntiles(const GemmDesc<T>& d, int sh) {
+        return (int64_t)((d.m + tile_rows(sh) - 1) / tile_rows(sh)) * ((d.n + tile_cols(sh) - 1) / tile_cols(sh));
+    }
+    static int nsplit(const GemmDesc<T>& d, int sh, int64_t launch_tiles) {
         const int64_t cap = std::max<int64_t>(1, (int64_t(1) << 22) / ((int64_t)d.m * d.n));   // <= 4M partial entries
-        return (int)std::min<int64_t>({(d.k + 255) / 256, 32, cap});
+        int64_t S = 1;
+        if (d.k >= 768 && ntiles(d, sh) < 128) S = std::min<int64_t>((d.k + 255) / 256, 32);
+        if (launch_tiles < 256 && d.k >= 128)
+            S = std::max<int64_t>(S, std::min<int64_t>((d.k + 63) / 64, std::max<int64_t>(1, 512 / launch_tiles)));
+        return (int)std::min<int64_t>({S, 32, cap});
     }
     // the GEMMs of one launch per tile shape, plus the split-k reductions
     struct Batch {
@@ -331,16 +341,23 @@ template <typename T> struct HF {
         double fl[3] = {0.0, 0.0, 0.0};
         std::vector<ReduceDesc<T>> rd;
         std::vector<CopyTile> rt;
+        int64_t ws_left = int64_t(1) << 26;   // partial-product entries one launch may use
     };
-    void add_gemm(Batch& b, const GemmDesc<T>& d, int sh, Arena<T>& ws) {
-        b.fl[sh] += 8.0 * d.m * d.n * d.k;
-        const int S = nsplit(d, sh);
+    // sh: the product's tile shape; forced: an in-place product, which
+    // keeps its shape unless it is split (its partials are not in place)
+    void add_gemm(Batch& b, const GemmDesc<T>& d, int sh, bool forced, int64_t launch_tiles, Arena<T>& ws) {
+        int S = nsplit(d, sh, launch_tiles);
+        if ((int64_t)S * d.m * d.n > b.ws_left) S = 1;
         if (S <= 1) {
+            b.fl[sh] += 8.0 * d.m * d.n * d.k;
             add_tiles(b.t[sh], (int)b.g[sh].size(), d, sh);
             b.g[sh].push_back(d);
             return;
         }
+        if (forced) sh = pick_shape(d.m, d.n);
+        b.fl[sh] += 8.0 * d.m * d.n * d.k;
         const int64_t mn = (int64_t)d.m * d.n;
+        b.ws_left -= mn * S;
         cplx<T>* W = ws.alloc((size_t)(mn * S));
         const int kc = (d.k + S - 1) / S;
         for (int q = 0; q < S; ++q) {
@@ -361,7 +378,10 @@ template <typename T> struct HF {
         b.rd.push_back(ReduceDesc<T>{d.m, d.n, S, d.ldc, d.alpha, d.beta, W, d.C});
         for (int64_t e0 = 0; e0 < mn; e0 += kCopyChunk) b.rt.push_back(CopyTile{ri, (int)e0});
     }
-    Arena<T> wsp[2];   // split-k workspaces of the recorded programs (alternating)
+    // split-k workspaces: of the recorded programs (alternating; one level
+    // at a time, since a level's partial products start after the previous
+    // level's reductions), and of the recompression's launches
+    Arena<T> wsp[2], wsr;
     int wsp_cur = 0;
 
     // one batched GEMM launch of algorithmic flops fl, timed when profiling
@@ -475,7 +495,6 @@ template <typename T> struct HF {
         // previous program was staged
         wsp_cur ^= 1;
         Arena<T>& ws = wsp[wsp_cur];
-        ws.reset();
         std::vector<Seg> seg(L);
         std::vector<char> host;
         auto put = [&](const void* src, size_t bytes) {
@@ -487,9 +506,12 @@ template <typename T> struct HF {
         for (int lv = 0; lv < L; ++lv) {
             Seg& sg = seg[lv];
             Batch bt;
+            ws.reset();
+            int64_t lt = 0;
+            for (int i : gl[lv]) lt += ntiles(gd[i], gshape[i] >= 0 ? gshape[i] : pick_shape(gd[i].m, gd[i].n));
             for (int i : gl[lv]) {
                 const GemmDesc<T>& d = gd[i];
-                add_gemm(bt, d, gshape[i] >= 0 ? gshape[i] : pick_shape(d.m, d.n), ws);
+                add_gemm(bt, d, gshape[i] >= 0 ? gshape[i] : pick_shape(d.m, d.n), gshape[i] >= 0, lt, ws);
             }
             for (int sh = 0; sh < 3; ++sh) {
                 sg.g[sh] = put(bt.g[sh].data(), bt.g[sh].size() * sizeof(GemmDesc<T>));
@@ -569,14 +591,36 @@ template <typename T> struct HF {
     void* imm_pinned = nullptr;
     size_t imm_pinned_bytes = 0;
     size_t imm_off = 0;
+    // Descriptors go to a pinned staging buffer.  While deferring, launches
+    // wait in a list and commit() uploads everything staged in one copy and
+    // then launches them in order.
+    bool deferring = false;
+    size_t committed = 0;
+    std::vector<std::function<void()>> deferred;
     template <typename D> const D* stage_upload(const std::vector<D>& v) {
         const size_t bytes = v.size() * sizeof(D);
         const size_t off = (imm_off + 255) & ~size_t(255);
         CBIE_REQUIRE(off + bytes <= imm_dev.n, -7, "recompression descriptor buffer overflow");
         std::memcpy((char*)imm_pinned + off, v.data(), bytes);
-        CBIE_HIP(hipMemcpyAsync(imm_dev.p + off, (char*)imm_pinned + off, bytes, hipMemcpyHostToDevice, s));
+        if (!deferring) {
+            CBIE_HIP(hipMemcpyAsync(imm_dev.p + off, (char*)imm_pinned + off, bytes, hipMemcpyHostToDevice, s));
+            committed = off + bytes;
+        }
         imm_off = off + bytes;
         return (const D*)(imm_dev.p + off);
+    }
+    void launch(std::function<void()> f) {
+        if (deferring) deferred.push_back(std::move(f));
+        else f();
+    }
+    void commit() {
+        if (imm_off > committed)
+            CBIE_HIP(hipMemcpyAsync(imm_dev.p + committed, (char*)imm_pinned + committed, imm_off - committed,
+                                    hipMemcpyHostToDevice, s));
+        committed = imm_off;
+        for (auto& f : deferred) f();
+        deferred.clear();
+        deferring = false;
     }
     void imm_begin(size_t bytes) {
         wait_stream();   // earlier uploads from the pinned buffer are done
@@ -587,24 +631,31 @@ template <typename T> struct HF {
             imm_dev.alloc(imm_pinned_bytes);
         }
         imm_off = 0;
+        committed = 0;
     }
     // independent products, split-k workspaces from the recompression's
     // scratch (valid until its round ends)
     void run_gemms(const std::vector<GemmDesc<T>>& g) {
         if (g.empty()) return;
         Batch bt;
-        for (const GemmDesc<T>& d : g) add_gemm(bt, d, pick_shape(d.m, d.n), rscratch);
+        int64_t lt = 0;
+        for (const GemmDesc<T>& d : g) lt += ntiles(d, pick_shape(d.m, d.n));
+        wsr.reset();   // the previous launch's reductions precede these products on the stream
+        for (const GemmDesc<T>& d : g) add_gemm(bt, d, pick_shape(d.m, d.n), false, lt, wsr);
         for (int sh = 0; sh < 3; ++sh) {
             if (bt.t[sh].empty()) continue;
             flops += bt.fl[sh];
             const GemmDesc<T>* dg = stage_upload(bt.g[sh]);
             const GemmTile* dt = stage_upload(bt.t[sh]);
-            launch_gemm(dg, dt, (int)bt.t[sh].size(), sh, bt.fl[sh]);
+            const int nt = (int)bt.t[sh].size();
+            const double fl = bt.fl[sh];
+            launch([=] { launch_gemm(dg, dt, nt, sh, fl); });
         }
         if (!bt.rt.empty()) {
             const ReduceDesc<T>* dr = stage_upload(bt.rd);
             const CopyTile* dt = stage_upload(bt.rt);
-            reduce_batched<T>(s, dr, dt, (int)bt.rt.size());
+            const int nt = (int)bt.rt.size();
+            launch([=] { reduce_batched<T>(s, dr, dt, nt); });
             ++launches;
         }
     }
@@ -615,7 +666,8 @@ template <typename T> struct HF {
             for (int64_t e0 = 0; e0 < (int64_t)c2[i].m * c2[i].n; e0 += kCopyChunk) tiles.push_back(CopyTile{(int)i, (int)e0});
         const CopyDesc<T>* dc = stage_upload(c2);
         const CopyTile* dt = stage_upload(tiles);
-        copy_batched<T>(s, dc, dt, (int)tiles.size());
+        const int nt = (int)tiles.size();
+        launch([=] { copy_batched<T>(s, dc, dt, nt); });
         ++launches;
     }
 
@@ -706,25 +758,44 @@ template <typename T> struct HF {
                 aj.push_back(J);
                 h4.push_back(GemmDesc<T>{m, t.cap, pp, 0, 0, o, z, t.Q, t.Ub, t.Uo, m, pp, m, 0});
             }
-            rand_batched<T>(s, stage_upload(rd), (int)rd.size());
+            deferring = true;
+            {
+                const RandDesc<T>* d = stage_upload(rd);
+                const int n = (int)rd.size();
+                launch([=] { rand_batched<T>(s, d, n); });
+            }
             ++launches;
             run_gemms(g1);
             run_gemms(g2);
             run_gemms(g3);
             run_gemms(g4);
-            pchol_batched<T>(s, stage_upload(pc), (int)pc.size());
+            {
+                const PcholDesc<T>* d = stage_upload(pc);
+                const int n = (int)pc.size();
+                launch([=] { pchol_batched<T>(s, d, n); });
+            }
             ++launches;
             run_gemms(g5);
             run_gemms(q1);
-            pchol_batched<T>(s, stage_upload(pc2), (int)pc2.size());
+            {
+                const PcholDesc<T>* d = stage_upload(pc2);
+                const int n = (int)pc2.size();
+                launch([=] { pchol_batched<T>(s, d, n); });
+            }
             ++launches;
             run_gemms(q2);
             run_gemms(g6);
             run_gemms(h1);
             run_gemms(h2);
-            aca_product_batched<T>(s, (int)aj.size(), stage_upload(aj), tol);
+            {
+                const AcaProdJob<T>* d = stage_upload(aj);
+                const int n = (int)aj.size();
+                const double tl = tol;
+                launch([=] { aca_product_batched<T>(s, n, d, tl); });
+            }
             ++launches;
             run_gemms(h4);
+            commit();
             if (rank_pinned_n < 2 * nb) {
                 if (rank_pinned) CBIE_HIP(hipHostFree(rank_pinned));
                 rank_pinned_n = std::max<size_t>(2 * nb, 2 * rank_pinned_n);
@@ -772,14 +843,30 @@ template <typename T> struct HF {
 
     // run the program, then recompress the given low-rank blocks that hold
     // pending columns or a dirty dense accumulator
+    // debug: GPU time of the recorded programs and of the recompressions
+    hipEvent_t dev_ev[3] = {nullptr, nullptr, nullptr};
+    double gpu_prog = 0.0, gpu_recomp = 0.0;
     void flush_set(const std::vector<int>& leaves) {
+        if (debug && !dev_ev[0])
+            for (auto& e : dev_ev) CBIE_HIP(hipEventCreate(&e));
+        if (debug) CBIE_HIP(hipEventRecord(dev_ev[0], s));
         execute();
+        if (debug) CBIE_HIP(hipEventRecord(dev_ev[1], s));
         std::vector<int> todo;
         for (int b : leaves)
             if (lr[b].pending() && lr_busy[b] == 0) todo.push_back(b);
         if (todo.empty()) return;
         for (int b : todo) flush_k += lr[b].K;
         recompress(todo);
+        if (debug) {
+            CBIE_HIP(hipEventRecord(dev_ev[2], s));
+            CBIE_HIP(hipEventSynchronize(dev_ev[2]));
+            float a = 0.f, b = 0.f;
+            CBIE_HIP(hipEventElapsedTime(&a, dev_ev[0], dev_ev[1]));
+            CBIE_HIP(hipEventElapsedTime(&b, dev_ev[1], dev_ev[2]));
+            gpu_prog += 1e-3 * a;
+            gpu_recomp += 1e-3 * b;
+        }
         ++flushes;
         if (debug && flushes % 25 == 0)
             fprintf(stderr, "[cbie] flush %lld: %zu blocks, %.2f s\n", (long long)flushes, todo.size(), now_s() - t_start);
@@ -906,6 +993,14 @@ template <typename T> struct HF {
         return {rect(RES_U, id, v.r0, v.m, 0, kAll), rect(RES_V, id, v.c0, v.n, 0, kAll)};
     }
 
+    // Appending k columns would leave low-rank block C with factors larger
+    // than the block itself: the product is then added to its dense
+    // accumulator instead (folded in at the next recompression).
+    bool to_dacc(const View& C, int k) const {
+        const LR& L = lr[leaf_of(C)];
+        return (int64_t)L.m * L.n <= kDenseAccMax && (int64_t)(L.K + k) * (L.m + L.n) > (int64_t)L.m * L.n;
+    }
+
     // room for k more columns of low-rank block C: returns the first new
     // column.  The new columns are zeroed where the product written into
     // them covers only some of the block's rows (or columns).
@@ -956,6 +1051,14 @@ template <typename T> struct HF {
             int ldc;
             cplx<T>* Cp = dptr(C, ldc);
             rec_gemm(0, 1, C.m, C.n, k, al, Xp, ldx, Yp, ldy, one(), Cp, ldc, cat({res(X), res(Y)}), res(C));
+            return;
+        }
+        if (to_dacc(C, k)) {
+            const int lc = leaf_of(C);
+            cplx<T>* D = dacc(lc);
+            const int m = lr[lc].m;
+            rec_gemm(0, 1, C.m, C.n, k, al, Xp, ldx, Yp, ldy, one(), D + (int64_t)C.c0 * m + C.r0, m,
+                     cat({res(X), res(Y)}), {rect(RES_D, lc, C.r0, C.m, C.c0, C.n)});
             return;
         }
         if (lrb(C).K + k > kmax) {
@@ -1038,9 +1141,8 @@ template <typename T> struct HF {
             const int wa = kind(A) == LRK ? lrb(A).K : -1, wb = kind(B) == LRK ? lrb(B).K : -1;
             const bool small = (int64_t)lrb(C).m * lrb(C).n <= kDenseAccMax;
             auto pair_w = [&](int a_lr, int b_lr) {   // width appended for one part pair
-                if (a_lr >= 0) return a_lr;
-                if (b_lr >= 0) return b_lr;
-                return small ? 0 : A.n;
+                const int w = a_lr >= 0 ? a_lr : (b_lr >= 0 ? b_lr : (small ? 0 : A.n));
+                return to_dacc(C, w) ? 0 : w;
             };
             for (int pa = 0; pa < (da ? 2 : 1); ++pa)
                 for (int pb = 0; pb < (db ? 2 : 1); ++pb)
@@ -1066,10 +1168,25 @@ template <typename T> struct HF {
         const int kA = kind(A), kB = kind(B), kC = kind(C);
         const bool dA = kA != LRK, dB = kB != LRK;
         const std::vector<Res> rA = dA ? res(A) : fac(A), rB = dB ? res(B) : fac(B);
-        if (kC != LRK) {
-            const std::vector<Res> rC = res(C);
-            int ldc;
-            cplx<T>* Cp = dptr(C, ldc);
+        // a dense target: C itself, or the dense accumulator of a low-rank C
+        bool dense = kC != LRK;
+        std::vector<Res> rC;
+        int ldc = 0;
+        cplx<T>* Cp = nullptr;
+        if (dense) {
+            rC = res(C);
+            Cp = dptr(C, ldc);
+        } else {
+            const int w = !dA ? lrb(A).K : (!dB ? lrb(B).K : A.n);
+            if ((dA && dB && (int64_t)lrb(C).m * lrb(C).n <= kDenseAccMax) || to_dacc(C, w)) {
+                const int lc = leaf_of(C);
+                Cp = dacc(lc) + (int64_t)C.c0 * lr[lc].m + C.r0;
+                ldc = lr[lc].m;
+                rC = {rect(RES_D, lc, C.r0, C.m, C.c0, C.n)};
+                dense = true;
+            }
+        }
+        if (dense) {
             if (dA && dB) {
                 int lda, ldb;
                 cplx<T>* Ap = dptr(A, lda);
@@ -1150,14 +1267,6 @@ template <typename T> struct HF {
             const Res rX = rect(RES_U, lc, C.r0, C.m, col, kb), rY = rect(RES_V, lc, C.c0, C.n, col, kb);
             rec_gemm(0, 0, C.m, kb, A.n, al, Ap, lda, Lb.U + B.r0, Lb.m, zero(), X, Lc.m, cat({rA, rB}), {rX});
             rec_copy(0, C.n, kb, one(), Lb.V + B.c0, Lb.n, Y, Lc.n, rB, {rY});
-        } else if ((int64_t)lrb(C).m * lrb(C).n <= kDenseAccMax) {
-            int lda, ldb;
-            cplx<T>* Ap = dptr(A, lda);
-            cplx<T>* Bp = dptr(B, ldb);
-            cplx<T>* D = dacc(lc);
-            const int m = lr[lc].m;
-            rec_gemm(0, 0, C.m, C.n, A.n, al, Ap, lda, Bp, ldb, one(), D + (int64_t)C.c0 * m + C.r0, m, cat({rA, rB}),
-                     {rect(RES_D, lc, C.r0, C.m, C.c0, C.n)});
         } else {
             const int k = A.n;
             width_dd += k;
@@ -1441,12 +1550,13 @@ template <typename T> static void run_factor(Ctx& c, HF<T>& f) {
         fprintf(stderr,
                 "[cbie] levels %lld flushes %lld (width overflows %lld) rounds %lld widths lrA %.0f lrB %.0f dd %.0f flushK %.0f; "
                 "host waited %.2f s of %.2f s; host in level_of %.2f s (%lld calls, %lld entries scanned), "
-                "execute %.2f s, recompress %.2f s; factor storage %.2f GB\n",
+                "execute %.2f s, recompress %.2f s; factor storage %.2f GB; flush spans: program %.2f s, "
+                "recompression %.2f s\n",
                 (long long)f.levels_run, (long long)f.flushes, (long long)f.flush_overflow,
                 (long long)f.recompress_rounds, f.width_lr_a,
                 f.width_lr_b, f.width_dd, f.flush_k, f.t_wait, now_s() - f.t_start, f.t_level,
                 (long long)f.n_level_calls, (long long)f.n_scanned, f.t_exec, f.t_recomp,
-                1e-9 * (double)f.store.bump.live * sizeof(cplx<T>));
+                1e-9 * (double)f.store.bump.live * sizeof(cplx<T>), f.gpu_prog, f.gpu_recomp);
 }
 
 void stage_factor(Ctx& c, int prec) {
