@@ -61,39 +61,47 @@ template <typename T> struct Arena {
         cur = chunks.empty() ? -1 : 0;
         live = 0;
     }
+    double capacity() const {
+        double c = 0;
+        for (const auto& b : chunks) c += (double)b.n;
+        return c;
+    }
 };
 
-// Device storage of the factors: power-of-two size classes (at least 4096
-// elements) carved from a bump arena, with free lists.  A released buffer
+// Device storage of the factors: size classes of four steps per power of
+// two (at least 4096 elements) carved from a bump arena, with free lists.  A released buffer
 // may still be read or written by tasks recorded before its release, so it
 // is reused only after the stream has completed them: released while a
 // program is being recorded -> waiting for that program's launch ->
 // free once the stream has been synchronized after the launch.
 template <typename T> struct Pool {
     Arena<T> bump;
-    std::vector<std::vector<cplx<T>*>> free_cls = std::vector<std::vector<cplx<T>*>>(64);
+    std::vector<std::vector<cplx<T>*>> free_cls = std::vector<std::vector<cplx<T>*>>(256);
     std::vector<std::pair<cplx<T>*, int>> rec, run;
-    size_t live = 0;
+    size_t live = 0, peak = 0;
+    // class c holds (4 + c % 4) 2^(c / 4 - 2) elements
+    static size_t cls_size(int c) { return (size_t)(4 + c % 4) << (c / 4 - 2); }
     static int cls(size_t n) {
-        int c = 12;
-        while (((size_t)1 << c) < n) ++c;
+        int c = 48;                        // 4096 elements
+        while (cls_size(c) < n) ++c;
         return c;
     }
     cplx<T>* alloc(size_t n) {
         const int c = cls(n);
-        live += (size_t)1 << c;
+        live += cls_size(c);
+        peak = std::max(peak, live);
         if (!free_cls[c].empty()) {
             cplx<T>* p = free_cls[c].back();
             free_cls[c].pop_back();
             return p;
         }
-        return bump.alloc((size_t)1 << c);
+        return bump.alloc(cls_size(c));
     }
     // n: the size passed to alloc
     void release(cplx<T>* p, size_t n) {
         if (!p) return;
         rec.push_back({p, cls(n)});
-        live -= (size_t)1 << cls(n);
+        live -= cls_size(cls(n));
     }
     void launched() {
         run.insert(run.end(), rec.begin(), rec.end());
@@ -694,7 +702,23 @@ template <typename T> struct HF {
         // Gram eigenvalue ratio kept by the pivoted Cholesky: CholeskyQR2 is
         // stable while cond(Y) < u^{-1/2}, i.e. ratio > ~u (FP64 1e-16, FP32 1e-7)
         const double gram_thr = sizeof(T) == 8 ? 1e-16 : 1e-7;
+        std::vector<int> rest_b, rest_p;
         while (!todo.empty()) {
+            // blocks whose temporaries fit the scratch budget go in this round
+            {
+                size_t mem = 0, take = 0;
+                for (; take < todo.size(); ++take) {
+                    const LR& L = lr[todo[take]];
+                    const size_t pp = (size_t)pq[take], K1 = (size_t)std::max(L.K, 1);
+                    const size_t need = pp * (3 * (size_t)L.n + 4 * (size_t)L.m + 2 * K1 + 6 * pp);
+                    if (take > 0 && mem + need > kRecompScratch) break;
+                    mem += need;
+                }
+                rest_b.assign(todo.begin() + take, todo.end());
+                rest_p.assign(pq.begin() + take, pq.end());
+                todo.resize(take);
+                pq.resize(take);
+            }
             const size_t nb = todo.size();
             size_t bytes = 0;
             for (size_t q = 0; q < nb; ++q)
@@ -825,7 +849,9 @@ template <typename T> struct HF {
                 L.V = store.alloc((size_t)L.n * L.cap);
                 cp.push_back(CopyDesc<T>{L.m, rr, 0, L.m, L.m, o, tm[q].Uo, L.U});
                 cp.push_back(CopyDesc<T>{L.n, rr, 0, L.n, L.n, o, tm[q].Vb, L.V});
-                if (L.dirty) cp.push_back(CopyDesc<T>{L.m, L.n, 0, L.m, L.m, z, nullptr, L.D});
+                // the dense accumulator is folded in: released until needed again
+                store.release(L.D, (size_t)L.m * L.n);
+                L.D = nullptr;
                 L.r = L.K = rr;
                 L.dirty = false;
             }
@@ -834,10 +860,16 @@ template <typename T> struct HF {
             rscratch.reset();
             todo = again;
             pq = again_p;
+            todo.insert(todo.end(), rest_b.begin(), rest_b.end());
+            pq.insert(pq.end(), rest_p.begin(), rest_p.end());
             ++recompress_rounds;
         }
     }
     int64_t recompress_rounds = 0;
+    // temporaries (elements) of one recompression round and of a recorded
+    // program before it is run early
+    static constexpr size_t kRecompScratch = size_t(1) << 29;
+    static constexpr size_t kScratchBudget = size_t(1) << 29;
     int* rank_pinned = nullptr;   // rank readback (pinned host memory)
     size_t rank_pinned_n = 0;
 
@@ -1094,6 +1126,9 @@ template <typename T> struct HF {
         }
     };
     void update(const View& C, const View& A, const View& B, cplx<T> al) {
+        // no scratch view is live outside the pinned shortcuts: when the
+        // program's temporaries grow large, run it and recycle them
+        if (pin == 0 && scratch.live > kScratchBudget) execute();
         const bool hc = kind(C) == HIER, ha = kind(A) == HIER, hb = kind(B) == HIER;
         const Busy busy_a(lr_busy, kind(A) == LRK ? leaf_of(A) : -1), busy_b(lr_busy, kind(B) == LRK ? leaf_of(B) : -1);
         // low-rank times hierarchical: the product has the operand's rank;
@@ -1550,13 +1585,16 @@ template <typename T> static void run_factor(Ctx& c, HF<T>& f) {
         fprintf(stderr,
                 "[cbie] levels %lld flushes %lld (width overflows %lld) rounds %lld widths lrA %.0f lrB %.0f dd %.0f flushK %.0f; "
                 "host waited %.2f s of %.2f s; host in level_of %.2f s (%lld calls, %lld entries scanned), "
-                "execute %.2f s, recompress %.2f s; factor storage %.2f GB; flush spans: program %.2f s, "
-                "recompression %.2f s\n",
+                "execute %.2f s, recompress %.2f s; factor storage %.2f GB (peak live %.2f GB), scratch %.2f GB, "
+                "recompression scratch %.2f GB, split-k %.2f GB; flush spans: program %.2f s, recompression %.2f s\n",
                 (long long)f.levels_run, (long long)f.flushes, (long long)f.flush_overflow,
                 (long long)f.recompress_rounds, f.width_lr_a,
                 f.width_lr_b, f.width_dd, f.flush_k, f.t_wait, now_s() - f.t_start, f.t_level,
                 (long long)f.n_level_calls, (long long)f.n_scanned, f.t_exec, f.t_recomp,
-                1e-9 * (double)f.store.bump.live * sizeof(cplx<T>), f.gpu_prog, f.gpu_recomp);
+                1e-9 * (double)f.store.bump.live * sizeof(cplx<T>), 1e-9 * (double)f.store.peak * sizeof(cplx<T>),
+                1e-9 * f.scratch.capacity() * sizeof(cplx<T>), 1e-9 * f.rscratch.capacity() * sizeof(cplx<T>),
+                1e-9 * (f.wsp[0].capacity() + f.wsp[1].capacity() + f.wsr.capacity()) * sizeof(cplx<T>), f.gpu_prog,
+                f.gpu_recomp);
 }
 
 void stage_factor(Ctx& c, int prec) {
@@ -1586,6 +1624,8 @@ template <typename T> static void lu_solve_tree(Ctx& c, HF<T>& f, cplx<T>* X, in
         f.solveU(root, v);
     }
     f.execute();
+    CBIE_REQUIRE(f.audit_conflicts == 0, -7,
+                 "dependency audit: " + std::to_string(f.audit_conflicts) + " conflicting task pairs in one level");
 }
 
 // column norms |r_j|^2 and |b_j|^2

@@ -87,3 +87,50 @@ def test_sphere_2pi_against_dense_oracle(prec):
     print(f"prec {prec}: |J - J_oracle| {err:.2e}, RCS vs oracle {rcs_err:.2e}, vs Mie {mie_err:.2e}, sweeps {it}")
     assert err < 1e-5
     assert rcs_err < 1e-5
+
+
+def test_headline_sphere_sampled_rows_and_pipelines_agree():
+    """The benchmark configuration (PEC sphere ka = 20, 384 patches, q = 8,
+    49152 unknowns, leaf 256, eta 1, ACA 1e-6, 16 seeded waves): the mixed
+    pipeline's solution leaves a small residual on exact oracle rows sampled
+    one by one, and agrees with the complex128 pipeline's solution."""
+    from paper_2408_17116_amd import cbie
+    spec = W.sphere_pec_ka20()
+    kh, pol = W.plane_waves(16, seed=0)
+    s = _solver(spec, leaf=256, tol=1e-6)
+    b = s.rhs_planewave(kh, pol)
+    s.factor(cbie.PREC_C64_IR)
+    x64, it = s.solve(b, tol=1e-9, maxit=20)
+    s.factor(cbie.PREC_C128)
+    x128, _ = s.solve(b, tol=1e-9, maxit=0)
+    x64 = x64.cpu().numpy()
+    x128 = x128.cpu().numpy()
+    s.close()
+    agree = np.linalg.norm(x64 - x128) / np.linalg.norm(x128)
+    nd = G.build_nodes(spec)
+    rows = W.sample_indices(2 * nd.size, 6, seed=21)
+    Ar = mfie.matrix_rows(nd, spec.k0, rows)
+    bo = mfie.rhs_planewave(nd, spec.k0, kh, pol)
+    res = np.abs(Ar @ x64 - bo[rows]).max() / np.abs(bo).max()
+    print(f"N {spec.n_unknowns}: mixed vs complex128 {agree:.2e}, sampled-row residual {res:.2e}, sweeps {it}")
+    assert agree < 1e-5
+    assert res < 1e-5
+
+
+def test_dependency_audit_clean():
+    """The recorded H-LU program, checked against the memory each task really
+    touches: conflicting tasks run in recording order at distinct levels."""
+    import os
+    from paper_2408_17116_amd import cbie
+    spec = W.tiny_sphere(s=4, q=4, k0=6.0)
+    os.environ["CBIE_CHECK_DEPS"] = "1"
+    try:
+        for prec in (cbie.PREC_C64_IR, cbie.PREC_C128):
+            s = _solver(spec, leaf=64, tol=1e-8)
+            s.factor(prec)          # raises if the audit finds a conflict
+            kh, pol = W.plane_waves(2, seed=4)
+            b = s.rhs_planewave(kh, pol)
+            s.solve(b, tol=1e-10, maxit=0 if prec == cbie.PREC_C128 else 30)
+            s.close()
+    finally:
+        del os.environ["CBIE_CHECK_DEPS"]
