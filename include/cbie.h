@@ -168,8 +168,58 @@ typedef struct {
     int64_t gemm_launches;
     double gemm_flops;
     double gemm_seconds;
+    /* compress: admissible blocks redone with the full width because the
+     * predicted width was too small; ACA workspace of the pass(es), bytes */
+    int64_t aca_fallbacks;
+    double aca_workspace_bytes;
 } cbie_stats;
 cbie_status cbie_get_stats(cbie_ctx* ctx, void* stats_out, size_t bytes);
+
+/* ------------------------------------------------------------------
+ * Rank predictor (an addition to the paper's method).  A fully connected
+ * network 8 -> 64 -> 64 -> 1 with ReLU maps geometric features of an
+ * admissible block to the natural log of its adaptive ACA rank.  Parameters
+ * (CBIE_MLP_NPARAMS float32): W1 (64 x 8, row-major), b1 (64), W2 (64 x 64,
+ * row-major), b2 (64), W3 (64), b3 (1).  Inputs are standardized by a
+ * per-feature mean and standard deviation (8 float32 each).
+ * Features of block (t, s), object wavenumber k, boxes of the node clusters:
+ *   log m, log n (unknowns), k diam_t, k diam_s, k dist, max(diam)/dist,
+ *   log10(ACA tol), k diam_t diam_s / dist  (diam: box diagonal, dist: box gap)
+ * ------------------------------------------------------------------ */
+#define CBIE_MLP_NFEAT 8
+#define CBIE_MLP_NPARAMS 4801
+
+/* After build_tree: features of every admissible block (host, count x 8
+ * float32, low-rank block order) and, after compress, their ranks (host,
+ * count int32; -1 before compress).  cap: rows the arrays hold (either may
+ * be NULL); count_out: number of admissible blocks.  Errors: ESTATE, EINVAL. */
+cbie_status cbie_get_block_features(cbie_ctx* ctx, double aca_tol, int64_t cap, float* feat, int32_t* ranks,
+                                    int64_t* count_out);
+
+/* The model used by compress(CBIE_RANK_PREDICTED) (host arrays, copied).
+ * A block's ACA then starts with width ceil(exp(y) (1 + margin)) + 2
+ * (y: predicted log-rank); a block that fills it without converging is
+ * redone with the full width, so the factors equal the adaptive ones.
+ * Errors: EINVAL. */
+cbie_status cbie_set_rank_model(cbie_ctx* ctx, const float* params, const float* mean, const float* sdev,
+                                float margin);
+
+/* Network kernels on a HIP stream; every array is device float32 (order:
+ * int32).  X: n x 8 row-major raw features.
+ * forward: y[i] = network((X[i] - mean) / sdev).
+ * grad: loss[0] = mean_i (y_i - t_i)^2 and grad (CBIE_MLP_NPARAMS) its
+ *   gradient with respect to the parameters.
+ * train: Adam (beta1 0.9, beta2 0.999, eps 1e-8, rate lr) for nsteps steps,
+ *   step s on samples order[s * batch .. (s + 1) * batch); params updated in
+ *   place, losses[s] = that batch's loss before the step.  One work-group.
+ * Errors: EINVAL (sizes), EHIP. */
+cbie_status cbie_mlp_forward(void* hip_stream, const float* params, const float* mean, const float* sdev,
+                             const float* X, int64_t n, float* y);
+cbie_status cbie_mlp_grad(void* hip_stream, const float* params, const float* mean, const float* sdev,
+                          const float* X, const float* t, int64_t n, float* grad, float* loss);
+cbie_status cbie_mlp_train(void* hip_stream, float* params, const float* mean, const float* sdev, const float* X,
+                           const float* t, const int32_t* order, int64_t nsteps, int batch, float lr,
+                           float* losses);
 
 /* Kernel timing: on != 0 brackets every batched GEMM launch with HIP events
  * on the context stream (their sum is reported as gemm_seconds).  Costs a

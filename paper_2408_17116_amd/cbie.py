@@ -24,7 +24,10 @@ RANK_ADAPTIVE, RANK_PREDICTED = 0, 1
 EXPORTED = ["cbie_create", "cbie_build_tree", "cbie_fill", "cbie_compress", "cbie_factor",
             "cbie_solve", "cbie_matvec", "cbie_rhs_planewave", "cbie_farfield", "cbie_get_stats",
             "cbie_set_profiling", "cbie_get_near_pairs", "cbie_export_dense", "cbie_last_error",
-            "cbie_destroy"]
+            "cbie_destroy", "cbie_get_block_features", "cbie_set_rank_model", "cbie_mlp_forward",
+            "cbie_mlp_grad", "cbie_mlp_train"]
+
+MLP_NFEAT, MLP_NPARAMS = 8, 4801
 
 
 class CbieError(RuntimeError):
@@ -52,7 +55,8 @@ class Stats(C.Structure):
         ("t_compress", C.c_double), ("t_factor", C.c_double), ("t_solve", C.c_double),
         ("factor_flops", C.c_int64), ("n_kernel_launches", C.c_int64),
         ("ir_iterations", C.c_int64), ("quad_seconds", C.c_double),
-        ("gemm_launches", C.c_int64), ("gemm_flops", C.c_double), ("gemm_seconds", C.c_double)]
+        ("gemm_launches", C.c_int64), ("gemm_flops", C.c_double), ("gemm_seconds", C.c_double),
+        ("aca_fallbacks", C.c_int64), ("aca_workspace_bytes", C.c_double)]
 
 
 _lib = None
@@ -83,6 +87,11 @@ def load(path: str = LIB_PATH):
         "cbie_export_dense": ([vp, vp, C.c_long], i32),
         "cbie_last_error": ([vp], C.c_char_p),
         "cbie_destroy": ([vp], None),
+        "cbie_get_block_features": ([vp, dbl, i64, vp, vp, C.POINTER(i64)], i32),
+        "cbie_set_rank_model": ([vp, vp, vp, vp, C.c_float], i32),
+        "cbie_mlp_forward": ([vp, vp, vp, vp, vp, i64, vp], i32),
+        "cbie_mlp_grad": ([vp, vp, vp, vp, vp, vp, i64, vp, vp], i32),
+        "cbie_mlp_train": ([vp, vp, vp, vp, vp, vp, vp, i64, i32, C.c_float, vp], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -216,7 +225,84 @@ class Solver:
                                                  p.ctypes.data_as(C.c_void_p), C.byref(cnt)))
         return t, p
 
+    def block_features(self, aca_tol):
+        """(features (count, 8) float32, ranks (count,) int32; -1 before
+        compress) of the admissible blocks, in low-rank block order."""
+        cnt = C.c_int64(0)
+        self._check(self.lib.cbie_get_block_features(self.h, aca_tol, 0, None, None, C.byref(cnt)))
+        f = np.empty((cnt.value, MLP_NFEAT), dtype=np.float32)
+        r = np.empty(cnt.value, dtype=np.int32)
+        self._check(self.lib.cbie_get_block_features(self.h, aca_tol, cnt.value, f.ctypes.data_as(C.c_void_p),
+                                                     r.ctypes.data_as(C.c_void_p), C.byref(cnt)))
+        return f, r
+
+    def set_rank_model(self, params, mean, sdev, margin=0.25):
+        """Model for compress(mode=RANK_PREDICTED) (host arrays, copied)."""
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        m = np.ascontiguousarray(mean, dtype=np.float32)
+        d = np.ascontiguousarray(sdev, dtype=np.float32)
+        if p.size != MLP_NPARAMS or m.size != MLP_NFEAT or d.size != MLP_NFEAT:
+            raise ValueError("rank model sizes")
+        self._check(self.lib.cbie_set_rank_model(self.h, p.ctypes.data_as(C.c_void_p), m.ctypes.data_as(C.c_void_p),
+                                                 d.ctypes.data_as(C.c_void_p), float(margin)))
+
     def export_dense(self):
         A = self.torch.empty((self.n, self.n), dtype=self.torch.complex128, device="cuda")
         self._check(self.lib.cbie_export_dense(self.h, _ptr(A), self.n))
         return A.t()   # the library writes column-major
+
+
+# ------------------------------------------------------------------ network
+def _f32(t, n=None):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise TypeError("expected a contiguous float32 CUDA tensor")
+    if n is not None and t.numel() != n:
+        raise ValueError(f"expected {n} elements, got {t.numel()}")
+    return _ptr(t)
+
+
+def _mlp_check(st, what):
+    if st != OK:
+        raise CbieError(st, what)
+
+
+def mlp_forward(params, mean, sdev, X):
+    """y[i] = network((X[i] - mean) / sdev); X (n, 8) raw features."""
+    import torch
+    n = X.shape[0]
+    y = torch.empty(n, dtype=torch.float32, device=X.device)
+    _mlp_check(load().cbie_mlp_forward(C.c_void_p(torch.cuda.current_stream().cuda_stream), _f32(params, MLP_NPARAMS),
+                                       _f32(mean, MLP_NFEAT), _f32(sdev, MLP_NFEAT), _f32(X, n * MLP_NFEAT), n,
+                                       _f32(y)), "cbie_mlp_forward")
+    return y
+
+
+def mlp_grad(params, mean, sdev, X, t):
+    """(loss, gradient) of mean (y - t)^2 over all samples."""
+    import torch
+    n = X.shape[0]
+    g = torch.empty(MLP_NPARAMS, dtype=torch.float32, device=X.device)
+    L = torch.empty(1, dtype=torch.float32, device=X.device)
+    _mlp_check(load().cbie_mlp_grad(C.c_void_p(torch.cuda.current_stream().cuda_stream), _f32(params, MLP_NPARAMS),
+                                    _f32(mean, MLP_NFEAT), _f32(sdev, MLP_NFEAT), _f32(X, n * MLP_NFEAT),
+                                    _f32(t, n), n, _f32(g), _f32(L)), "cbie_mlp_grad")
+    return L, g
+
+
+def mlp_train(params, mean, sdev, X, t, order, batch, lr):
+    """Adam on consecutive runs of `batch` sample indices of `order` (int32
+    CUDA tensor); params (float32 CUDA) updated in place; per-step losses."""
+    import torch
+    n = X.shape[0]
+    if not (order.is_cuda and order.dtype == torch.int32 and order.is_contiguous()):
+        raise TypeError("order: contiguous int32 CUDA tensor")
+    if order.numel() and (int(order.min()) < 0 or int(order.max()) >= n):
+        raise ValueError("order holds an index outside the samples")
+    nsteps = order.numel() // batch
+    losses = torch.empty(max(nsteps, 1), dtype=torch.float32, device=X.device)
+    _mlp_check(load().cbie_mlp_train(C.c_void_p(torch.cuda.current_stream().cuda_stream), _f32(params, MLP_NPARAMS),
+                                     _f32(mean, MLP_NFEAT), _f32(sdev, MLP_NFEAT), _f32(X, n * MLP_NFEAT),
+                                     _f32(t, n), _ptr(order), nsteps, batch, float(lr), _f32(losses)),
+               "cbie_mlp_train")
+    return losses[:nsteps]

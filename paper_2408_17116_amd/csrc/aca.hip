@@ -5,6 +5,7 @@
 
 #include "ctx.hpp"
 #include "lowrank.hpp"
+#include "mlp.hpp"
 
 namespace cbie {
 
@@ -236,57 +237,119 @@ __global__ void k_export_lr(const DenseBlockDev* __restrict__ blocks, int n_bloc
     }
 }
 
+// ACA of the given blocks with the given widths: ranks and convergence
+// flags, factors in the workspace (U then V per block)
+struct AcaPass {
+    std::vector<AcaJob> jobs;
+    DBuf<zd> ws;
+    DBuf<unsigned char> used;
+    DBuf<AcaJob> d_jobs;
+    DBuf<int> d_rank, d_flag;
+    std::vector<int> rank, flag;
+    int64_t ws_elems = 0;
+};
+static void aca_pass(Ctx& c, double tol, const std::vector<int>& blocks, const std::vector<int>& width, AcaPass& P) {
+    const int nb = (int)blocks.size();
+    P.jobs.assign(nb, AcaJob{});
+    int64_t off = 0, uoff = 0;
+    for (int q = 0; q < nb; ++q) {
+        const DenseBlockDev& d = c.lblk[blocks[q]];
+        AcaJob& J = P.jobs[q];
+        J.row_node0 = d.row_node0;
+        J.row_nodes = d.row_nodes;
+        J.col_node0 = d.col_node0;
+        J.col_nodes = d.col_nodes;
+        J.obj = d.obj;
+        const int m = 2 * d.row_nodes, n = 2 * d.col_nodes;
+        J.cap = width[q];
+        J.u_off = off;
+        off += (int64_t)m * J.cap;
+        J.v_off = off;
+        off += (int64_t)n * J.cap;
+        J.used_off = uoff;
+        uoff += m;
+    }
+    P.ws_elems = off;
+    P.ws.alloc(std::max<int64_t>(off, 1));
+    P.used.alloc(std::max<int64_t>(uoff, 1));
+    P.d_jobs.upload(P.jobs, c.stream);
+    P.d_rank.alloc(std::max(nb, 1));
+    P.d_flag.alloc(std::max(nb, 1));
+    k_aca<<<nb, 256, 0, c.stream>>>(P.d_jobs.p, nb, c.d_tree_node.p, c.nd, c.d_objs.p, tol, P.ws.p, P.used.p,
+                                    P.d_rank.p, P.d_flag.p);
+    check_launch("k_aca");
+    P.rank.resize(nb);
+    P.flag.resize(nb);
+    P.d_rank.download(P.rank.data(), nb, c.stream);
+    P.d_flag.download(P.flag.data(), nb, c.stream);
+    c.sync();
+}
+
 void stage_compress(Ctx& c, double tol, int mode) {
-    (void)mode;   // rank prediction is layered on top of the adaptive pass
     const double t0 = now_s();
     const int nb = (int)c.lblk.size();
+    CBIE_REQUIRE(mode != CBIE_RANK_PREDICTED || c.rank_model.set, CBIE_EINVAL, "predicted ranks without a rank model");
     c.aca_tol = tol;
+    ++c.lr_version;
     c.lr.u_off.assign(nb, 0);
     c.lr.v_off.assign(nb, 0);
     c.lr.rank.assign(nb, 0);
     c.lr.cap.assign(nb, 0);
     int64_t lr_entries = 0, max_rank = 0, sum_rank = 0;
+    c.stats.aca_fallbacks = 0;
+    c.stats.aca_workspace_bytes = 0.0;
     if (nb > 0) {
-        // workspace: U (m x cap) and V (n x cap) per block
-        std::vector<AcaJob> jobs(nb);
-        int64_t off = 0, uoff = 0;
+        std::vector<int> all(nb), full(nb), width(nb);
         for (int b = 0; b < nb; ++b) {
-            const DenseBlockDev& d = c.lblk[b];
-            AcaJob& J = jobs[b];
-            J.row_node0 = d.row_node0;
-            J.row_nodes = d.row_nodes;
-            J.col_node0 = d.col_node0;
-            J.col_nodes = d.col_nodes;
-            J.obj = d.obj;
-            const int m = 2 * d.row_nodes, n = 2 * d.col_nodes;
-            J.cap = std::min({m, n, kAcaMaxRank});
-            J.u_off = off;
-            off += (int64_t)m * J.cap;
-            J.v_off = off;
-            off += (int64_t)n * J.cap;
-            J.used_off = uoff;
-            uoff += m;
+            all[b] = b;
+            full[b] = std::min({2 * c.lblk[b].row_nodes, 2 * c.lblk[b].col_nodes, kAcaMaxRank});
         }
-        DBuf<zd> ws;
-        ws.alloc(off);
-        DBuf<unsigned char> used;
-        used.alloc(uoff);
-        DBuf<AcaJob> d_jobs;
-        d_jobs.upload(jobs, c.stream);
-        DBuf<int> d_rank, d_flag;
-        d_rank.alloc(nb);
-        d_flag.alloc(nb);
-        k_aca<<<nb, 256, 0, c.stream>>>(d_jobs.p, nb, c.d_tree_node.p, c.nd, c.d_objs.p, tol, ws.p, used.p,
-                                        d_rank.p, d_flag.p);
-        check_launch("k_aca");
-        std::vector<int> flag(nb);
-        d_rank.download(c.lr.rank.data(), nb, c.stream);
-        d_flag.download(flag.data(), nb, c.stream);
-        c.sync();
+        width = full;
+        if (mode == CBIE_RANK_PREDICTED) {
+            // widths from the network's predicted log-ranks
+            std::vector<float> f;
+            block_features(c, tol, f);
+            const auto& M = c.rank_model;
+            DBuf<float> dp, dm, ds, dx, dy;
+            dp.upload(M.params, c.stream);
+            dm.upload(M.mean, c.stream);
+            ds.upload(M.sdev, c.stream);
+            dx.upload(f, c.stream);
+            dy.alloc(nb);
+            mlp_forward(c.stream, dp.p, dm.p, ds.p, dx.p, nb, dy.p);
+            std::vector<float> y(nb);
+            dy.download(y.data(), nb, c.stream);
+            c.sync();
+            for (int b = 0; b < nb; ++b) {
+                const double r = std::ceil(std::exp((double)std::min(y[b], 20.f)) * (1.0 + M.margin)) + 2.0;
+                width[b] = (int)std::min<double>(full[b], std::max(8.0, r));
+            }
+        }
+        AcaPass P;
+        aca_pass(c, tol, all, width, P);
+        double ws_bytes = (double)P.ws_elems * sizeof(zd);
+        // blocks that filled a predicted width without converging: full width
+        std::vector<int> redo, redo_w;
+        for (int b = 0; b < nb; ++b)
+            if (!P.flag[b] && P.rank[b] == width[b] && width[b] < full[b]) {
+                redo.push_back(b);
+                redo_w.push_back(full[b]);
+            }
+        AcaPass R;
+        std::vector<int> src(nb, -1);   // block -> job in the redo pass
+        if (!redo.empty()) {
+            aca_pass(c, tol, redo, redo_w, R);
+            ws_bytes += (double)R.ws_elems * sizeof(zd);
+            for (size_t q = 0; q < redo.size(); ++q) src[redo[q]] = (int)q;
+        }
+        c.stats.aca_fallbacks = (int64_t)redo.size();
+        c.stats.aca_workspace_bytes = ws_bytes;
         int64_t so = 0;
         for (int b = 0; b < nb; ++b) {
             const int64_t m = 2 * (int64_t)c.lblk[b].row_nodes, n = 2 * (int64_t)c.lblk[b].col_nodes;
-            const int r = c.lr.rank[b];
+            const int r = src[b] >= 0 ? R.rank[src[b]] : P.rank[b];
+            const int fl = src[b] >= 0 ? R.flag[src[b]] : P.flag[b];
+            c.lr.rank[b] = r;
             c.lr.cap[b] = r;
             c.lr.u_off[b] = so;
             so += m * r;
@@ -295,15 +358,34 @@ void stage_compress(Ctx& c, double tol, int mode) {
             lr_entries += (m + n) * r;
             max_rank = std::max<int64_t>(max_rank, r);
             sum_rank += r;
-            c.stats_unconverged += flag[b] ? 0 : 1;
+            c.stats_unconverged += fl ? 0 : 1;
         }
         c.lr.mem.alloc(std::max<int64_t>(so, 1));
-        DBuf<int64_t> du, dv;
-        du.upload(c.lr.u_off, c.stream);
-        dv.upload(c.lr.v_off, c.stream);
-        dim3 grid(32, nb);
-        k_lr_compact<<<grid, 256, 0, c.stream>>>(d_jobs.p, nb, ws.p, d_rank.p, du.p, dv.p, c.lr.mem.p);
-        check_launch("k_lr_compact");
+        // compact both passes' factors (the redone blocks from the second)
+        auto compact = [&](AcaPass& Q, const std::vector<int>& blocks, bool second) {
+            const int nq = (int)blocks.size();
+            if (nq == 0) return;
+            std::vector<int64_t> uo(nq), vo(nq);
+            std::vector<int> rk(nq);
+            for (int q = 0; q < nq; ++q) {
+                const int b = blocks[q];
+                const bool mine = second ? true : src[b] < 0;
+                uo[q] = c.lr.u_off[b];
+                vo[q] = c.lr.v_off[b];
+                rk[q] = mine ? c.lr.rank[b] : 0;
+            }
+            DBuf<int64_t> du, dv;
+            DBuf<int> dr;
+            du.upload(uo, c.stream);
+            dv.upload(vo, c.stream);
+            dr.upload(rk, c.stream);
+            dim3 grid(32, nq);
+            k_lr_compact<<<grid, 256, 0, c.stream>>>(Q.d_jobs.p, nq, Q.ws.p, dr.p, du.p, dv.p, c.lr.mem.p);
+            check_launch("k_lr_compact");
+            c.sync();
+        };
+        compact(P, all, false);
+        compact(R, redo, true);
         c.lr.d_u_off.upload(c.lr.u_off, c.stream);
         c.lr.d_v_off.upload(c.lr.v_off, c.stream);
         c.lr.d_rank.upload(c.lr.rank, c.stream);

@@ -1,7 +1,9 @@
 // C-ABI entry points: argument checks, state machine, error capture.
+#include <cmath>
 #include <cstring>
 
 #include "ctx.hpp"
+#include "mlp.hpp"
 
 struct cbie_ctx {
     cbie::Ctx c;
@@ -30,6 +32,20 @@ template <typename F> static cbie_status guarded(cbie_ctx* ctx, F&& f) {
         return CBIE_ENOMEM;
     } catch (const std::exception& e) {
         ctx->c.err = std::string("internal: ") + e.what();
+        return CBIE_EINTERNAL;
+    }
+}
+
+// entry points on a bare stream: no context holds an error message
+template <typename F> static cbie_status guarded_stream(F&& f) {
+    try {
+        f();
+        return CBIE_OK;
+    } catch (const Error& e) {
+        return (cbie_status)e.code;
+    } catch (const std::bad_alloc&) {
+        return CBIE_ENOMEM;
+    } catch (const std::exception&) {
         return CBIE_EINTERNAL;
     }
 }
@@ -218,6 +234,64 @@ cbie_status cbie_export_dense(cbie_ctx* ctx, void* a_dev, long ld) {
         CBIE_REQUIRE(a_dev && ld >= c.n_unk, CBIE_EINVAL, "export arguments");
         stage_export_dense(c, (zd*)a_dev, ld);
     });
+}
+
+cbie_status cbie_get_block_features(cbie_ctx* ctx, double aca_tol, int64_t cap, float* feat, int32_t* ranks,
+                                    int64_t* count_out) {
+    return guarded(ctx, [&](Ctx& c) {
+        CBIE_REQUIRE(c.state >= ST_TREE, CBIE_ESTATE, "features before build_tree");
+        CBIE_REQUIRE(count_out && cap >= 0 && aca_tol > 0 && aca_tol < 1, CBIE_EINVAL, "feature arguments");
+        const int64_t nb = (int64_t)c.lblk.size();
+        *count_out = nb;
+        const int64_t m = std::min(cap, nb);
+        if (feat && m > 0) {
+            std::vector<float> f;
+            block_features(c, aca_tol, f);
+            std::memcpy(feat, f.data(), (size_t)m * kMlpIn * sizeof(float));
+        }
+        if (ranks)
+            for (int64_t b = 0; b < m; ++b)
+                ranks[b] = (c.state >= ST_COMPRESSED && (int64_t)c.lr.rank.size() == nb) ? c.lr.rank[b] : -1;
+    });
+}
+
+cbie_status cbie_set_rank_model(cbie_ctx* ctx, const float* params, const float* mean, const float* sdev,
+                                float margin) {
+    return guarded(ctx, [&](Ctx& c) {
+        CBIE_REQUIRE(params && mean && sdev && margin >= 0 && margin < 100, CBIE_EINVAL, "rank model arguments");
+        for (int k = 0; k < kMlpIn; ++k)
+            CBIE_REQUIRE(sdev[k] > 0 && std::isfinite(mean[k]), CBIE_EINVAL, "feature scaling");
+        for (int e = 0; e < kMlpParams; ++e) CBIE_REQUIRE(std::isfinite(params[e]), CBIE_EINVAL, "parameters");
+        auto& M = c.rank_model;
+        M.params.assign(params, params + kMlpParams);
+        M.mean.assign(mean, mean + kMlpIn);
+        M.sdev.assign(sdev, sdev + kMlpIn);
+        M.margin = margin;
+        M.set = true;
+    });
+}
+
+cbie_status cbie_mlp_forward(void* hip_stream, const float* params, const float* mean, const float* sdev,
+                             const float* X, int64_t n, float* y) {
+    if (n < 0 || (n > 0 && (!params || !mean || !sdev || !X || !y))) return CBIE_EINVAL;
+    return guarded_stream([&] { mlp_forward((hipStream_t)hip_stream, params, mean, sdev, X, n, y); });
+}
+
+cbie_status cbie_mlp_grad(void* hip_stream, const float* params, const float* mean, const float* sdev,
+                          const float* X, const float* t, int64_t n, float* grad, float* loss) {
+    if (n <= 0 || !params || !mean || !sdev || !X || !t || !grad || !loss) return CBIE_EINVAL;
+    return guarded_stream([&] { mlp_grad((hipStream_t)hip_stream, params, mean, sdev, X, t, n, grad, loss); });
+}
+
+cbie_status cbie_mlp_train(void* hip_stream, float* params, const float* mean, const float* sdev, const float* X,
+                           const float* t, const int32_t* order, int64_t nsteps, int batch, float lr,
+                           float* losses) {
+    if (nsteps < 0 || batch <= 0 || !(lr > 0) || !params || !mean || !sdev || !X || !t || !order ||
+        (nsteps > 0 && !losses))
+        return CBIE_EINVAL;
+    if (nsteps == 0) return CBIE_OK;
+    return guarded_stream(
+        [&] { mlp_train((hipStream_t)hip_stream, params, mean, sdev, X, t, order, nsteps, batch, lr, losses); });
 }
 
 const char* cbie_last_error(const cbie_ctx* ctx) {

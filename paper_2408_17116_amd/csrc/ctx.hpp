@@ -78,9 +78,20 @@ struct Ctx {
     DBuf<int64_t> d_mv_tmp_off;
     DBuf<zd> mv_tmp;
     int mv_tmp_nrhs = 0;
+    // bumped whenever the low-rank ranks change (compress); the matvec
+    // scratch layout above is valid for one version only
+    int64_t lr_version = 0, mv_tmp_version = -1;
 
     // factorization
     std::shared_ptr<HMat> hm;   // type-erased deleter: HMat stays incomplete here
+
+    // rank predictor for compress(CBIE_RANK_PREDICTED): parameters, feature
+    // mean and standard deviation, allocation margin
+    struct RankModel {
+        bool set = false;
+        std::vector<float> params, mean, sdev;
+        float margin = 0.25f;
+    } rank_model;
 
     // statistics
     cbie_stats stats{};

@@ -158,7 +158,7 @@ void apply_operator_tree(Ctx& c, int nrhs, const zd* xt, zd* yt) {
     }
     const int nl = (int)c.lblk.size();
     if (nl > 0) {
-        if (c.mv_tmp_off.size() != (size_t)nl || c.mv_tmp_nrhs != nrhs) {
+        if (c.mv_tmp_version != c.lr_version || c.mv_tmp_off.size() != (size_t)nl || c.mv_tmp_nrhs != nrhs) {
             std::vector<int64_t> off(nl);
             int64_t o = 0;
             for (int b = 0; b < nl; ++b) { off[b] = o; o += (int64_t)c.lr.rank[b] * nrhs; }
@@ -166,6 +166,7 @@ void apply_operator_tree(Ctx& c, int nrhs, const zd* xt, zd* yt) {
             c.d_mv_tmp_off.upload(off, c.stream);
             c.mv_tmp.alloc(std::max<int64_t>(o, 1));
             c.mv_tmp_nrhs = nrhs;
+            c.mv_tmp_version = c.lr_version;
         }
         int maxr = 1, maxm = 0;
         for (int b = 0; b < nl; ++b) {

@@ -79,3 +79,21 @@ def test_no_near_pair_in_low_rank_blocks_and_full_cover():
     N = A.shape[0]
     assert st["dense_entries"] <= N * N
     assert st["n_near_pairs"] > 0
+
+
+def test_matvec_after_recompression_at_other_tolerances():
+    """The matvec's per-block scratch layout depends on the ranks: after a
+    new compress (ranks larger, then smaller) the product must still equal
+    the compressed matrix applied densely."""
+    import torch
+    spec = W.tiny_sphere(s=4, q=4, k0=6.0)
+    s, _ = _filled(spec, leaf=64, tol=1e-4)
+    x = torch.from_numpy(W.random_complex((s.n, 2), seed=4)).cuda()
+    s.matvec(x)
+    for tol in (1e-9, 1e-3, 1e-7):
+        s.compress(tol)
+        y = s.matvec(x)
+        yd = s.export_dense() @ x
+        err = (torch.linalg.norm(y - yd) / torch.linalg.norm(yd)).item()
+        print(f"tol {tol:g}: max rank {s.stats()['max_rank']}, matvec vs dense {err:.1e}")
+        assert err < 1e-13
