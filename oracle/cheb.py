@@ -86,6 +86,24 @@ def lagrange_basis(q: int, u) -> np.ndarray:
     return np.einsum("n,nl,n...->l...", a / q, Tn_nodes, Tn_u)
 
 
+def lagrange_deriv(q: int, u) -> np.ndarray:
+    """ell_l'(u) for l = 0..q-1 at points u in (-1, 1); shape (q, *u).
+    Uses T_n'(x) = n U_{n-1}(x)."""
+    x, _ = fejer1(q)
+    a = alpha(q)
+    Tn_nodes = cheb_T(q, x)          # [n, l]
+    u = np.asarray(u, dtype=float)
+    U = np.empty((q + 1,) + u.shape)
+    U[0] = 1.0
+    U[1] = 2 * u
+    for n in range(2, q + 1):
+        U[n] = 2 * u * U[n - 1] - U[n - 2]
+    dT = np.zeros((q,) + u.shape)
+    for n in range(1, q):
+        dT[n] = n * U[n - 1]
+    return np.einsum("n,nl,n...->l...", a / q, Tn_nodes, dT)
+
+
 def diff_matrix(q: int) -> np.ndarray:
     """D[l', l] = ell_l'(u_l'): derivative of the interpolant at the nodes.
     Uses T_n'(x) = n U_{n-1}(x)."""

@@ -12,7 +12,14 @@ scattered  E_s = sum_n E_n (i a_n N_e1n^(3) - b_n M_o1n^(3)),
 Perfect conductor: tangential E vanishes at r = a, which gives
 a_n = psi_n'(x) / xi_n'(x), b_n = psi_n(x) / xi_n(x) with
 psi_n = rho j_n, xi_n = rho h_n^(1), x = k a.
-Surface current J = r_hat x H at r = a.
+Homogeneous dielectric sphere (relative eps_r, mu_r, index m = sqrt(eps_r mu_r)):
+continuity of tangential E and H at r = a (B&H eq. 4.53 written with psi, xi)
+a_n = (m psi_n(mx) psi_n'(x) - mu_r psi_n(x) psi_n'(mx))
+      / (m psi_n(mx) xi_n'(x) - mu_r xi_n(x) psi_n'(mx)),
+b_n = (mu_r psi_n(mx) psi_n'(x) - m psi_n(x) psi_n'(mx))
+      / (mu_r psi_n(mx) xi_n'(x) - m xi_n(x) psi_n'(mx)),
+which tend to the conductor's as m -> infinity.
+Surface currents J = r_hat x H and M = E x r_hat at r = a (outside).
 Truncation after n_max = x + 4 x^(1/3) + 2 terms (Wiscombe), plus a margin.
 """
 from __future__ import annotations
@@ -45,6 +52,21 @@ def pec_coefficients(x: float):
     return dpsi / dxi, psi / xi
 
 
+def dielectric_coefficients(x: float, eps_r, mu_r=1.0):
+    nmax = n_terms(x)
+    m = np.sqrt(complex(eps_r) * complex(mu_r))
+    if abs(m.imag) < 1e-15:
+        m = m.real
+    mu_r = complex(mu_r).real if abs(complex(mu_r).imag) < 1e-15 else complex(mu_r)
+    psi, dpsi, xi, dxi = riccati(nmax, x)
+    n = np.arange(1, nmax + 1)
+    pm = m * x * spherical_jn(n, m * x)
+    dpm = spherical_jn(n, m * x) + m * x * spherical_jn(n, m * x, derivative=True)
+    an = (m * pm * dpsi - mu_r * psi * dpm) / (m * pm * dxi - mu_r * xi * dpm)
+    bn = (mu_r * pm * dpsi - m * psi * dpm) / (mu_r * pm * dxi - m * xi * dpm)
+    return an, bn
+
+
 def pi_tau(n_max, mu):
     """Angular functions pi_n, tau_n (n = 1..n_max) at mu = cos(theta)."""
     mu = np.asarray(mu, dtype=float)
@@ -73,11 +95,12 @@ def _basis(th, ph):
     return er, et, ep
 
 
-def _fields_bh(k, a, r, which):
+def _fields_bh(k, a, r, which, coef=None):
     """Total E and H (B&H convention) at points r, outside or on the sphere.
-    which = 'H' or 'E'.  Returns complex (..., 3)."""
+    which = 'H' or 'E'; coef = (a_n, b_n), the conductor's by default.
+    Returns complex (..., 3)."""
     x = k * a
-    an, bn = pec_coefficients(x)
+    an, bn = pec_coefficients(x) if coef is None else coef
     nmax = an.size
     n = np.arange(1, nmax + 1)
     En = (1j ** n) * (2 * n + 1) / (n * (n + 1))
@@ -129,6 +152,28 @@ def pec_surface_current(k, a, r):
     return np.conj(J)
 
 
+def dielectric_surface_currents(k, a, eps_r, mu_r, r):
+    """(J, M) = (n x H_1, E_1 x n) on the sphere |r| = a at points r
+    (..., 3), exterior total fields, e^{j w t} convention."""
+    r = np.asarray(r, dtype=float)
+    coef = dielectric_coefficients(k * a, eps_r, mu_r)
+    H = _fields_bh(k, a, r, "H", coef)
+    E = _fields_bh(k, a, r, "E", coef)
+    n = r / np.linalg.norm(r, axis=-1, keepdims=True)
+    return np.conj(np.cross(n, H)), np.conj(np.cross(E, n))
+
+
+def dielectric_amplitudes(k, a, eps_r, mu_r, theta):
+    an, bn = dielectric_coefficients(k * a, eps_r, mu_r)
+    return _amplitudes(an, bn, theta)
+
+
+def dielectric_rcs(k, a, eps_r, mu_r, theta):
+    """Bistatic RCS (phi = 0, phi = 90 deg) of the dielectric sphere."""
+    S1, S2 = dielectric_amplitudes(k, a, eps_r, mu_r, theta)
+    return 4 * np.pi * np.abs(S2) ** 2 / k ** 2, 4 * np.pi * np.abs(S1) ** 2 / k ** 2
+
+
 def pec_total_field(k, a, r, which="E"):
     """Total E or H (e^{j w t} convention) at points r with |r| >= a."""
     return np.conj(_fields_bh(k, a, np.asarray(r, dtype=float), which))
@@ -137,6 +182,10 @@ def pec_total_field(k, a, r, which="E"):
 def pec_amplitudes(k, a, theta):
     """S1, S2 at scattering angles theta (B&H eq. 4.74)."""
     an, bn = pec_coefficients(k * a)
+    return _amplitudes(an, bn, theta)
+
+
+def _amplitudes(an, bn, theta):
     nmax = an.size
     n = np.arange(1, nmax + 1)
     pi, tau = pi_tau(nmax, np.cos(theta))
