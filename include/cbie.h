@@ -74,13 +74,19 @@ typedef struct {
 } cbie_patch;
 
 typedef struct {
-    cbie_formulation form;     /* only CBIE_MFIE_PEC is implemented          */
+    cbie_formulation form;     /* CBIE_MFIE_PEC (perfect conductor, 2 unknowns
+                                  per node) or CBIE_NMULLER (homogeneous
+                                  dielectric, 4 unknowns per node); every
+                                  object of a context has the same form   */
     double k0;                 /* exterior wavenumber, rad/m, > 0           */
     double axes[3];            /* ellipsoid semi-axes, > 0                   */
     double center[3];
     int q;                     /* Chebyshev points per direction, 2..8       */
     int n_patches;
     const cbie_patch* patches; /* host array of n_patches, copied at create  */
+    double eps_r, mu_r;        /* N-Mueller: interior relative permittivity and
+                                  permeability (real, > 0; the exterior is
+                                  vacuum); ignored for CBIE_MFIE_PEC        */
 } cbie_object;
 
 /* Create a context for n_objs independent objects (block-diagonal system,

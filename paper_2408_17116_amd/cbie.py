@@ -43,7 +43,7 @@ class _Patch(C.Structure):
 class _Object(C.Structure):
     _fields_ = [("form", C.c_int), ("k0", C.c_double), ("axes", C.c_double * 3),
                 ("center", C.c_double * 3), ("q", C.c_int), ("n_patches", C.c_int),
-                ("patches", C.POINTER(_Patch))]
+                ("patches", C.POINTER(_Patch)), ("eps_r", C.c_double), ("mu_r", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -128,6 +128,11 @@ class Solver:
             objs[o].q = spec.q
             objs[o].n_patches = len(pts)
             objs[o].patches = arr
+            eps, mu = complex(getattr(spec, "eps_r", 1.0)), complex(getattr(spec, "mu_r", 1.0))
+            if eps.imag != 0 or mu.imag != 0:
+                raise ValueError("lossless interior materials only (real eps_r, mu_r)")
+            objs[o].eps_r = eps.real
+            objs[o].mu_r = mu.real
         self.n = sum(s.n_unknowns for s in objects)
         if stream is None:
             stream = torch.cuda.current_stream()

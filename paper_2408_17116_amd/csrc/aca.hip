@@ -69,17 +69,20 @@ __device__ inline void far_pair(const NodeArrays& nd, double k, int gi, int gj, 
 //   v_k = r / r[j_k]; u_k = residual column j_k (written into U[:, k]);
 //   |S_k|^2 += 2 Re sum_{l<k} (u_l^H u_k)(v_l^H v_k) + |u_k|^2 |v_k|^2;
 //   stop when |u_k| |v_k| <= tol |S_k|, else i_{k+1} = argmax |u_k| over
-//   unused rows.  Columns are generated on the fly from the far rule (an
-//   admissible block holds no near pair).
+//   unused rows.  MFIE entries are generated on the fly from the far rule
+//   (an admissible block holds no near pair); with `dense` set, the block
+//   is read from its explicit copy (column-major m x n at J.a_off).
 __global__ __launch_bounds__(256) void k_aca(const AcaJob* __restrict__ jobs, int n_jobs,
                                              const int* __restrict__ tree_node, NodeArrays nd,
                                              const ObjDev* __restrict__ objs, double tol,
                                              zd* __restrict__ ws, unsigned char* __restrict__ used_ws,
-                                             int* __restrict__ rank_out, int* __restrict__ flag_out) {
+                                             int* __restrict__ rank_out, int* __restrict__ flag_out,
+                                             const zd* __restrict__ dense) {
     const int jb = blockIdx.x;
     if (jb >= n_jobs) return;
     const AcaJob J = jobs[jb];
-    const int m = 2 * J.row_nodes, n = 2 * J.col_nodes;
+    const int m = J.upn * J.row_nodes, n = J.upn * J.col_nodes;
+    const zd* A = dense ? dense + J.a_off : nullptr;
     zd* U = ws + J.u_off;   // m x cap
     zd* V = ws + J.v_off;   // n x cap
     unsigned char* used = used_ws + J.used_off;
@@ -102,20 +105,29 @@ __global__ __launch_bounds__(256) void k_aca(const AcaJob* __restrict__ jobs, in
         for (int l = tid; l < rank; l += 256) s_coef[l] = U[(int64_t)l * m + irow];
         if (tid == 0) used[irow] = 1;
         __syncthreads();
-        const int gi = tree_node[J.row_node0 + irow / 2];
-        const int b = irow & 1;
         zd* vk = V + (int64_t)rank * n;
         ArgMax am{-1.0, 0x7fffffff};
-        for (int jn = tid; jn < J.col_nodes; jn += 256) {
-            const int gj = tree_node[J.col_node0 + jn];
-            zd K[2][2];
-            far_pair(nd, k0, gi, gj, K);
-            for (int a = 0; a < 2; ++a) {
-                const int j = 2 * jn + a;
-                zd r = K[b][a];
+        if (A) {
+            for (int j = tid; j < n; j += 256) {
+                zd r = A[(int64_t)j * m + irow];
                 for (int l = 0; l < rank; ++l) r = r - s_coef[l] * V[(int64_t)l * n + j];
                 vk[j] = r;
                 am = better(am, ArgMax{abs2(r), j});
+            }
+        } else {
+            const int gi = tree_node[J.row_node0 + irow / 2];
+            const int b = irow & 1;
+            for (int jn = tid; jn < J.col_nodes; jn += 256) {
+                const int gj = tree_node[J.col_node0 + jn];
+                zd K[2][2];
+                far_pair(nd, k0, gi, gj, K);
+                for (int a = 0; a < 2; ++a) {
+                    const int j = 2 * jn + a;
+                    zd r = K[b][a];
+                    for (int l = 0; l < rank; ++l) r = r - s_coef[l] * V[(int64_t)l * n + j];
+                    vk[j] = r;
+                    am = better(am, ArgMax{abs2(r), j});
+                }
             }
         }
         am = block_argmax(am, sh_am);
@@ -138,22 +150,32 @@ __global__ __launch_bounds__(256) void k_aca(const AcaJob* __restrict__ jobs, in
         for (int l = tid; l < rank; l += 256) s_coef[l] = V[(int64_t)l * n + jp];
         __syncthreads();
         // residual column jp into U[:, rank]
-        const int gj = tree_node[J.col_node0 + jp / 2];
-        const int a = jp & 1;
         zd* uk = U + (int64_t)rank * m;
         ArgMax nx{-1.0, 0x7fffffff};
         double nu2 = 0.0;
-        for (int in = tid; in < J.row_nodes; in += 256) {
-            const int gi2 = tree_node[J.row_node0 + in];
-            zd K[2][2];
-            far_pair(nd, k0, gi2, gj, K);
-            for (int bb = 0; bb < 2; ++bb) {
-                const int i = 2 * in + bb;
-                zd c = K[bb][a];
+        if (A) {
+            for (int i = tid; i < m; i += 256) {
+                zd c = A[(int64_t)jp * m + i];
                 for (int l = 0; l < rank; ++l) c = c - s_coef[l] * U[(int64_t)l * m + i];
                 uk[i] = c;
                 nu2 += abs2(c);
                 if (!used[i]) nx = better(nx, ArgMax{abs2(c), i});
+            }
+        } else {
+            const int gj = tree_node[J.col_node0 + jp / 2];
+            const int a = jp & 1;
+            for (int in = tid; in < J.row_nodes; in += 256) {
+                const int gi2 = tree_node[J.row_node0 + in];
+                zd K[2][2];
+                far_pair(nd, k0, gi2, gj, K);
+                for (int bb = 0; bb < 2; ++bb) {
+                    const int i = 2 * in + bb;
+                    zd c = K[bb][a];
+                    for (int l = 0; l < rank; ++l) c = c - s_coef[l] * U[(int64_t)l * m + i];
+                    uk[i] = c;
+                    nu2 += abs2(c);
+                    if (!used[i]) nx = better(nx, ArgMax{abs2(c), i});
+                }
             }
         }
         double nv2 = 0.0;
@@ -206,7 +228,7 @@ __global__ void k_lr_compact(const AcaJob* __restrict__ jobs, int n_jobs, const 
     const int jb = blockIdx.y;
     if (jb >= n_jobs) return;
     const AcaJob J = jobs[jb];
-    const int64_t m = 2 * (int64_t)J.row_nodes, n = 2 * (int64_t)J.col_nodes, r = rank[jb];
+    const int64_t m = J.upn * (int64_t)J.row_nodes, n = J.upn * (int64_t)J.col_nodes, r = rank[jb];
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < (m + n) * r;
          e += (int64_t)gridDim.x * blockDim.x) {
         if (e < m * r) store[u_dst[jb] + e] = ws[J.u_off + e];
@@ -222,7 +244,7 @@ __global__ void k_export_lr(const DenseBlockDev* __restrict__ blocks, int n_bloc
     const int bid = blockIdx.y;
     if (bid >= n_blocks) return;
     const DenseBlockDev B = blocks[bid];
-    const int64_t m = 2 * (int64_t)B.row_nodes, n = 2 * (int64_t)B.col_nodes;
+    const int64_t m = B.upn * (int64_t)B.row_nodes, n = B.upn * (int64_t)B.col_nodes;
     const int r = rank[bid];
     const zd* U = store + u_off[bid];
     const zd* V = store + v_off[bid];
@@ -231,8 +253,8 @@ __global__ void k_export_lr(const DenseBlockDev* __restrict__ blocks, int n_bloc
         const int64_t i = e % m, j = e / m;
         zd s{0.0, 0.0};
         for (int l = 0; l < r; ++l) cfma(s, U[l * m + i], V[l * n + j]);
-        const int64_t gr = 2 * (int64_t)tree_node[B.row_node0 + i / 2] + (i & 1);
-        const int64_t gc = 2 * (int64_t)tree_node[B.col_node0 + j / 2] + (j & 1);
+        const int64_t gr = B.upn * (int64_t)tree_node[B.row_node0 + i / B.upn] + (i % B.upn);
+        const int64_t gc = B.upn * (int64_t)tree_node[B.col_node0 + j / B.upn] + (j % B.upn);
         A[gc * lda + gr] = s;
     }
 }
@@ -260,7 +282,8 @@ static void aca_pass(Ctx& c, double tol, const std::vector<int>& blocks, const s
         J.col_node0 = d.col_node0;
         J.col_nodes = d.col_nodes;
         J.obj = d.obj;
-        const int m = 2 * d.row_nodes, n = 2 * d.col_nodes;
+        J.upn = d.upn;
+        const int m = d.upn * d.row_nodes, n = d.upn * d.col_nodes;
         J.cap = width[q];
         J.u_off = off;
         off += (int64_t)m * J.cap;
@@ -272,12 +295,50 @@ static void aca_pass(Ctx& c, double tol, const std::vector<int>& blocks, const s
     P.ws_elems = off;
     P.ws.alloc(std::max<int64_t>(off, 1));
     P.used.alloc(std::max<int64_t>(uoff, 1));
-    P.d_jobs.upload(P.jobs, c.stream);
     P.d_rank.alloc(std::max(nb, 1));
     P.d_flag.alloc(std::max(nb, 1));
-    k_aca<<<nb, 256, 0, c.stream>>>(P.d_jobs.p, nb, c.d_tree_node.p, c.nd, c.d_objs.p, tol, P.ws.p, P.used.p,
-                                    P.d_rank.p, P.d_flag.p);
-    check_launch("k_aca");
+    if (c.upn == 2) {
+        P.d_jobs.upload(P.jobs, c.stream);
+        k_aca<<<nb, 256, 0, c.stream>>>(P.d_jobs.p, nb, c.d_tree_node.p, c.nd, c.d_objs.p, tol, P.ws.p, P.used.p,
+                                        P.d_rank.p, P.d_flag.p, nullptr);
+        check_launch("k_aca");
+    } else {
+        // N-Mueller: the blocks are filled explicitly (the surface divergence
+        // couples whole source patches), in rounds of at most kAcaDense
+        // entries, and compressed from their copies.
+        DBuf<zd> dense;
+        int q0 = 0;
+        while (q0 < nb) {
+            int q1 = q0;
+            int64_t tot = 0;
+            std::vector<DenseBlockDev> blk;
+            while (q1 < nb) {
+                const DenseBlockDev& d = c.lblk[blocks[q1]];
+                const int64_t e = (int64_t)c.upn * d.row_nodes * c.upn * d.col_nodes;
+                if (q1 > q0 && tot + e > kAcaDense) break;
+                DenseBlockDev x = d;
+                x.offset = tot;
+                x.ld = c.upn * d.row_nodes;
+                blk.push_back(x);
+                P.jobs[q1].a_off = tot;
+                tot += e;
+                ++q1;
+            }
+            if ((int64_t)dense.n < tot) dense.alloc(tot);
+            DBuf<DenseBlockDev> d_blk;
+            d_blk.upload(blk, c.stream);
+            fill_blocks_nm(c, blk, d_blk.p, dense.p);
+            DBuf<AcaJob> d_sub;
+            std::vector<AcaJob> sub(P.jobs.begin() + q0, P.jobs.begin() + q1);
+            d_sub.upload(sub, c.stream);
+            k_aca<<<q1 - q0, 256, 0, c.stream>>>(d_sub.p, q1 - q0, c.d_tree_node.p, c.nd, c.d_objs.p, tol, P.ws.p,
+                                                 P.used.p, P.d_rank.p + q0, P.d_flag.p + q0, dense.p);
+            check_launch("k_aca");
+            c.sync();
+            q0 = q1;
+        }
+        P.d_jobs.upload(P.jobs, c.stream);
+    }
     P.rank.resize(nb);
     P.flag.resize(nb);
     P.d_rank.download(P.rank.data(), nb, c.stream);
@@ -302,7 +363,7 @@ void stage_compress(Ctx& c, double tol, int mode) {
         std::vector<int> all(nb), full(nb), width(nb);
         for (int b = 0; b < nb; ++b) {
             all[b] = b;
-            full[b] = std::min({2 * c.lblk[b].row_nodes, 2 * c.lblk[b].col_nodes, kAcaMaxRank});
+            full[b] = std::min({c.upn * c.lblk[b].row_nodes, c.upn * c.lblk[b].col_nodes, kAcaMaxRank});
         }
         width = full;
         if (mode == CBIE_RANK_PREDICTED) {
@@ -346,7 +407,7 @@ void stage_compress(Ctx& c, double tol, int mode) {
         c.stats.aca_workspace_bytes = ws_bytes;
         int64_t so = 0;
         for (int b = 0; b < nb; ++b) {
-            const int64_t m = 2 * (int64_t)c.lblk[b].row_nodes, n = 2 * (int64_t)c.lblk[b].col_nodes;
+            const int64_t m = c.upn * (int64_t)c.lblk[b].row_nodes, n = c.upn * (int64_t)c.lblk[b].col_nodes;
             const int r = src[b] >= 0 ? R.rank[src[b]] : P.rank[b];
             const int fl = src[b] >= 0 ? R.flag[src[b]] : P.flag[b];
             c.lr.rank[b] = r;
@@ -397,7 +458,7 @@ void stage_compress(Ctx& c, double tol, int mode) {
     st.sum_rank = sum_rank;
     const double N = (double)c.n_unk;
     double full = 0.0;
-    for (size_t o = 0; o < c.objs.size(); ++o) full += 4.0 * (double)c.obj_nodes[o] * c.obj_nodes[o];
+    for (size_t o = 0; o < c.objs.size(); ++o) full += (double)c.upn * c.upn * c.obj_nodes[o] * c.obj_nodes[o];
     st.compression_rate = 1.0 - (double)(st.dense_entries + lr_entries) / full;
     (void)N;
     st.t_compress = now_s() - t0;

@@ -57,7 +57,11 @@ cbie_status cbie_create(const cbie_object* objs, int n_objs, void* hip_stream, c
     *out = nullptr;
     for (int o = 0; o < n_objs; ++o) {
         const cbie_object& ob = objs[o];
-        if (ob.form != CBIE_MFIE_PEC) return CBIE_EINVAL;
+        if (ob.form != CBIE_MFIE_PEC && ob.form != CBIE_NMULLER) return CBIE_EINVAL;
+        if (ob.form != objs[0].form) return CBIE_EINVAL;
+        if (ob.form == CBIE_NMULLER &&
+            !(ob.eps_r > 0 && ob.mu_r > 0 && std::isfinite(ob.eps_r) && std::isfinite(ob.mu_r)))
+            return CBIE_EINVAL;
         if (!(ob.k0 > 0) || ob.q < 2 || ob.q > 8 || ob.n_patches <= 0 || !ob.patches) return CBIE_EINVAL;
         for (int d = 0; d < 3; ++d)
             if (!(ob.axes[d] > 0)) return CBIE_EINVAL;
@@ -85,6 +89,8 @@ cbie_status cbie_create(const cbie_object* objs, int n_objs, void* hip_stream, c
             od.k0 = ob.k0;
             od.q = ob.q;
             od.form = ob.form;
+            od.eps_r = ob.form == CBIE_NMULLER ? ob.eps_r : 1.0;
+            od.mu_r = ob.form == CBIE_NMULLER ? ob.mu_r : 1.0;
             c.objs.push_back(od);
             c.obj_patch0.push_back((int)c.patches.size());
             c.obj_npatch.push_back(ob.n_patches);
@@ -106,7 +112,8 @@ cbie_status cbie_create(const cbie_object* objs, int n_objs, void* hip_stream, c
         }
         CBIE_REQUIRE(node < (1 << 30), CBIE_EINVAL, "too many nodes");
         c.n_nodes = node;
-        c.n_unk = 2 * (int64_t)node;
+        c.upn = objs[0].form == CBIE_NMULLER ? 4 : 2;
+        c.n_unk = c.upn * (int64_t)node;
         c.d_patches.upload(c.patches, c.stream);
         c.d_objs.upload(c.objs, c.stream);
         c.d_node_patch.upload(c.node_patch, c.stream);
@@ -128,8 +135,8 @@ cbie_status cbie_build_tree(cbie_ctx* ctx, int leaf_size, double eta, double nea
     return guarded(ctx, [&](Ctx& c) {
         int qmax = 0;
         for (const auto& o : c.objs) qmax = std::max(qmax, o.q);
-        CBIE_REQUIRE(leaf_size >= 2 * qmax * qmax && eta > 0 && near_delta > 0, CBIE_EINVAL,
-                     "leaf_size < 2 q^2, eta <= 0 or near_delta <= 0");
+        CBIE_REQUIRE(leaf_size >= c.upn * qmax * qmax && leaf_size <= 256 && eta > 0 && near_delta > 0,
+                     CBIE_EINVAL, "leaf_size outside [unknowns of one patch, 256], eta <= 0 or near_delta <= 0");
         c.hm.reset();
         stage_build_tree(c, leaf_size, eta, near_delta);
         c.state = ST_TREE;

@@ -38,12 +38,14 @@ struct Ctx {
     std::vector<int> node_patch;            // original node -> original patch
     int n_nodes = 0;
     int64_t n_unk = 0;
+    int upn = 2;                            // unknowns per node: 2 (MFIE) or 4 (N-Mueller)
 
     // device problem tables
     DBuf<PatchDev> d_patches;
     DBuf<ObjDev> d_objs;
     DBuf<int> d_node_patch, d_obj_patch0, d_obj_npatch;
     DBuf<double> d_fej11_x, d_fej11_w, d_fej01_x, d_fej01_w;
+    DBuf<double> d_dmat;                    // Chebyshev differentiation matrices, q = 1..8
 
     // geometry (original node order)
     DBuf<double> d_geom;                    // 12 arrays of n_nodes
@@ -124,6 +126,8 @@ void stage_matvec(Ctx& c, int nrhs, const zd* x, zd* y, long ld);
 void stage_export_dense(Ctx& c, zd* A, long ld);
 void stage_rhs(Ctx& c, int nw, const double* khat, const double* pol, zd* b, long ld);
 void stage_farfield(Ctx& c, int nrhs, const zd* x, long ld, int ndir, const double* rhat, zd* E);
+// plain-rule N-Mueller entries of blocks (offsets / leading dimensions into dst)
+void fill_blocks_nm(Ctx& c, const std::vector<DenseBlockDev>& blocks, const DenseBlockDev* d_blocks, zd* dst);
 
 inline double now_s() {
     return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();

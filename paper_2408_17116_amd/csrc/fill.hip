@@ -161,6 +161,77 @@ __device__ inline void lagrange(int q, const double* xn, double x, double* L) {
 // Contraction: thread (b, a, k, l) accumulates
 //   sum_points w K[b][a](x) ell_k(v) ell_l(u)
 // over point tiles staged in LDS.
+// Triangles of the change of variables around (us, vs): per triangle the
+// legs a, b, L1/L2, asinh(L2/L1) and its kind (which leg carries t).
+__device__ inline int quad_triangles(double us, double vs, double (*tri)[6]) {
+    int nt = 0;
+    for (int iu = 0; iu < 2; ++iu) {
+        const double a = (iu ? 1.0 : -1.0) - us;
+        if (fabs(a) < 1e-14) continue;
+        for (int iv = 0; iv < 2; ++iv) {
+            const double b = (iv ? 1.0 : -1.0) - vs;
+            if (fabs(b) < 1e-14) continue;
+            for (int kind = 0; kind < 2; ++kind) {
+                const double L1 = kind ? fabs(b) : fabs(a);
+                const double L2 = kind ? fabs(a) : fabs(b);
+                tri[nt][0] = a;
+                tri[nt][1] = b;
+                tri[nt][2] = L1 / L2;
+                tri[nt][3] = asinh(L2 / L1);
+                tri[nt][4] = kind;
+                ++nt;
+            }
+        }
+    }
+    return nt;
+}
+
+// Parameter distance of a near target from its projection point.
+__device__ inline double near_param_dist(const PatchDev& P, const ObjDev& O, double us, double vs, double dist) {
+    V3 r0, au0, av0;
+    patch_eval(P, O, us, vs, r0, au0, av0);
+    return dist / sqrt(norm(au0) * norm(av0));
+}
+
+// Point pidx of the rule: offset (du, dv) from the singular point and weight.
+__device__ inline void quad_point(const double (*tri)[6], int nt, int nr, int self, double dpar,
+                                  const QuadRule& rule, const double* fej_x, const double* fej_w, int64_t pidx,
+                                  double& du, double& dv, double& wgt) {
+    const int t_i = (int)(pidx / ((int64_t)nt * nr));
+    const int rem = (int)(pidx % ((int64_t)nt * nr));
+    const int it = rem / nr, ir = rem % nr;
+    const double a = tri[t_i][0], b = tri[t_i][1];
+    const double ratio = tri[t_i][2], hi = tri[t_i][3];
+    const int kind = (int)tri[t_i][4];
+    const double sig = fej_x[rule.off_ang + it];
+    const double t = ratio * sinh(hi * sig);
+    const double wt = fej_w[rule.off_ang + it] * hi * ratio * cosh(hi * sig);
+    const double eu = kind ? t * a : a;
+    const double ev = kind ? b : t * b;
+    double s, ws;
+    if (self) {
+        s = fej_x[rule.off_rad + ir];
+        ws = fej_w[rule.off_rad + ir];
+    } else {
+        const double rho = sqrt(eu * eu + ev * ev);
+        const double e = dpar / rho;
+        const double s1 = fmin(0.5, 6.0 * e);
+        if (ir < rule.n_in) {
+            const double h2 = asinh(s1 / e);
+            const double sg = fej_x[rule.off_in + ir];
+            s = e * sinh(h2 * sg);
+            ws = fej_w[rule.off_in + ir] * h2 * e * cosh(h2 * sg);
+        } else {
+            const int jr = ir - rule.n_in;
+            s = s1 + (1.0 - s1) * fej_x[rule.off_out + jr];
+            ws = fej_w[rule.off_out + jr] * (1.0 - s1);
+        }
+    }
+    du = s * eu;
+    dv = s * ev;
+    wgt = wt * ws * s * fabs(a * b);
+}
+
 struct QuadPointLDS {
     double kw[256][8];   // w K (4 complex) per point
     double lu[256][8];
@@ -189,43 +260,13 @@ __global__ __launch_bounds__(256) void k_quad(
     const double* xq = fej11_x + q * (q - 1) / 2;   // the patch's own Chebyshev points
     const int tid = threadIdx.x;
 
-    if (tid == 0) {
-        int nt = 0;
-        for (int iu = 0; iu < 2; ++iu) {
-            const double a = (iu ? 1.0 : -1.0) - us;
-            if (fabs(a) < 1e-14) continue;
-            for (int iv = 0; iv < 2; ++iv) {
-                const double b = (iv ? 1.0 : -1.0) - vs;
-                if (fabs(b) < 1e-14) continue;
-                for (int kind = 0; kind < 2; ++kind) {
-                    const double L1 = kind ? fabs(b) : fabs(a);
-                    const double L2 = kind ? fabs(a) : fabs(b);
-                    s_tri[nt][0] = a;
-                    s_tri[nt][1] = b;
-                    s_tri[nt][2] = L1 / L2;
-                    s_tri[nt][3] = asinh(L2 / L1);
-                    s_tri[nt][4] = kind;
-                    ++nt;
-                }
-            }
-        }
-        s_ntri = nt;
-    }
+    if (tid == 0) s_ntri = quad_triangles(us, vs, s_tri);
     __syncthreads();
     const int ntri = s_ntri;
-
-    // near: parameter distance of the target from the projection point
-    double dpar = 0.0;
-    if (!E.self) {
-        V3 r0, au0, av0;
-        patch_eval(P, O, us, vs, r0, au0, av0);
-        dpar = E.dist / sqrt(norm(au0) * norm(av0));
-    }
+    const double dpar = E.self ? 0.0 : near_param_dist(P, O, us, vs, E.dist);
     const int nt = rule.n_ang;
     const int nr = E.self ? rule.n_rad : (rule.n_in + rule.n_out);
     const int64_t npts = (int64_t)ntri * nt * nr;
-    const double* tx = fej_x + rule.off_ang;
-    const double* tw = fej_w + rule.off_ang;
 
     // output ownership
     const int q2 = q * q;
@@ -242,39 +283,9 @@ __global__ __launch_bounds__(256) void k_quad(
         double Lu[8], Lv[8];
         for (int c = 0; c < 8; ++c) { kw[c] = 0.0; Lu[c] = 0.0; Lv[c] = 0.0; }
         if (pidx < npts) {
-            const int tri = (int)(pidx / ((int64_t)nt * nr));
-            const int rem = (int)(pidx % ((int64_t)nt * nr));
-            const int it = rem / nr, ir = rem % nr;
-            const double a = s_tri[tri][0], b = s_tri[tri][1];
-            const double ratio = s_tri[tri][2], hi = s_tri[tri][3];
-            const int kind = (int)s_tri[tri][4];
-            const double sig = tx[it];
-            const double t = ratio * sinh(hi * sig);
-            const double wt = tw[it] * hi * ratio * cosh(hi * sig);
-            const double eu = kind ? t * a : a;
-            const double ev = kind ? b : t * b;
-            double s, ws;
-            if (E.self) {
-                s = fej_x[rule.off_rad + ir];
-                ws = fej_w[rule.off_rad + ir];
-            } else {
-                const double rho = sqrt(eu * eu + ev * ev);
-                const double e = dpar / rho;
-                const double s1 = fmin(0.5, 6.0 * e);
-                if (ir < rule.n_in) {
-                    const double h2 = asinh(s1 / e);
-                    const double sg = fej_x[rule.off_in + ir];
-                    s = e * sinh(h2 * sg);
-                    ws = fej_w[rule.off_in + ir] * h2 * e * cosh(h2 * sg);
-                } else {
-                    const int jr = ir - rule.n_in;
-                    s = s1 + (1.0 - s1) * fej_x[rule.off_out + jr];
-                    ws = fej_w[rule.off_out + jr] * (1.0 - s1);
-                }
-            }
-            const double du = s * eu, dv = s * ev;
+            double du, dv, wgt;
+            quad_point(s_tri, nt, nr, E.self, dpar, rule, fej_x, fej_w, pidx, du, dv, wgt);
             const double u = us + du, v = vs + dv;
-            const double wgt = wt * ws * s * fabs(a * b);
             V3 r, au, av;
             patch_eval(P, O, u, v, r, au, av);
             const V3 R = E.self ? patch_delta(P, O, us, vs, du, dv) : (rt - r);
@@ -366,16 +377,284 @@ __global__ void k_near_scatter(const NearDest* __restrict__ dest, int64_t n_pair
     const NearDest D = dest[pid];
     const int q2 = D.q2;
     const DenseBlockDev B = blocks[D.block];
-    for (int t = threadIdx.x; t < 4 * q2; t += blockDim.x) {
-        const int b = t / (2 * q2);
-        const int rem = t % (2 * q2);
-        const int jl = rem / 2, a = rem % 2;
+    const int upn = B.upn;
+    for (int t = threadIdx.x; t < upn * upn * q2; t += blockDim.x) {
+        const int b = t / (upn * q2);
+        const int rem = t % (upn * q2);
+        const int jl = rem / upn, a = rem % upn;
         const zd v = vals[pid * stride + t];
-        const int64_t row = 2 * (int64_t)D.row_node + b;
-        const int64_t col = 2 * (int64_t)(D.col_node0 + jl) + a;
+        const int64_t row = upn * (int64_t)D.row_node + b;
+        const int64_t col = upn * (int64_t)(D.col_node0 + jl) + a;
         store[B.offset + col * B.ld + row] = cplx<T>{(T)v.re, (T)v.im};
     }
 }
+
+// ============================================================ N-Mueller
+// Lagrange basis at first-kind Chebyshev points and its derivative at x:
+// with t_k = lam_k / (x - x_k), S = sum_k t_k,
+//   ell_m(x) = t_m / S,
+//   ell_m'(x) = (t_m / S^2) sum_{k != m} t_k (x_k - x_m) / ((x - x_k)(x - x_m)),
+// a form without cancellation next to a node (every term is a product).
+// At a node the derivative row comes from the differentiation matrix D.
+__device__ inline void lagrange_d(int q, const double* xn, const double* D, double x, double* L, double* dL) {
+    for (int l = 0; l < q; ++l) {
+        if (x == xn[l]) {
+            for (int m = 0; m < q; ++m) {
+                L[m] = (m == l) ? 1.0 : 0.0;
+                dL[m] = D[l * q + m];
+            }
+            return;
+        }
+    }
+    double t[8], S = 0.0;
+    for (int l = 0; l < q; ++l) {
+        const double lam = ((l & 1) ? -1.0 : 1.0) * sin((2 * l + 1) * M_PI / (2.0 * q));
+        t[l] = lam / (x - xn[l]);
+        S += t[l];
+    }
+    const double iS = 1.0 / S;
+    for (int m = 0; m < q; ++m) {
+        double acc = 0.0;
+        for (int k = 0; k < q; ++k)
+            if (k != m) acc += t[k] * (xn[k] - xn[m]) / ((x - xn[k]) * (x - xn[m]));
+        L[m] = t[m] * iS;
+        dL[m] = t[m] * iS * iS * acc;
+    }
+}
+
+__device__ inline int dmat_offset(int q) { return (q - 1) * q * (2 * q - 1) / 6; }
+
+// Self/near integrals of the sixteen N-Mueller entries: one work-group per
+// (target node, source patch) pair, the same change of variables as k_quad.
+// Per point: the twelve distinct kernel values (X0, CH, CE) and the two
+// divergence weights phi; thread-owned outputs (type, b, a, k, l):
+//   X:  sum w (X0[b][a] ell_k(v) ell_l(u) + phi[b] d_a(ell_k(v) ell_l(u)))
+//   CH: sum w CH[b][a] ell_k(v) ell_l(u),   CE likewise,
+// written as (4, q^2, 4) [row c, source node, column a]; the identity terms
+// (mu_1 + mu_2)/2 and -(eps_1 + eps_2)/2 are added at the target node.
+constexpr int kNmTile = 128;
+struct QuadNmLDS {
+    double val[kNmTile][28];
+    double lu[kNmTile][8], lv[kNmTile][8], dlu[kNmTile][8], dlv[kNmTile][8];
+};
+
+__global__ __launch_bounds__(256) void k_quad_nm(
+    const PatchDev* __restrict__ patches, const ObjDev* __restrict__ objs, NodeArrays nd,
+    const NearPair* __restrict__ pairs, int64_t n_pairs, const double* __restrict__ fej11_x,
+    const double* __restrict__ fej_x, const double* __restrict__ fej_w, const double* __restrict__ dmat,
+    QuadRule rule, int64_t stride, zd* __restrict__ out) {
+    __shared__ QuadNmLDS S;
+    __shared__ double s_tri[8][6];
+    __shared__ int s_ntri;
+    const int64_t pid = blockIdx.x;
+    if (pid >= n_pairs) return;
+    const NearPair E = pairs[pid];
+    const PatchDev P = patches[E.patch];
+    const ObjDev O = objs[P.obj];
+    const NmMat M = nm_mat(O);
+    const int q = P.q;
+    const int i = E.target;
+    const V3 rt = v3(nd.rx[i], nd.ry[i], nd.rz[i]);
+    const V3 aut = v3(nd.aux[i], nd.auy[i], nd.auz[i]);
+    const V3 avt = v3(nd.avx[i], nd.avy[i], nd.avz[i]);
+    const double us = E.us, vs = E.vs;
+    const double* xq = fej11_x + q * (q - 1) / 2;
+    const double* Dq = dmat + dmat_offset(q);
+    const int tid = threadIdx.x;
+    if (tid == 0) s_ntri = quad_triangles(us, vs, s_tri);
+    __syncthreads();
+    const int ntri = s_ntri;
+    const double dpar = E.self ? 0.0 : near_param_dist(P, O, us, vs, E.dist);
+    const int nt = rule.n_ang;
+    const int nr = E.self ? rule.n_rad : (rule.n_in + rule.n_out);
+    const int64_t npts = (int64_t)ntri * nt * nr;
+    const int q2 = q * q;
+    const int nout = 12 * q2;
+    double acc[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+
+    for (int64_t base = 0; base < npts; base += kNmTile) {
+        const int64_t pidx = base + tid;
+        double vals[28];
+        double Lu[8], Lv[8], dLu[8], dLv[8];
+        for (int c = 0; c < 28; ++c) vals[c] = 0.0;
+        for (int c = 0; c < 8; ++c) { Lu[c] = Lv[c] = dLu[c] = dLv[c] = 0.0; }
+        if (tid < kNmTile && pidx < npts) {
+            double du, dv, wgt;
+            quad_point(s_tri, nt, nr, E.self, dpar, rule, fej_x, fej_w, pidx, du, dv, wgt);
+            const double u = us + du, v = vs + dv;
+            V3 r, au, av;
+            patch_eval(P, O, u, v, r, au, av);
+            const V3 R = E.self ? patch_delta(P, O, us, vs, du, dv) : (rt - r);
+            NmVals K;
+            nm_kernel(M, R, aut, avt, au, av, K);
+            for (int b = 0; b < 2; ++b)
+                for (int a = 0; a < 2; ++a) {
+                    const int e = 2 * (2 * b + a);
+                    vals[e] = wgt * K.X0[b][a].re;
+                    vals[e + 1] = wgt * K.X0[b][a].im;
+                    vals[8 + e] = wgt * K.CH[b][a].re;
+                    vals[8 + e + 1] = wgt * K.CH[b][a].im;
+                    vals[16 + e] = wgt * K.CE[b][a].re;
+                    vals[16 + e + 1] = wgt * K.CE[b][a].im;
+                }
+            for (int b = 0; b < 2; ++b) {
+                vals[24 + 2 * b] = wgt * K.phi[b].re;
+                vals[24 + 2 * b + 1] = wgt * K.phi[b].im;
+            }
+            lagrange_d(q, xq, Dq, u, Lu, dLu);
+            lagrange_d(q, xq, Dq, v, Lv, dLv);
+        }
+        __syncthreads();
+        if (tid < kNmTile) {
+            for (int c = 0; c < 28; ++c) S.val[tid][c] = vals[c];
+            for (int c = 0; c < 8; ++c) {
+                S.lu[tid][c] = Lu[c];
+                S.lv[tid][c] = Lv[c];
+                S.dlu[tid][c] = dLu[c];
+                S.dlv[tid][c] = dLv[c];
+            }
+        }
+        __syncthreads();
+        const int cnt = (int)min((int64_t)kNmTile, npts - base);
+        for (int r = 0; r < 3; ++r) {
+            const int o = tid + 256 * r;
+            if (o >= nout) break;
+            const int type = o / (4 * q2), rem = o % (4 * q2);
+            const int ba = rem / q2, kl = rem % q2;
+            const int b = ba >> 1, a = ba & 1, k = kl / q, l = kl % q;
+            const int e = 8 * type + 2 * ba;
+            double ar = acc[r][0], ai = acc[r][1];
+            if (type == 0) {
+                for (int pnt = 0; pnt < cnt; ++pnt) {
+                    const double bas = S.lv[pnt][k] * S.lu[pnt][l];
+                    const double dbas = a ? S.dlv[pnt][k] * S.lu[pnt][l] : S.lv[pnt][k] * S.dlu[pnt][l];
+                    ar = fma(S.val[pnt][e], bas, fma(S.val[pnt][24 + 2 * b], dbas, ar));
+                    ai = fma(S.val[pnt][e + 1], bas, fma(S.val[pnt][25 + 2 * b], dbas, ai));
+                }
+            } else {
+                for (int pnt = 0; pnt < cnt; ++pnt) {
+                    const double bas = S.lv[pnt][k] * S.lu[pnt][l];
+                    ar = fma(S.val[pnt][e], bas, ar);
+                    ai = fma(S.val[pnt][e + 1], bas, ai);
+                }
+            }
+            acc[r][0] = ar;
+            acc[r][1] = ai;
+        }
+    }
+    zd* dst = out + pid * stride;
+    for (int r = 0; r < 3; ++r) {
+        const int o = tid + 256 * r;
+        if (o >= nout) break;
+        const int type = o / (4 * q2), rem = o % (4 * q2);
+        const int ba = rem / q2, kl = rem % q2;
+        const int b = ba >> 1, a = ba & 1;
+        const bool diag = E.self && a == b && (P.node0 + kl) == i;
+        const zd v{acc[r][0], acc[r][1]};
+        if (type == 0) {
+            dst[((int64_t)b * q2 + kl) * 4 + 2 + a] = v;            // H_b x M^a
+            dst[((int64_t)(2 + b) * q2 + kl) * 4 + a] = v;          // E_b x J^a
+        } else if (type == 1) {
+            dst[((int64_t)b * q2 + kl) * 4 + a] = zd{v.re + (diag ? 0.5 * (1.0 + M.m2) : 0.0), v.im};
+        } else {
+            dst[((int64_t)(2 + b) * q2 + kl) * 4 + 2 + a] = zd{v.re - (diag ? 0.5 * (1.0 + M.e2) : 0.0), v.im};
+        }
+    }
+}
+
+// Far (Fejer-rule) entries of N-Mueller blocks, column-major with leading
+// dimension ld = 4 row_nodes.  A work-group takes 32 row nodes against one
+// source patch (tile.col0: its first local column node, tile.pad: q).  The
+// surface divergence of the source is the derivative of its Chebyshev
+// interpolant: the weight phi of node (k, l) reaches column (k, m) of the
+// u-component through D[l][m] and column (m, l) of the v-component through
+// D[k][m].  Pass 1 stages w phi in LDS, pass 2 writes all sixteen entries.
+// Self pairs are left zero (near pairs are overwritten by k_quad_nm).
+template <typename T>
+__global__ __launch_bounds__(256) void k_far_fill_nm(const DenseTile* __restrict__ tiles, int n_tiles,
+                                                     const DenseBlockDev* __restrict__ blocks,
+                                                     const int* __restrict__ tree_node, NodeArrays nd,
+                                                     const ObjDev* __restrict__ objs,
+                                                     const double* __restrict__ dmat, cplx<T>* __restrict__ store) {
+    __shared__ zd s_phi[2][32][65];
+    __shared__ double s_D[64];
+    const int tile = blockIdx.x;
+    if (tile >= n_tiles) return;
+    const DenseTile Tl = tiles[tile];
+    const DenseBlockDev B = blocks[Tl.block];
+    const int q = Tl.pad, q2 = q * q;
+    const NmMat M = nm_mat(objs[B.obj]);
+    const double* Dq = dmat + dmat_offset(q);
+    for (int e = threadIdx.x; e < q2; e += 256) s_D[e] = Dq[e];
+    const int nrow = min(32, B.row_nodes - Tl.row0);
+    for (int p = threadIdx.x; p < 32 * q2; p += 256) {
+        const int il = p & 31, j = p >> 5;
+        zd ph[2] = {zd{0.0, 0.0}, zd{0.0, 0.0}};
+        if (il < nrow) {
+            const int gi = tree_node[B.row_node0 + Tl.row0 + il];
+            const int gj = tree_node[B.col_node0 + Tl.col0 + j];
+            if (gi != gj) {
+                NmVals K;
+                nm_kernel(M, v3(nd.rx[gi] - nd.rx[gj], nd.ry[gi] - nd.ry[gj], nd.rz[gi] - nd.rz[gj]),
+                          v3(nd.aux[gi], nd.auy[gi], nd.auz[gi]), v3(nd.avx[gi], nd.avy[gi], nd.avz[gi]),
+                          v3(nd.aux[gj], nd.auy[gj], nd.auz[gj]), v3(nd.avx[gj], nd.avy[gj], nd.avz[gj]), K);
+                const double w = nd.w[gj];
+                ph[0] = w * K.phi[0];
+                ph[1] = w * K.phi[1];
+            }
+        }
+        s_phi[0][il][j] = ph[0];
+        s_phi[1][il][j] = ph[1];
+    }
+    __syncthreads();
+    cplx<T>* base = store + B.offset;
+    for (int p = threadIdx.x; p < 32 * q2; p += 256) {
+        const int il = p & 31, j = p >> 5;
+        if (il >= nrow) continue;
+        const int ti = Tl.row0 + il;
+        const int gi = tree_node[B.row_node0 + ti];
+        const int gj = tree_node[B.col_node0 + Tl.col0 + j];
+        NmVals K;
+        double w = 0.0;
+        if (gi != gj) {
+            nm_kernel(M, v3(nd.rx[gi] - nd.rx[gj], nd.ry[gi] - nd.ry[gj], nd.rz[gi] - nd.rz[gj]),
+                      v3(nd.aux[gi], nd.auy[gi], nd.auz[gi]), v3(nd.avx[gi], nd.avy[gi], nd.avz[gi]),
+                      v3(nd.aux[gj], nd.auy[gj], nd.auz[gj]), v3(nd.avx[gj], nd.avy[gj], nd.avz[gj]), K);
+            w = nd.w[gj];
+        } else {
+            for (int b = 0; b < 2; ++b)
+                for (int a = 0; a < 2; ++a) K.X0[b][a] = K.CH[b][a] = K.CE[b][a] = zd{0.0, 0.0};
+        }
+        const int kk = j / q, ll = j % q;
+        zd dvu[2], dvv[2];
+        for (int b = 0; b < 2; ++b) {
+            zd su{0.0, 0.0}, sv{0.0, 0.0};
+            for (int m = 0; m < q; ++m) {
+                cfma(su, zd{s_D[m * q + ll], 0.0}, s_phi[b][il][kk * q + m]);
+                cfma(sv, zd{s_D[m * q + kk], 0.0}, s_phi[b][il][m * q + ll]);
+            }
+            dvu[b] = su;
+            dvv[b] = sv;
+        }
+        const int64_t row = 4 * (int64_t)ti;
+        for (int a = 0; a < 2; ++a) {
+            const int64_t cj = 4 * (int64_t)(Tl.col0 + j) + a, cm = cj + 2;
+            cplx<T>* colJ = base + cj * B.ld + row;
+            cplx<T>* colM = base + cm * B.ld + row;
+            for (int b = 0; b < 2; ++b) {
+                const zd X = w * K.X0[b][a] + (a ? dvv[b] : dvu[b]);
+                const zd ch = w * K.CH[b][a], ce = w * K.CE[b][a];
+                colJ[b] = cplx<T>{(T)ch.re, (T)ch.im};
+                colJ[2 + b] = cplx<T>{(T)X.re, (T)X.im};
+                colM[b] = cplx<T>{(T)X.re, (T)X.im};
+                colM[2 + b] = cplx<T>{(T)ce.re, (T)ce.im};
+            }
+        }
+    }
+}
+
+template __global__ void k_far_fill_nm<double>(const DenseTile*, int, const DenseBlockDev*, const int*, NodeArrays,
+                                               const ObjDev*, const double*, zd*);
 
 template __global__ void k_far_fill<double>(const DenseTile*, int, const DenseBlockDev*, const int*,
                                             NodeArrays, const ObjDev*, zd*);
@@ -399,12 +678,13 @@ __global__ void k_export_dense_block(const DenseBlockDev* __restrict__ blocks, i
     const int bid = blockIdx.y;
     if (bid >= n_blocks) return;
     const DenseBlockDev B = blocks[bid];
-    const int64_t m = 2 * (int64_t)B.row_nodes, n = 2 * (int64_t)B.col_nodes;
+    const int upn = B.upn;
+    const int64_t m = upn * (int64_t)B.row_nodes, n = upn * (int64_t)B.col_nodes;
     for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < m * n;
          e += (int64_t)gridDim.x * blockDim.x) {
         const int64_t r = e % m, c = e / m;
-        const int64_t gr = 2 * (int64_t)tree_node[B.row_node0 + r / 2] + (r & 1);
-        const int64_t gc = 2 * (int64_t)tree_node[B.col_node0 + c / 2] + (c & 1);
+        const int64_t gr = upn * (int64_t)tree_node[B.row_node0 + r / upn] + (r % upn);
+        const int64_t gc = upn * (int64_t)tree_node[B.col_node0 + c / upn] + (c % upn);
         A[gc * lda + gr] = store[B.offset + c * B.ld + r];
     }
 }

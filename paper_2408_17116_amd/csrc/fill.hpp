@@ -31,11 +31,11 @@ struct QuadRule {
 // A dense block as the fill kernels see it (tree order).
 struct DenseBlockDev {
     int64_t offset;      // element offset into the dense store
-    int ld;              // leading dimension (= 2 row_nodes)
+    int ld;              // leading dimension (= upn row_nodes)
     int row_node0, row_nodes;   // tree-order node range of the rows
     int col_node0, col_nodes;   // tree-order node range of the columns
     int obj;
-    int pad;
+    int upn;             // unknowns per node: 2 (MFIE) or 4 (N-Mueller)
 };
 
 struct DenseTile {
@@ -60,6 +60,11 @@ __global__ void k_quad(const PatchDev*, const ObjDev*, NodeArrays, const NearPai
 template <typename T>
 __global__ void k_far_fill(const DenseTile*, int, const DenseBlockDev*, const int*, NodeArrays,
                            const ObjDev*, cplx<T>*);
+__global__ void k_quad_nm(const PatchDev*, const ObjDev*, NodeArrays, const NearPair*, int64_t, const double*,
+                          const double*, const double*, const double*, QuadRule, int64_t, zd*);
+template <typename T>
+__global__ void k_far_fill_nm(const DenseTile*, int, const DenseBlockDev*, const int*, NodeArrays, const ObjDev*,
+                              const double*, cplx<T>*);
 template <typename T>
 __global__ void k_near_scatter(const NearDest*, int64_t, int64_t, const zd*, const DenseBlockDev*, cplx<T>*);
 

@@ -23,6 +23,7 @@ struct ObjDev {
     double k0;
     int q;
     int form;
+    double eps_r, mu_r;   // interior material (N-Mueller)
 };
 
 __device__ __constant__ static const double kFaceFrames[6][3][3] = {
@@ -114,6 +115,87 @@ __device__ inline void mfie_kernel(double k, V3 R, V3 au_t, V3 av_t, V3 au_s, V3
     K[0][1] = zd{gr * t01, gi * t01};
     K[1][0] = zd{gr * t10, gi * t10};
     K[1][1] = zd{gr * t11, gi * t11};
+}
+
+// ----------------------------------------------------------- N-Mueller kernel
+// Homogeneous dielectric body in vacuum (Sec. II-A, eqs. 7-9 with
+// alpha = -eps_2/eps_1, beta = -mu_2/mu_1; eps_1 = mu_1 = 1, omega = k0).
+// Unknowns per node (J^u, J^v, M^u, M^v) sqrt(G); rows per node
+// (H_u, H_v, E_u, E_v) tested with t_b: t_b . (n x Y) = s_b T_b . Y,
+// (s_u, T_u) = (-1, a_v), (s_v, T_v) = (+1, a_u).  With R = r - r',
+// G_k = e^{-jkR}/(4 pi R), g_k = -(1 + jkR) e^{-jkR}/(4 pi R^3):
+//   S  = G_1 - mu_2 eps_2 G_2,  C_E = g_1 - eps_2 g_2,  C_H = g_1 - mu_2 g_2,
+//   X0[b][a] = s_b j w S (T_b . a_a)     -> rows H_b x M^a and E_b x J^a
+//   CH[b][a] = -s_b C_H R . (a_a x T_b)  -> H_b x J^a
+//   CE[b][a] =  s_b C_E R . (a_a x T_b)  -> E_b x M^a
+//   phi[b]   = (j / w) s_b (g_1 - g_2) (T_b . R), the weight of the surface
+//              divergence of the source J (E rows) or M (H rows).
+// The interior terms are written as differences G_1 - G_2 and g_1 - g_2,
+// evaluated from closed forms that do not cancel at small k R.
+struct NmMat {
+    double k1, k2, w, e2, m2;
+};
+__device__ inline NmMat nm_mat(const ObjDev& O) {
+    return NmMat{O.k0, O.k0 * sqrt(O.eps_r * O.mu_r), O.k0, O.eps_r, O.mu_r};
+}
+
+// x cos x - sin x = sum_{n >= 1} (-1)^n 2n x^{2n+1} / (2n+1)!
+__device__ inline double xcos_minus_sin(double x) {
+    if (fabs(x) < 0.5) {
+        const double x2 = x * x;
+        double term = x, s = 0.0;
+        for (int n = 1; n <= 9; ++n) {
+            term *= -x2 / ((2.0 * n) * (2.0 * n + 1.0));
+            s += 2.0 * n * term;
+        }
+        return s;
+    }
+    double sn, cs;
+    sincos(x, &sn, &cs);
+    return x * cs - sn;
+}
+
+struct NmVals {
+    zd X0[2][2], CH[2][2], CE[2][2], phi[2];
+};
+
+__device__ inline void nm_kernel(const NmMat& M, V3 R, V3 au_t, V3 av_t, V3 au_s, V3 av_s, NmVals& o) {
+    const double R2 = dot(R, R);
+    const double Rn = sqrt(R2);
+    const double x1 = M.k1 * Rn, x2 = M.k2 * Rn;
+    const double s1 = sin(x1), s2 = sin(x2);
+    const double h1 = sin(0.5 * x1), h2 = sin(0.5 * x2);
+    const double m1c = -2.0 * h1 * h1, m2c = -2.0 * h2 * h2;   // cos x - 1 = -2 sin^2(x/2)
+    const double inv1 = 1.0 / (4.0 * M_PI * Rn), inv3 = inv1 / R2;
+    // G_1 and G_1 - G_2:  e^{-jx} = (cos x - 1) + 1 - j sin x
+    const zd G1{(1.0 + m1c) * inv1, -s1 * inv1};
+    const zd dG{(m1c - m2c) * inv1, -(s1 - s2) * inv1};
+    // (1 + jx) e^{-jx} - 1 = (cos x - 1 + x sin x) + j (x cos x - sin x)
+    const double q1r = m1c + x1 * s1, q1i = xcos_minus_sin(x1);
+    const double q2r = m2c + x2 * s2, q2i = xcos_minus_sin(x2);
+    const zd g1{-(1.0 + q1r) * inv3, -q1i * inv3};
+    const zd dg{-(q1r - q2r) * inv3, -(q1i - q2i) * inv3};
+    const double em = M.e2 * M.m2;
+    const zd S = (1.0 - em) * G1 + em * dG;
+    const zd CE = (1.0 - M.e2) * g1 + M.e2 * dg;
+    const zd CH = (1.0 - M.m2) * g1 + M.m2 * dg;
+    const zd jwS{-M.w * S.im, M.w * S.re};
+    const V3 T[2] = {av_t, au_t};
+    const V3 A[2] = {au_s, av_s};
+    for (int b = 0; b < 2; ++b) {
+        const double sb = b ? 1.0 : -1.0;
+        const double TR = dot(T[b], R);
+        // (j / w) s_b TR dg
+        const double f = sb * TR / M.w;
+        o.phi[b] = zd{-f * dg.im, f * dg.re};
+        for (int a = 0; a < 2; ++a) {
+            const double Ta = dot(T[b], A[a]);
+            const double cr = dot(R, cross(A[a], T[b]));
+            o.X0[b][a] = (sb * Ta) * jwS;
+            o.CH[b][a] = (-sb * cr) * CH;
+            o.CE[b][a] = (sb * cr) * CE;
+        }
+    }
 }
 
 }  // namespace cbie

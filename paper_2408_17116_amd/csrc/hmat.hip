@@ -1539,8 +1539,8 @@ template <typename T> static std::shared_ptr<HF<T>> make_factor(Ctx& c) {
     f->lr_busy.assign(c.lblk.size(), 0);
     for (size_t b = 0; b < c.lblk.size(); ++b) {
         auto& L = f->lr[b];
-        L.m = 2 * c.lblk[b].row_nodes;
-        L.n = 2 * c.lblk[b].col_nodes;
+        L.m = c.upn * c.lblk[b].row_nodes;
+        L.n = c.upn * c.lblk[b].col_nodes;
         L.r = L.K = c.lr.rank[b];
         L.cap = std::max(L.r, 1);
         L.U = f->store.alloc((size_t)L.m * L.cap);
@@ -1659,7 +1659,7 @@ void stage_solve(Ctx& c, int nrhs, const zd* b, zd* x, long ld, double tol, int 
     xt.alloc(NN);
     rt.alloc(NN);
     const unsigned g = ceil_div(NN, 256);
-    k_to_tree<double><<<g, 256, 0, s>>>(c.d_tree_node.p, N, nrhs, b, ld, bt.p);
+    k_to_tree<double><<<g, 256, 0, s>>>(c.d_tree_node.p, c.upn, N, nrhs, b, ld, bt.p);
     check_launch("k_to_tree");
     DBuf<double> nrm;
     nrm.alloc(2 * (size_t)nrhs);
@@ -1697,7 +1697,7 @@ void stage_solve(Ctx& c, int nrhs, const zd* b, zd* x, long ld, double tol, int 
         k_add<<<g, 256, 0, s>>>(NN, rt.p, xt.p);
         check_launch("k_add");
     }
-    k_from_tree<double><<<g, 256, 0, s>>>(c.d_tree_node.p, N, nrhs, xt.p, x, ld);
+    k_from_tree<double><<<g, 256, 0, s>>>(c.d_tree_node.p, c.upn, N, nrhs, xt.p, x, ld);
     check_launch("k_from_tree");
     c.sync();
     c.gemm_timer.harvest();

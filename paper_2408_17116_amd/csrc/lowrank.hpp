@@ -7,14 +7,18 @@ namespace cbie {
 // Largest rank an admissible block may reach in the ACA (columns of its
 // workspace); blocks that hit it are reported as not converged.
 constexpr int kAcaMaxRank = 512;
+// explicit block copies compressed per round (N-Mueller), complex128 entries
+constexpr int64_t kAcaDense = int64_t(1) << 28;
 
 struct AcaJob {
     int row_node0, row_nodes;    // tree-order node range of the rows
     int col_node0, col_nodes;
     int obj;
+    int upn;                     // unknowns per node
     int cap;                     // workspace columns
     int64_t u_off, v_off;        // workspace offsets (elements)
     int64_t used_off;            // row-flag offset (bytes)
+    int64_t a_off;               // explicit copy of the block (N-Mueller), elements
 };
 
 }  // namespace cbie

@@ -10,29 +10,29 @@ namespace cbie {
 
 // x (original order, ld) -> xt (tree order, ld_t = n_unk), nrhs columns
 template <typename T>
-__global__ void k_to_tree(const int* __restrict__ tree_node, int64_t n_unk, int nrhs, const zd* __restrict__ x,
-                          int64_t ld, cplx<T>* __restrict__ xt) {
+__global__ void k_to_tree(const int* __restrict__ tree_node, int upn, int64_t n_unk, int nrhs,
+                          const zd* __restrict__ x, int64_t ld, cplx<T>* __restrict__ xt) {
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (e >= n_unk * nrhs) return;
     const int64_t r = e / n_unk, u = e % n_unk;
-    const zd v = x[r * ld + 2 * (int64_t)tree_node[u >> 1] + (u & 1)];
+    const zd v = x[r * ld + upn * (int64_t)tree_node[u / upn] + (u % upn)];
     xt[e] = cplx<T>{(T)v.re, (T)v.im};
 }
 
 template <typename T>
-__global__ void k_from_tree(const int* __restrict__ tree_node, int64_t n_unk, int nrhs,
+__global__ void k_from_tree(const int* __restrict__ tree_node, int upn, int64_t n_unk, int nrhs,
                             const cplx<T>* __restrict__ yt, zd* __restrict__ y, int64_t ld) {
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (e >= n_unk * nrhs) return;
     const int64_t r = e / n_unk, u = e % n_unk;
     const cplx<T> v = yt[e];
-    y[r * ld + 2 * (int64_t)tree_node[u >> 1] + (u & 1)] = zd{(double)v.re, (double)v.im};
+    y[r * ld + upn * (int64_t)tree_node[u / upn] + (u % upn)] = zd{(double)v.re, (double)v.im};
 }
 
-template __global__ void k_to_tree<double>(const int*, int64_t, int, const zd*, int64_t, zd*);
-template __global__ void k_to_tree<float>(const int*, int64_t, int, const zd*, int64_t, zf*);
-template __global__ void k_from_tree<double>(const int*, int64_t, int, const zd*, zd*, int64_t);
-template __global__ void k_from_tree<float>(const int*, int64_t, int, const zf*, zd*, int64_t);
+template __global__ void k_to_tree<double>(const int*, int, int64_t, int, const zd*, int64_t, zd*);
+template __global__ void k_to_tree<float>(const int*, int, int64_t, int, const zd*, int64_t, zf*);
+template __global__ void k_from_tree<double>(const int*, int, int64_t, int, const zd*, zd*, int64_t);
+template __global__ void k_from_tree<float>(const int*, int, int64_t, int, const zf*, zd*, int64_t);
 
 __device__ inline void atomic_add_z(zd* p, zd v) {
     atomicAdd(&p->re, v.re);
@@ -47,7 +47,7 @@ __global__ __launch_bounds__(256) void k_dense_mv(const DenseBlockDev* __restric
     const int bid = blockIdx.y;
     if (bid >= nb) return;
     const DenseBlockDev B = blocks[bid];
-    const int m = 2 * B.row_nodes, n = 2 * B.col_nodes;
+    const int m = B.upn * B.row_nodes, n = B.upn * B.col_nodes;
     const int r0 = blockIdx.x * 64;
     if (r0 >= m) return;
     const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;   // 4 groups split the columns
@@ -55,7 +55,7 @@ __global__ __launch_bounds__(256) void k_dense_mv(const DenseBlockDev* __restric
     __shared__ zd sx[8][256];
     __shared__ zd red[4][64][8];
     const zd* D = store + B.offset;
-    const int64_t c0 = 2 * (int64_t)B.col_node0, rr0 = 2 * (int64_t)B.row_node0;
+    const int64_t c0 = B.upn * (int64_t)B.col_node0, rr0 = B.upn * (int64_t)B.row_node0;
     for (int rb = 0; rb < nrhs; rb += 8) {
         const int nr = min(8, nrhs - rb);
         zd acc[8];
@@ -100,9 +100,9 @@ __global__ __launch_bounds__(256) void k_lr_vt(const DenseBlockDev* __restrict__
     const int r = rank[bid];
     if (l >= r) return;
     const DenseBlockDev B = blocks[bid];
-    const int n = 2 * B.col_nodes;
+    const int n = B.upn * B.col_nodes;
     const zd* V = store + v_off[bid] + (int64_t)l * n;
-    const int64_t c0 = 2 * (int64_t)B.col_node0;
+    const int64_t c0 = B.upn * (int64_t)B.col_node0;
     __shared__ double sh[2][4];
     for (int rr = 0; rr < nrhs; ++rr) {
         double sr = 0.0, si = 0.0;
@@ -130,13 +130,13 @@ __global__ __launch_bounds__(256) void k_lr_u(const DenseBlockDev* __restrict__ 
     const int bid = blockIdx.y;
     if (bid >= nb) return;
     const DenseBlockDev B = blocks[bid];
-    const int m = 2 * B.row_nodes;
+    const int m = B.upn * B.row_nodes;
     const int i = blockIdx.x * 256 + threadIdx.x;
     if (i >= m) return;
     const int r = rank[bid];
     const zd* U = store + u_off[bid];
     const zd* T = tmp + t_off[bid];
-    const int64_t r0 = 2 * (int64_t)B.row_node0;
+    const int64_t r0 = B.upn * (int64_t)B.row_node0;
     for (int rr = 0; rr < nrhs; ++rr) {
         zd s{0.0, 0.0};
         for (int l = 0; l < r; ++l) cfma(s, U[(int64_t)l * m + i], T[(int64_t)rr * r + l]);
@@ -151,7 +151,7 @@ void apply_operator_tree(Ctx& c, int nrhs, const zd* xt, zd* yt) {
     const int nd = (int)c.dblk.size();
     if (nd > 0) {
         int maxm = 0;
-        for (const auto& d : c.dblk) maxm = std::max(maxm, 2 * d.row_nodes);
+        for (const auto& d : c.dblk) maxm = std::max(maxm, c.upn * d.row_nodes);
         dim3 grid(ceil_div(maxm, 64), nd);
         k_dense_mv<<<grid, 256, 0, c.stream>>>(c.d_dblk.p, nd, c.dense.p, xt, yt, N, nrhs);
         check_launch("k_dense_mv");
@@ -171,7 +171,7 @@ void apply_operator_tree(Ctx& c, int nrhs, const zd* xt, zd* yt) {
         int maxr = 1, maxm = 0;
         for (int b = 0; b < nl; ++b) {
             maxr = std::max(maxr, c.lr.rank[b]);
-            maxm = std::max(maxm, 2 * c.lblk[b].row_nodes);
+            maxm = std::max(maxm, c.upn * c.lblk[b].row_nodes);
         }
         k_lr_vt<<<dim3(maxr, nl), 256, 0, c.stream>>>(c.d_lblk.p, nl, c.lr.d_v_off.p, c.lr.d_rank.p,
                                                        c.d_mv_tmp_off.p, c.lr.mem.p, xt, c.mv_tmp.p, N, nrhs);
@@ -189,18 +189,20 @@ void stage_matvec(Ctx& c, int nrhs, const zd* x, zd* y, long ld) {
     xt.alloc(N * nrhs);
     yt.alloc(N * nrhs);
     const unsigned g = ceil_div(N * nrhs, 256);
-    k_to_tree<double><<<g, 256, 0, c.stream>>>(c.d_tree_node.p, N, nrhs, x, ld, xt.p);
+    k_to_tree<double><<<g, 256, 0, c.stream>>>(c.d_tree_node.p, c.upn, N, nrhs, x, ld, xt.p);
     check_launch("k_to_tree");
     apply_operator_tree(c, nrhs, xt.p, yt.p);
-    k_from_tree<double><<<g, 256, 0, c.stream>>>(c.d_tree_node.p, N, nrhs, yt.p, y, ld);
+    k_from_tree<double><<<g, 256, 0, c.stream>>>(c.d_tree_node.p, c.upn, N, nrhs, yt.p, y, ld);
     check_launch("k_from_tree");
     c.sync();
 }
 
-// --------------------------------------------------------------- RHS (eq. 22)
-// b_u = -a_v . H_inc, b_v = a_u . H_inc, H_inc = khat x pol e^{-j k khat.r}
+// ------------------------------------------------------ RHS (eqs. 19, 22)
+// MFIE: b_u = -a_v . H_inc, b_v = a_u . H_inc.  N-Mueller (rows H_u, H_v,
+// E_u, E_v of a node): -a_v . H_inc, a_u . H_inc, -a_v . E_inc, a_u . E_inc.
+// E_inc = pol e^{-j k khat.r}, H_inc = khat x E_inc (exterior vacuum).
 __global__ void k_rhs(NodeArrays nd, const int* __restrict__ node_patch, const PatchDev* __restrict__ patches,
-                      const ObjDev* __restrict__ objs, int n_nodes, int nw, const double* __restrict__ kp,
+                      const ObjDev* __restrict__ objs, int n_nodes, int upn, int nw, const double* __restrict__ kp,
                       zd* __restrict__ b, int64_t ld) {
     const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
     if (e >= (int64_t)n_nodes * nw) return;
@@ -215,8 +217,14 @@ __global__ void k_rhs(NodeArrays nd, const int* __restrict__ node_patch, const P
     const V3 au = v3(nd.aux[i], nd.auy[i], nd.auz[i]);
     const V3 av = v3(nd.avx[i], nd.avy[i], nd.avz[i]);
     const double cu = -dot(av, h), cv = dot(au, h);
-    b[(int64_t)w * ld + 2 * i] = zd{cu * cs, -cu * s};
-    b[(int64_t)w * ld + 2 * i + 1] = zd{cv * cs, -cv * s};
+    zd* bi = b + (int64_t)w * ld + (int64_t)upn * i;
+    bi[0] = zd{cu * cs, -cu * s};
+    bi[1] = zd{cv * cs, -cv * s};
+    if (upn == 4) {
+        const double eu = -dot(av, po), ev = dot(au, po);
+        bi[2] = zd{eu * cs, -eu * s};
+        bi[3] = zd{ev * cs, -ev * s};
+    }
 }
 
 void stage_rhs(Ctx& c, int nw, const double* khat, const double* pol, zd* b, long ld) {
@@ -226,43 +234,47 @@ void stage_rhs(Ctx& c, int nw, const double* khat, const double* pol, zd* b, lon
     DBuf<double> d_kp;
     d_kp.upload(kp, c.stream);
     k_rhs<<<ceil_div((int64_t)c.n_nodes * nw, 256), 256, 0, c.stream>>>(
-        c.nd, c.d_node_patch.p, c.d_patches.p, c.d_objs.p, c.n_nodes, nw, d_kp.p, b, ld);
+        c.nd, c.d_node_patch.p, c.d_patches.p, c.d_objs.p, c.n_nodes, c.upn, nw, d_kp.p, b, ld);
     check_launch("k_rhs");
     c.sync();
 }
 
 // ---------------------------------------------------------------- far field
-// N(rhat) = sum_nodes w (F^u a_u + F^v a_v) e^{j k rhat.r};  E = -j k N_perp / (4 pi).
+// N(rhat) = sum_nodes w (F_J^u a_u + F_J^v a_v) e^{j k rhat.r}, L likewise
+// from M (N-Mueller only);  E = -j k (N_perp - rhat x L) / (4 pi).
 // One work-group per (direction, rhs).
 __global__ __launch_bounds__(256) void k_farfield(NodeArrays nd, const int* __restrict__ node_patch,
                                                   const PatchDev* __restrict__ patches,
-                                                  const ObjDev* __restrict__ objs, int n_nodes,
+                                                  const ObjDev* __restrict__ objs, int n_nodes, int upn,
                                                   const zd* __restrict__ x, int64_t ld, int ndir,
                                                   const double* __restrict__ rhat, zd* __restrict__ E) {
     const int d = blockIdx.x, r = blockIdx.y;
     if (d >= ndir) return;
     const V3 rh = v3(rhat[3 * d], rhat[3 * d + 1], rhat[3 * d + 2]);
-    double acc[6] = {0, 0, 0, 0, 0, 0};
+    double acc[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};   // N (re, im per axis), then L
     double kk = 0.0;
     for (int i = threadIdx.x; i < n_nodes; i += 256) {
         const double k = objs[patches[node_patch[i]].obj].k0;
         kk = k;
-        const zd fu = x[(int64_t)r * ld + 2 * i], fv = x[(int64_t)r * ld + 2 * i + 1];
+        const zd* xi = x + (int64_t)r * ld + (int64_t)upn * i;
         double s, cs;
         sincos(k * dot(rh, v3(nd.rx[i], nd.ry[i], nd.rz[i])), &s, &cs);   // e^{+j phi}
         const double w = nd.w[i];
         const double au[3] = {nd.aux[i], nd.auy[i], nd.auz[i]};
         const double av[3] = {nd.avx[i], nd.avy[i], nd.avz[i]};
-        for (int c = 0; c < 3; ++c) {
-            const double jr = w * (fu.re * au[c] + fv.re * av[c]);
-            const double ji = w * (fu.im * au[c] + fv.im * av[c]);
-            acc[2 * c] += jr * cs - ji * s;
-            acc[2 * c + 1] += jr * s + ji * cs;
+        for (int src = 0; src < upn / 2; ++src) {
+            const zd fu = xi[2 * src], fv = xi[2 * src + 1];
+            for (int c = 0; c < 3; ++c) {
+                const double jr = w * (fu.re * au[c] + fv.re * av[c]);
+                const double ji = w * (fu.im * au[c] + fv.im * av[c]);
+                acc[6 * src + 2 * c] += jr * cs - ji * s;
+                acc[6 * src + 2 * c + 1] += jr * s + ji * cs;
+            }
         }
     }
-    __shared__ double sh[6][4];
+    __shared__ double sh[12][4];
     __shared__ double shk[4];
-    for (int c = 0; c < 6; ++c) {
+    for (int c = 0; c < 12; ++c) {
         double v = acc[c];
         for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
         if ((threadIdx.x & 63) == 0) sh[c][threadIdx.x >> 6] = v;
@@ -272,14 +284,19 @@ __global__ __launch_bounds__(256) void k_farfield(NodeArrays nd, const int* __re
     if ((threadIdx.x & 63) == 0) shk[threadIdx.x >> 6] = km;
     __syncthreads();
     if (threadIdx.x == 0) {
-        double N[6];
-        for (int c = 0; c < 6; ++c) N[c] = sh[c][0] + sh[c][1] + sh[c][2] + sh[c][3];
+        double N[12];
+        for (int c = 0; c < 12; ++c) N[c] = sh[c][0] + sh[c][1] + sh[c][2] + sh[c][3];
+        const double* L = N + 6;
         const double k = fmax(fmax(shk[0], shk[1]), fmax(shk[2], shk[3]));
         const double rv[3] = {rh.x, rh.y, rh.z};
         const double dre = rv[0] * N[0] + rv[1] * N[2] + rv[2] * N[4];
         const double dim = rv[0] * N[1] + rv[1] * N[3] + rv[2] * N[5];
         for (int c = 0; c < 3; ++c) {
-            const double pr = N[2 * c] - rv[c] * dre, pi = N[2 * c + 1] - rv[c] * dim;
+            // N_perp - rhat x L (L = 0 for a conductor)
+            const int c1 = (c + 1) % 3, c2 = (c + 2) % 3;
+            const double xr = rv[c1] * L[2 * c2] - rv[c2] * L[2 * c1];
+            const double xim = rv[c1] * L[2 * c2 + 1] - rv[c2] * L[2 * c1 + 1];
+            const double pr = N[2 * c] - rv[c] * dre - xr, pi = N[2 * c + 1] - rv[c] * dim - xim;
             // -j k / (4 pi) (pr + j pi) = (k pi - j k pr) / (4 pi)
             E[((int64_t)r * ndir + d) * 3 + c] = zd{k * pi / (4 * M_PI), -k * pr / (4 * M_PI)};
         }
@@ -292,7 +309,7 @@ void stage_farfield(Ctx& c, int nrhs, const zd* x, long ld, int ndir, const doub
     DBuf<zd> d_E;
     d_E.alloc(3 * (size_t)ndir * nrhs);
     k_farfield<<<dim3(ndir, nrhs), 256, 0, c.stream>>>(c.nd, c.d_node_patch.p, c.d_patches.p, c.d_objs.p,
-                                                       c.n_nodes, x, ld, ndir, d_r.p, d_E.p);
+                                                       c.n_nodes, c.upn, x, ld, ndir, d_r.p, d_E.p);
     check_launch("k_farfield");
     d_E.download(E, 3 * (size_t)ndir * nrhs, c.stream);
     c.sync();

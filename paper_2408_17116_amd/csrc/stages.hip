@@ -38,6 +38,30 @@ void make_fejer_tables(Ctx& c) {
     c.d_fej11_w.upload(aw, c.stream);
     c.d_fej01_x.upload(bx, c.stream);
     c.d_fej01_w.upload(bw, c.stream);
+    // Differentiation matrices of the interpolant at the q points, q = 1..8,
+    // stored at offset (q-1) q (2q-1) / 6: D[i][j] = ell_j'(x_i), from the
+    // barycentric weights lam_j = 1 / prod_{k != j} (x_j - x_k):
+    // D[i][j] = (lam_j / lam_i) / (x_i - x_j), D[i][i] = -sum_{j != i} D[i][j].
+    std::vector<double> dm;
+    for (int q = 1; q <= 8; ++q) {
+        fejer(q, x, w);
+        std::vector<double> lam(q, 1.0);
+        for (int j = 0; j < q; ++j)
+            for (int k = 0; k < q; ++k)
+                if (k != j) lam[j] /= (x[j] - x[k]);
+        for (int i = 0; i < q; ++i) {
+            double diag = 0.0;
+            std::vector<double> row(q, 0.0);
+            for (int j = 0; j < q; ++j)
+                if (j != i) {
+                    row[j] = (lam[j] / lam[i]) / (x[i] - x[j]);
+                    diag -= row[j];
+                }
+            row[i] = diag;
+            dm.insert(dm.end(), row.begin(), row.end());
+        }
+    }
+    c.d_dmat.upload(dm, c.stream);
 }
 
 void stage_build_tree(Ctx& c, int leaf_size, double eta, double delta) {
@@ -112,6 +136,7 @@ void stage_build_tree(Ctx& c, int leaf_size, double eta, double delta) {
         in.pbox[p] = box;
     }
     for (const NearPair& e : c.near) in.near_patches[c.node_patch[e.target]].push_back(e.patch);
+    in.upn = c.upn;
     c.tree = build_tree(in, leaf_size, eta);
     c.leaf_size = leaf_size;
     c.eta = eta;
@@ -135,7 +160,8 @@ void stage_build_tree(Ctx& c, int leaf_size, double eta, double delta) {
         const Cluster& ct = T.clusters[b.t];
         const Cluster& cs = T.clusters[b.s];
         DenseBlockDev d{};
-        d.ld = 2 * ct.nodes;
+        d.ld = c.upn * ct.nodes;
+        d.upn = c.upn;
         d.row_node0 = ct.node0;
         d.row_nodes = ct.nodes;
         d.col_node0 = cs.node0;
@@ -148,7 +174,7 @@ void stage_build_tree(Ctx& c, int leaf_size, double eta, double delta) {
     for (int id : T.dense_blocks) {
         DenseBlockDev d = mkblk(T.blocks[id]);
         d.offset = off_d;
-        off_d += (int64_t)d.ld * 2 * d.col_nodes;
+        off_d += (int64_t)d.ld * c.upn * d.col_nodes;
         c.dblk.push_back(d);
     }
     c.lblk.clear();
@@ -172,6 +198,26 @@ void stage_build_tree(Ctx& c, int leaf_size, double eta, double delta) {
     st.t_tree = now_s() - t0;
 }
 
+// Plain-rule N-Mueller entries of the given blocks (host list and its device
+// copy; offsets and leading dimensions into dst): tiles of 32 row nodes
+// against one source patch.
+void fill_blocks_nm(Ctx& c, const std::vector<DenseBlockDev>& blocks, const DenseBlockDev* d_blocks, zd* dst) {
+    std::vector<DenseTile> tiles;
+    for (int b = 0; b < (int)blocks.size(); ++b) {
+        const DenseBlockDev& d = blocks[b];
+        const int q = c.objs[d.obj].q;
+        for (int r0 = 0; r0 < d.row_nodes; r0 += 32)
+            for (int c0 = 0; c0 < d.col_nodes; c0 += q * q) tiles.push_back(DenseTile{b, r0, c0, q});
+    }
+    if (tiles.empty()) return;
+    DBuf<DenseTile> d_tiles;
+    d_tiles.upload(tiles, c.stream);
+    k_far_fill_nm<double><<<(unsigned)tiles.size(), 256, 0, c.stream>>>(
+        d_tiles.p, (int)tiles.size(), d_blocks, c.d_tree_node.p, c.nd, c.d_objs.p, c.d_dmat.p, dst);
+    check_launch("k_far_fill_nm");
+    c.sync();   // the tile list is released on return
+}
+
 void stage_fill(Ctx& c, int n_ang, int n_rad) {
     const double t0 = now_s();
     const Tree& T = c.tree;
@@ -192,8 +238,9 @@ void stage_fill(Ctx& c, int n_ang, int n_rad) {
     int qmax = 0;
     for (const auto& p : c.patches) qmax = std::max(qmax, p.q);
     const int q2 = qmax * qmax;
+    const int64_t stride = (int64_t)c.upn * c.upn * q2;   // entries of one (target, patch) pair
     DBuf<zd> vals;
-    vals.alloc((size_t)np * 4 * q2);
+    vals.alloc((size_t)np * stride);
     hipEvent_t e0, e1;
     CBIE_HIP(hipEventCreate(&e0));
     CBIE_HIP(hipEventCreate(&e1));
@@ -201,27 +248,38 @@ void stage_fill(Ctx& c, int n_ang, int n_rad) {
     const int64_t chunk = 1 << 20;
     for (int64_t p0 = 0; p0 < np; p0 += chunk) {
         const int64_t cnt = std::min(chunk, np - p0);
-        k_quad<<<(unsigned)cnt, 256, 0, c.stream>>>(c.d_patches.p, c.d_objs.p, c.nd, c.d_near.p + p0, cnt,
-                                                    c.d_fej11_x.p, c.d_fej01_x.p, c.d_fej01_w.p, rule,
-                                                    (int64_t)4 * q2, vals.p + p0 * 4 * q2);
-        check_launch("k_quad");
+        if (c.upn == 4) {
+            k_quad_nm<<<(unsigned)cnt, 256, 0, c.stream>>>(c.d_patches.p, c.d_objs.p, c.nd, c.d_near.p + p0, cnt,
+                                                           c.d_fej11_x.p, c.d_fej01_x.p, c.d_fej01_w.p, c.d_dmat.p,
+                                                           rule, stride, vals.p + p0 * stride);
+            check_launch("k_quad_nm");
+        } else {
+            k_quad<<<(unsigned)cnt, 256, 0, c.stream>>>(c.d_patches.p, c.d_objs.p, c.nd, c.d_near.p + p0, cnt,
+                                                        c.d_fej11_x.p, c.d_fej01_x.p, c.d_fej01_w.p, rule, stride,
+                                                        vals.p + p0 * stride);
+            check_launch("k_quad");
+        }
     }
     CBIE_HIP(hipEventRecord(e1, c.stream));
 
     // 2) far entries of every dense block
     c.dense.alloc((size_t)c.stats.dense_entries);
-    std::vector<DenseTile> tiles;
-    for (int b = 0; b < (int)c.dblk.size(); ++b) {
-        const DenseBlockDev& d = c.dblk[b];
-        for (int r0 = 0; r0 < d.row_nodes; r0 += 64)
-            for (int c0 = 0; c0 < d.col_nodes; c0 += 16) tiles.push_back(DenseTile{b, r0, c0, 0});
-    }
-    DBuf<DenseTile> d_tiles;
-    d_tiles.upload(tiles, c.stream);
-    if (!tiles.empty()) {
-        k_far_fill<double><<<(unsigned)tiles.size(), 256, 0, c.stream>>>(
-            d_tiles.p, (int)tiles.size(), c.d_dblk.p, c.d_tree_node.p, c.nd, c.d_objs.p, c.dense.p);
-        check_launch("k_far_fill");
+    if (c.upn == 4) {
+        fill_blocks_nm(c, c.dblk, c.d_dblk.p, c.dense.p);
+    } else {
+        std::vector<DenseTile> tiles;
+        for (int b = 0; b < (int)c.dblk.size(); ++b) {
+            const DenseBlockDev& d = c.dblk[b];
+            for (int r0 = 0; r0 < d.row_nodes; r0 += 64)
+                for (int c0 = 0; c0 < d.col_nodes; c0 += 16) tiles.push_back(DenseTile{b, r0, c0, 0});
+        }
+        DBuf<DenseTile> d_tiles;
+        d_tiles.upload(tiles, c.stream);
+        if (!tiles.empty()) {
+            k_far_fill<double><<<(unsigned)tiles.size(), 256, 0, c.stream>>>(
+                d_tiles.p, (int)tiles.size(), c.d_dblk.p, c.d_tree_node.p, c.nd, c.d_objs.p, c.dense.p);
+            check_launch("k_far_fill");
+        }
     }
 
     // 3) overwrite near/self entries: destination block of each pair
@@ -261,8 +319,8 @@ void stage_fill(Ctx& c, int n_ang, int n_rad) {
     DBuf<NearDest> d_dest;
     d_dest.upload(dest, c.stream);
     if (np > 0) {
-        k_near_scatter<double><<<(unsigned)np, 256, 0, c.stream>>>(d_dest.p, np, (int64_t)4 * q2, vals.p,
-                                                                  c.d_dblk.p, c.dense.p);
+        k_near_scatter<double><<<(unsigned)np, 256, 0, c.stream>>>(d_dest.p, np, stride, vals.p, c.d_dblk.p,
+                                                                  c.dense.p);
         check_launch("k_near_scatter");
     }
     c.sync();
@@ -286,6 +344,22 @@ void stage_export_dense(Ctx& c, zd* A, long ld) {
         if (c.state >= ST_COMPRESSED) {
             void export_lowrank(Ctx & c, zd * A, long ld);
             export_lowrank(c, A, ld);
+        } else if (c.upn == 4) {
+            // plain-rule entries of each admissible block, through a dense copy
+            for (const DenseBlockDev& d0 : c.lblk) {
+                DenseBlockDev d = d0;
+                d.offset = 0;
+                d.ld = c.upn * d.row_nodes;
+                DBuf<zd> tmp;
+                tmp.alloc((size_t)d.ld * c.upn * d.col_nodes);
+                DBuf<DenseBlockDev> d_b;
+                std::vector<DenseBlockDev> one{d};
+                d_b.upload(one, c.stream);
+                fill_blocks_nm(c, one, d_b.p, tmp.p);
+                k_export_dense_block<<<dim3(64, 1), 256, 0, c.stream>>>(d_b.p, 1, c.d_tree_node.p, tmp.p, A, ld);
+                check_launch("k_export_dense_block");
+                c.sync();
+            }
         } else {
             dim3 grid(64, (unsigned)c.lblk.size());
             k_export_far<<<grid, 256, 0, c.stream>>>(c.d_lblk.p, (int)c.lblk.size(), c.d_tree_node.p, c.nd,

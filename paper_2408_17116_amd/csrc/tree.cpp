@@ -38,6 +38,7 @@ Tree build_tree(const TreeInput& in, int leaf_unknowns, double eta) {
         Cluster c;
         c.obj = obj;
         c.level = level;
+        c.upn = in.upn;
         int nodes = 0;
         for (int d = 0; d < 3; ++d) { c.bmin[d] = 1e300; c.bmax[d] = -1e300; }
         for (int p : ps) {
@@ -50,7 +51,7 @@ Tree build_tree(const TreeInput& in, int leaf_unknowns, double eta) {
         c.nodes = nodes;
         const int id = (int)T.clusters.size();
         T.clusters.push_back(c);
-        if (2 * (int64_t)nodes <= leaf_unknowns || ps.size() == 1) {
+        if ((int64_t)in.upn * nodes <= leaf_unknowns || ps.size() == 1) {
             Cluster& cc = T.clusters[id];
             cc.p0 = (int)T.patch_order.size();
             for (int p : ps) T.patch_order.push_back(p);

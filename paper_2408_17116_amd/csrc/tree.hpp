@@ -12,10 +12,11 @@ struct Cluster {
     int obj = 0;
     int level = 0;
     int child[2] = {-1, -1};
+    int upn = 2;                 // unknowns per node
     double bmin[3], bmax[3];     // bounding box of the cluster's nodes
     bool leaf() const { return child[0] < 0; }
-    int64_t unk0() const { return 2 * (int64_t)node0; }
-    int64_t nunk() const { return 2 * (int64_t)nodes; }
+    int64_t unk0() const { return upn * (int64_t)node0; }
+    int64_t nunk() const { return upn * (int64_t)nodes; }
 };
 
 enum BlockType { BLK_DENSE = 0, BLK_LR = 1, BLK_HIER = 2 };
@@ -36,6 +37,7 @@ struct TreeInput {
     // near sets per patch: original patch indices near to some node of the patch
     std::vector<std::vector<int>> near_patches;
     int n_objs;
+    int upn = 2;                            // unknowns per node
 };
 
 struct Tree {
