@@ -10,7 +10,11 @@ H-LU, and the 16-right-hand-side solve.  Two pipelines are timed:
 Inputs (patch tables, wave directions) are generated before the timed
 region; every step rebuilds everything from them on the GPU.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu]
+A second workload is reported beside it (not the value): the dielectric
+sphere eps_r = 16, ka = 5, 96 patches q = 8, 24576 unknowns, N-Mueller
+formulation, one plane wave, one step per pipeline after one warmup.
+
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-dielectric]
 """
 from __future__ import annotations
 
@@ -24,9 +28,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
-def run_pipeline(cbie, spec, kh, pol, prec, ir_tol):
+def run_pipeline(cbie, spec, kh, pol, prec, ir_tol, profile=True):
     s = cbie.Solver([spec])
-    s.set_profiling(True)
+    s.set_profiling(profile)
     s.build_tree(leaf_size=256, eta=1.0, near_delta=1.0)
     s.fill()
     s.compress(1e-6)
@@ -36,6 +40,35 @@ def run_pipeline(cbie, spec, kh, pol, prec, ir_tol):
     st = s.stats()
     st["ir_iterations"] = it
     return s, x, st
+
+
+def dielectric(cbie, W, precs, names):
+    """N-Mueller workload: seconds and unknowns/s per pipeline (one warmup,
+    one timed step), refinement sweeps and the residual against the stored
+    operator."""
+    import numpy as np
+    import torch
+    spec = W.sphere_dielectric()
+    kh, pol = np.array([[0.0, 0.0, 1.0]]), np.array([[1.0, 0.0, 0.0]])
+    out = {"workload": "dielectric sphere eps_r=16, ka=5, 96 patches q=8, 24576 unknowns, N-Mueller, "
+                       "leaf 256, eta 1, ACA 1e-6, 1 plane wave"}
+    for name in names:
+        prec = precs[name]
+        s, x, st = run_pipeline(cbie, spec, kh, pol, prec, 1e-10, profile=False)
+        s.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s, x, st = run_pipeline(cbie, spec, kh, pol, prec, 1e-10, profile=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        b = s.rhs_planewave(kh, pol)
+        res = (torch.linalg.norm(s.matvec(x) - b) / torch.linalg.norm(b)).item()
+        s.close()
+        out[name] = {"seconds": dt, "unknowns_per_s": spec.n_unknowns / dt, "ir_iterations": st["ir_iterations"],
+                     "residual": res, "phases_s": {p: st["t_" + p] for p in ("tree", "fill", "compress", "factor",
+                                                                               "solve")}}
+        print(f"[bench] dielectric {name}: {dt:.2f} s", file=sys.stderr, flush=True)
+    return out
 
 
 def cpu_baseline(spec, kh, pol, budget_s=20.0):
@@ -86,6 +119,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--pipelines", default="mixed,fp64")
+    ap.add_argument("--no-dielectric", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the H-matrix solve of one object is not "
@@ -147,6 +181,8 @@ def main():
     }
     for name, (d, s2) in results.items():
         line.setdefault("pipelines", {})[name] = {"seconds": d, "unknowns_per_s": N / d}
+    if not args.no_dielectric:
+        line["dielectric_sphere"] = dielectric(cbie, W, precs, args.pipelines.split(","))
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(spec, kh, pol)
     print(json.dumps(line))

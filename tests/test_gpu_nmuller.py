@@ -142,3 +142,36 @@ def test_sampled_rows_at_dielectric_sphere():
     print(f"rows {rows}: err {err:.2e}")
     assert err < 1e-8
     s.close()
+
+
+def test_dielectric_sphere_workload_end_to_end():
+    """eps_r = 16, ka = 5, 24576 unknowns, ACA 1e-6, complex64 H-LU with FP64
+    refinement: the residual against the stored operator, and the Mie series
+    (its gap here is the discretization's: q = 8 points per patch side with
+    the interior wavenumber 4 k0)."""
+    import torch
+    from oracle import post
+    from paper_2408_17116_amd import cbie
+    spec = W.sphere_dielectric()
+    s = _solver(spec, leaf=256)
+    s.fill()
+    s.compress(1e-6)
+    s.factor(cbie.PREC_C64_IR)
+    b = s.rhs_planewave(KH, POL)
+    x, it = s.solve(b, tol=1e-10, maxit=30)
+    res = (torch.linalg.norm(s.matvec(x) - b) / torch.linalg.norm(b)).item()
+    nd = G.build_nodes(spec)
+    J, M = Mu.currents(nd, x.cpu().numpy()[:, 0])
+    Jm, Mm = mie.dielectric_surface_currents(spec.k0, 1.0, spec.eps_r, 1.0, nd.r)
+    eJ = np.linalg.norm(J - Jm) / np.linalg.norm(Jm)
+    th = np.arange(0, 181)
+    sE, sH = mie.dielectric_rcs(spec.k0, 1.0, spec.eps_r, 1.0, np.deg2rad(th))
+    E0 = s.farfield(x, post.plane_cut(th, 0.0))[0]
+    E90 = s.farfield(x, post.plane_cut(th, 90.0))[0]
+    r0, r90 = 4 * np.pi * np.sum(np.abs(E0) ** 2, 1), 4 * np.pi * np.sum(np.abs(E90) ** 2, 1)
+    erc = max(np.linalg.norm(r0 - sE) / np.linalg.norm(sE), np.linalg.norm(r90 - sH) / np.linalg.norm(sH))
+    print(f"sweeps {it}, residual {res:.1e}, J vs Mie {eJ:.2e}, RCS vs Mie {erc:.2e}")
+    assert res < 1e-9
+    assert erc < 1e-4
+    assert eJ < 2e-3
+    s.close()
