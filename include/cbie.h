@@ -130,6 +130,10 @@ cbie_status cbie_factor(cbie_ctx* ctx, cbie_precision prec);
  * r = b - A x (FP64, stored operator), x += LU^{-1} r until
  * max_j |r_j|/|b_j| <= ir_tol or ir_maxit sweeps (ENOCONV then, x holds
  * the last iterate).  ir_iters_out (may be NULL) receives the sweep count.
+ * The substitution program (eqs. 26-28) is recorded once per factorization
+ * and number of right-hand sides, captured into a HIP graph on a private
+ * stream, and replayed for every later substitution (the refinement sweeps
+ * and later solves); the context stream waits on the replay through events.
  * Errors: ESTATE, EINVAL, ENOCONV, EHIP. */
 cbie_status cbie_solve(cbie_ctx* ctx, int nrhs, const void* b_dev, void* x_dev, long ld,
                        double ir_tol, int ir_maxit, int* ir_iters_out);
@@ -178,6 +182,10 @@ typedef struct {
      * predicted width was too small; ACA workspace of the pass(es), bytes */
     int64_t aca_fallbacks;
     double aca_workspace_bytes;
+    /* solve: substitutions run as a replay of the captured HIP graph of the
+     * program recorded by the first solve with this factorization and this
+     * number of right-hand sides (cumulative over the factorization) */
+    int64_t solve_replays;
 } cbie_stats;
 cbie_status cbie_get_stats(cbie_ctx* ctx, void* stats_out, size_t bytes);
 

@@ -56,7 +56,7 @@ class Stats(C.Structure):
         ("factor_flops", C.c_int64), ("n_kernel_launches", C.c_int64),
         ("ir_iterations", C.c_int64), ("quad_seconds", C.c_double),
         ("gemm_launches", C.c_int64), ("gemm_flops", C.c_double), ("gemm_seconds", C.c_double),
-        ("aca_fallbacks", C.c_int64), ("aca_workspace_bytes", C.c_double)]
+        ("aca_fallbacks", C.c_int64), ("aca_workspace_bytes", C.c_double), ("solve_replays", C.c_int64)]
 
 
 _lib = None

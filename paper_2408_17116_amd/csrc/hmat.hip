@@ -23,6 +23,7 @@
 #include <cmath>
 #include <cstring>
 #include <functional>
+#include <memory>
 #include <unordered_map>
 
 #include "batch.hpp"
@@ -392,6 +393,56 @@ template <typename T> struct HF {
     Arena<T> wsp[2], wsr;
     int wsp_cur = 0;
 
+    // A recorded substitution program kept for replay.  The right-hand
+    // sides live in X (n_unk x nrhs, factor precision); descriptors, split-k
+    // workspace and temporaries belong to the replay, so its launch sequence
+    // stays valid until the factorization is destroyed.  The sequence is
+    // captured once into a HIP graph on a private stream; a replay is one
+    // graph launch ordered against the context stream by two events.
+    struct Replay {
+        int nrhs = 0;
+        DBuf<cplx<T>> X;
+        Arena<T> scratch, ws;
+        DBuf<char> desc;
+        std::vector<std::function<void(hipStream_t)>> seq;
+        hipStream_t gs = nullptr;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        hipEvent_t ev[2] = {nullptr, nullptr};
+        Replay() {
+            scratch.chunk_elems = size_t(1) << 22;
+            ws.chunk_elems = size_t(1) << 22;
+        }
+        ~Replay() {
+            if (exec) (void)hipGraphExecDestroy(exec);
+            if (graph) (void)hipGraphDestroy(graph);
+            for (hipEvent_t e : ev)
+                if (e) (void)hipEventDestroy(e);
+            if (gs) (void)hipStreamDestroy(gs);
+        }
+    };
+    std::unique_ptr<Replay> rp;
+    Replay* rec_into = nullptr;   // set while a program is recorded for replay
+    int64_t replays = 0;
+
+    void capture_replay(Replay& R) {
+        CBIE_HIP(hipStreamCreateWithFlags(&R.gs, hipStreamNonBlocking));
+        CBIE_HIP(hipEventCreateWithFlags(&R.ev[0], hipEventDisableTiming));
+        CBIE_HIP(hipEventCreateWithFlags(&R.ev[1], hipEventDisableTiming));
+        CBIE_HIP(hipStreamBeginCapture(R.gs, hipStreamCaptureModeThreadLocal));
+        for (auto& f : R.seq) f(R.gs);
+        CBIE_HIP(hipStreamEndCapture(R.gs, &R.graph));
+        CBIE_HIP(hipGraphInstantiate(&R.exec, R.graph, nullptr, nullptr, 0));
+    }
+    void run_replay(Replay& R) {
+        CBIE_HIP(hipEventRecord(R.ev[0], s));
+        CBIE_HIP(hipStreamWaitEvent(R.gs, R.ev[0], 0));
+        CBIE_HIP(hipGraphLaunch(R.exec, R.gs));
+        CBIE_HIP(hipEventRecord(R.ev[1], R.gs));
+        CBIE_HIP(hipStreamWaitEvent(s, R.ev[1], 0));
+        ++replays;
+    }
+
     // one batched GEMM launch of algorithmic flops fl, timed when profiling
     void launch_gemm(const GemmDesc<T>* d, const GemmTile* t, int ntiles, int sh, double fl) {
         Ctx::KernelTimer& tm = c.gemm_timer;
@@ -502,7 +553,7 @@ template <typename T> struct HF {
         // the program that last used this workspace finished before the
         // previous program was staged
         wsp_cur ^= 1;
-        Arena<T>& ws = wsp[wsp_cur];
+        Arena<T>& ws = rec_into ? rec_into->ws : wsp[wsp_cur];
         std::vector<Seg> seg(L);
         std::vector<char> host;
         auto put = [&](const void* src, size_t bytes) {
@@ -557,22 +608,43 @@ template <typename T> struct HF {
         // the previous use of the staging buffers must be complete
         wait_stream();
         std::memcpy(pinned, host.data(), host.size());
-        DBuf<char>& dev = descbuf;
+        DBuf<char>& dev = rec_into ? rec_into->desc : descbuf;
         if (dev.n < host.size()) dev.alloc(std::max(host.size(), (size_t)1 << 20));
         CBIE_HIP(hipMemcpyAsync(dev.p, pinned, host.size(), hipMemcpyHostToDevice, s));
+        auto keep = [&](std::function<void(hipStream_t)> f) {
+            if (rec_into) rec_into->seq.push_back(std::move(f));
+        };
         for (int lv = 0; lv < L; ++lv) {
             const Seg& sg = seg[lv];
-            if (sg.nl) { leaf_batched<T>(s, (const LeafDesc<T>*)(dev.p + sg.l), sg.nl); ++launches; }
+            if (sg.nl) {
+                const LeafDesc<T>* dl = (const LeafDesc<T>*)(dev.p + sg.l);
+                const int n = sg.nl;
+                leaf_batched<T>(s, dl, n);
+                keep([=](hipStream_t st) { leaf_batched<T>(st, dl, n); });
+                ++launches;
+            }
             for (int sh = 0; sh < 3; ++sh)
-                if (sg.ngt[sh])
-                    launch_gemm((const GemmDesc<T>*)(dev.p + sg.g[sh]), (const GemmTile*)(dev.p + sg.gt[sh]),
-                                sg.ngt[sh], sh, sg.fl[sh]);
+                if (sg.ngt[sh]) {
+                    const GemmDesc<T>* dg = (const GemmDesc<T>*)(dev.p + sg.g[sh]);
+                    const GemmTile* dt = (const GemmTile*)(dev.p + sg.gt[sh]);
+                    const int nt = sg.ngt[sh];
+                    launch_gemm(dg, dt, nt, sh, sg.fl[sh]);
+                    keep([=](hipStream_t st) { gemm_batched<T>(st, dg, dt, nt, sh); });
+                }
             if (sg.nrt) {
-                reduce_batched<T>(s, (const ReduceDesc<T>*)(dev.p + sg.r), (const CopyTile*)(dev.p + sg.rt), sg.nrt);
+                const ReduceDesc<T>* dr = (const ReduceDesc<T>*)(dev.p + sg.r);
+                const CopyTile* dt = (const CopyTile*)(dev.p + sg.rt);
+                const int nt = sg.nrt;
+                reduce_batched<T>(s, dr, dt, nt);
+                keep([=](hipStream_t st) { reduce_batched<T>(st, dr, dt, nt); });
                 ++launches;
             }
             if (sg.nct) {
-                copy_batched<T>(s, (const CopyDesc<T>*)(dev.p + sg.c), (const CopyTile*)(dev.p + sg.ct), sg.nct);
+                const CopyDesc<T>* dc = (const CopyDesc<T>*)(dev.p + sg.c);
+                const CopyTile* dt = (const CopyTile*)(dev.p + sg.ct);
+                const int nt = sg.nct;
+                copy_batched<T>(s, dc, dt, nt);
+                keep([=](hipStream_t st) { copy_batched<T>(st, dc, dt, nt); });
                 ++launches;
             }
         }
@@ -1649,6 +1721,40 @@ __global__ void k_add(int64_t n, const zd* __restrict__ d, zd* __restrict__ x) {
     if (e < n) x[e] = x[e] + d[e];
 }
 
+// out = LU^{-1} rhs (tree order, FP64 in and out).  The first call for a
+// factorization and a number of right-hand sides records the substitution
+// program into a replay (and runs it); later calls copy rhs into the
+// replay's buffer and launch its captured graph.
+template <typename T> static void lu_solve_replay(Ctx& c, HF<T>& f, int nrhs, const zd* rhs, zd* out) {
+    const int64_t NN = c.n_unk * nrhs;
+    hipStream_t s = c.stream;
+    if (!f.rp || f.rp->nrhs != nrhs) {
+        f.rp.reset();
+        f.wait_stream();   // programs that used the previous replay's buffers are complete
+        auto R = std::make_unique<typename HF<T>::Replay>();
+        R->nrhs = nrhs;
+        R->X.alloc(NN);
+        convert<double, T>(s, NN, rhs, R->X.p);
+        std::swap(f.scratch, R->scratch);
+        f.rec_into = R.get();
+        try {
+            lu_solve_tree(c, f, R->X.p, nrhs);
+        } catch (...) {
+            f.rec_into = nullptr;
+            std::swap(f.scratch, R->scratch);
+            throw;
+        }
+        f.rec_into = nullptr;
+        std::swap(f.scratch, R->scratch);
+        f.capture_replay(*R);
+        f.rp = std::move(R);
+    } else {
+        convert<double, T>(s, NN, rhs, f.rp->X.p);
+        f.run_replay(*f.rp);
+    }
+    convert<T, double>(s, NN, f.rp->X.p, out);
+}
+
 void stage_solve(Ctx& c, int nrhs, const zd* b, zd* x, long ld, double tol, int maxit, int* iters) {
     const double t0 = now_s();
     CBIE_REQUIRE(c.hm, CBIE_ESTATE, "no factorization");
@@ -1669,8 +1775,12 @@ void stage_solve(Ctx& c, int nrhs, const zd* b, zd* x, long ld, double tol, int 
 
     DBuf<zf> w;
     if (c.hm->prec != CBIE_PREC_C128) w.alloc(NN);
+    const bool replay = !(getenv("CBIE_SOLVE_REPLAY") && atoi(getenv("CBIE_SOLVE_REPLAY")) == 0);
     auto correction = [&](const zd* rhs, zd* out) {   // out = LU^{-1} rhs
-        if (c.hm->prec == CBIE_PREC_C128) {
+        if (replay) {
+            if (c.hm->prec == CBIE_PREC_C128) lu_solve_replay(c, *c.hm->f64, nrhs, rhs, out);
+            else lu_solve_replay(c, *c.hm->f32, nrhs, rhs, out);
+        } else if (c.hm->prec == CBIE_PREC_C128) {
             if (out != rhs) CBIE_HIP(hipMemcpyAsync(out, rhs, sizeof(zd) * NN, hipMemcpyDeviceToDevice, s));
             lu_solve_tree(c, *c.hm->f64, out, nrhs);
         } else {
@@ -1704,6 +1814,7 @@ void stage_solve(Ctx& c, int nrhs, const zd* b, zd* x, long ld, double tol, int 
     c.stats.gemm_seconds = c.gemm_timer.seconds;
     if (iters) *iters = it;
     c.stats.ir_iterations = it;
+    c.stats.solve_replays = c.hm->prec == CBIE_PREC_C128 ? c.hm->f64->replays : c.hm->f32->replays;
     c.stats.t_solve = now_s() - t0;
     CBIE_REQUIRE(ok, CBIE_ENOCONV, "iterative refinement did not reach the tolerance");
 }
