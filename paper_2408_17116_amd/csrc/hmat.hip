@@ -134,6 +134,99 @@ inline Res rect(int kind, int id, int64_t r0, int64_t m, int64_t c0, int64_t n) 
     return Res{kind, id, r0, r0 + m, c0, c0 + n};
 }
 
+// Tile-shape autotuner.  Products are classed by m and n (<= 32, 64, 128,
+// 256, larger) and k (< 64, < 256, larger).  For each class the three tile
+// shapes are timed (HIP events, after a warm-up launch) on a batch of
+// products of the class's representative size, large enough to fill the
+// chip, and the fastest shape serves every later unforced product of the
+// class.  Once per process and precision, at the first factorization;
+// CBIE_AUTOTUNE=0 keeps the padded-area rule.
+template <typename T> struct Tuner {
+    static constexpr int NM = 5, NK = 3;
+    static inline bool ready = false;
+    static inline signed char table[NM][NM][NK];
+    static inline double seconds = 0.0;
+    static int mb(int m) { return m <= 32 ? 0 : m <= 64 ? 1 : m <= 128 ? 2 : m <= 256 ? 3 : 4; }
+    static int kb(int k) { return k < 64 ? 0 : k < 256 ? 1 : 2; }
+    static void tune(hipStream_t s, bool debug) {
+        if (ready) return;
+        const char* env = getenv("CBIE_AUTOTUNE");
+        if (env && atoi(env) == 0) return;
+        const double t0 = now_s();
+        const int rep_mn[NM] = {32, 64, 128, 256, 512}, rep_k[NK] = {32, 128, 512};
+        auto batch = [&](int m, int n) {
+            const int64_t t64 = (int64_t)((m + 63) / 64) * ((n + 63) / 64);
+            return (int)std::min<int64_t>(256, std::max<int64_t>(4, 4096 / t64));
+        };
+        size_t need = 0;
+        for (int i = 0; i < NM; ++i)
+            for (int j = 0; j < NM; ++j)
+                for (int l = 0; l < NK; ++l) {
+                    const size_t m = rep_mn[i], n = rep_mn[j], k = rep_k[l];
+                    need = std::max(need, (size_t)batch((int)m, (int)n) * (m * k + k * n + m * n));
+                }
+        DBuf<cplx<T>> buf;
+        buf.alloc(need);
+        CBIE_HIP(hipMemsetAsync(buf.p, 0, need * sizeof(cplx<T>), s));
+        DBuf<GemmDesc<T>> dd;
+        DBuf<GemmTile> dt;
+        hipEvent_t e0, e1;
+        CBIE_HIP(hipEventCreate(&e0));
+        CBIE_HIP(hipEventCreate(&e1));
+        for (int i = 0; i < NM; ++i)
+            for (int j = 0; j < NM; ++j)
+                for (int l = 0; l < NK; ++l) {
+                    const int m = rep_mn[i], n = rep_mn[j], k = rep_k[l], B = batch(m, n);
+                    std::vector<GemmDesc<T>> g(B);
+                    size_t off = 0;
+                    for (int b = 0; b < B; ++b) {
+                        GemmDesc<T>& d = g[b];
+                        d = GemmDesc<T>{};
+                        d.m = m; d.n = n; d.k = k;
+                        d.alpha = cplx<T>{(T)1, (T)0};
+                        d.beta = cplx<T>{(T)0, (T)0};
+                        d.A = buf.p + off; off += (size_t)m * k; d.lda = m;
+                        d.B = buf.p + off; off += (size_t)k * n; d.ldb = k;
+                        d.C = buf.p + off; off += (size_t)m * n; d.ldc = m;
+                    }
+                    dd.upload(g, s);
+                    float best = 0.f;
+                    int best_sh = kTile64x64;
+                    for (int sh = 0; sh < 3; ++sh) {
+                        std::vector<GemmTile> t;
+                        for (int b = 0; b < B; ++b)
+                            for (int m0 = 0; m0 < m; m0 += tile_rows(sh))
+                                for (int n0 = 0; n0 < n; n0 += tile_cols(sh)) t.push_back(GemmTile{b, m0, n0, 0});
+                        dt.upload(t, s);
+                        gemm_batched<T>(s, dd.p, dt.p, (int)t.size(), sh);
+                        CBIE_HIP(hipEventRecord(e0, s));
+                        for (int r = 0; r < 3; ++r) gemm_batched<T>(s, dd.p, dt.p, (int)t.size(), sh);
+                        CBIE_HIP(hipEventRecord(e1, s));
+                        CBIE_HIP(hipEventSynchronize(e1));
+                        float ms = 0.f;
+                        CBIE_HIP(hipEventElapsedTime(&ms, e0, e1));
+                        if (sh == 0 || ms < best) { best = ms; best_sh = sh; }
+                    }
+                    table[i][j][l] = (signed char)best_sh;
+                }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        CBIE_HIP(hipStreamSynchronize(s));
+        seconds = now_s() - t0;
+        ready = true;
+        if (debug) {
+            fprintf(stderr, "[cbie] tile tuning %.3f s (shape per m class, n class; k < 64 | < 256 | larger):\n",
+                    seconds);
+            for (int i = 0; i < NM; ++i) {
+                fprintf(stderr, "[cbie]  ");
+                for (int j = 0; j < NM; ++j)
+                    fprintf(stderr, " %d%d%d", table[i][j][0], table[i][j][1], table[i][j][2]);
+                fprintf(stderr, "\n");
+            }
+        }
+    }
+};
+
 template <typename T> struct HF {
     Ctx& c;
     hipStream_t s;
@@ -312,7 +405,8 @@ template <typename T> struct HF {
     }
 
     // tile shape with the least padding; the square tile on ties
-    static int pick_shape(int m, int n) {
+    static int pick_shape(int m, int n, int k) {
+        if (Tuner<T>::ready) return Tuner<T>::table[Tuner<T>::mb(m)][Tuner<T>::mb(n)][Tuner<T>::kb(k)];
         auto area = [&](int sh) {
             const int64_t br = tile_rows(sh), bc = tile_cols(sh);
             return ((m + br - 1) / br * br) * ((n + bc - 1) / bc * bc);
@@ -363,7 +457,7 @@ template <typename T> struct HF {
             b.g[sh].push_back(d);
             return;
         }
-        if (forced) sh = pick_shape(d.m, d.n);
+        if (forced) sh = pick_shape(d.m, d.n, d.k);
         b.fl[sh] += 8.0 * d.m * d.n * d.k;
         const int64_t mn = (int64_t)d.m * d.n;
         b.ws_left -= mn * S;
@@ -567,10 +661,11 @@ template <typename T> struct HF {
             Batch bt;
             ws.reset();
             int64_t lt = 0;
-            for (int i : gl[lv]) lt += ntiles(gd[i], gshape[i] >= 0 ? gshape[i] : pick_shape(gd[i].m, gd[i].n));
+            for (int i : gl[lv])
+                lt += ntiles(gd[i], gshape[i] >= 0 ? gshape[i] : pick_shape(gd[i].m, gd[i].n, gd[i].k));
             for (int i : gl[lv]) {
                 const GemmDesc<T>& d = gd[i];
-                add_gemm(bt, d, gshape[i] >= 0 ? gshape[i] : pick_shape(d.m, d.n), gshape[i] >= 0, lt, ws);
+                add_gemm(bt, d, gshape[i] >= 0 ? gshape[i] : pick_shape(d.m, d.n, d.k), gshape[i] >= 0, lt, ws);
             }
             for (int sh = 0; sh < 3; ++sh) {
                 sg.g[sh] = put(bt.g[sh].data(), bt.g[sh].size() * sizeof(GemmDesc<T>));
@@ -719,9 +814,9 @@ template <typename T> struct HF {
         if (g.empty()) return;
         Batch bt;
         int64_t lt = 0;
-        for (const GemmDesc<T>& d : g) lt += ntiles(d, pick_shape(d.m, d.n));
+        for (const GemmDesc<T>& d : g) lt += ntiles(d, pick_shape(d.m, d.n, d.k));
         wsr.reset();   // the previous launch's reductions precede these products on the stream
-        for (const GemmDesc<T>& d : g) add_gemm(bt, d, pick_shape(d.m, d.n), false, lt, wsr);
+        for (const GemmDesc<T>& d : g) add_gemm(bt, d, pick_shape(d.m, d.n, d.k), false, lt, wsr);
         for (int sh = 0; sh < 3; ++sh) {
             if (bt.t[sh].empty()) continue;
             flops += bt.fl[sh];
@@ -1640,6 +1735,7 @@ template <typename T> static std::shared_ptr<HF<T>> make_factor(Ctx& c) {
 }
 
 template <typename T> static void run_factor(Ctx& c, HF<T>& f) {
+    Tuner<T>::tune(c.stream, f.debug);
     for (int root : c.tree.block_roots) f.hlu(root);
     f.flush_all();
     std::vector<int> info(c.dblk.size());
