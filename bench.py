@@ -15,6 +15,9 @@ sphere eps_r = 16, ka = 5, 96 patches q = 8, 24576 unknowns, N-Mueller
 formulation, one plane wave, one step per pipeline after one warmup.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-dielectric]
+python bench.py --copy-probe   (a plain 1 GiB read + 1 GiB write elementwise
+                                kernel, three launches: the reference for
+                                scaling HBM traffic counters)
 """
 from __future__ import annotations
 
@@ -71,6 +74,21 @@ def dielectric(cbie, W, precs, names):
     return out
 
 
+def gemm_traffic(pipeline):
+    """HBM bytes per k_zgemm launch from the committed counter runs
+    (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known size), or
+    None when the GEMM source has changed since they were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "k_zgemm_traffic_sphere_ka20_49152_mixed.json")
+    if pipeline != "mixed" or not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    for src, sha in rec["source_sha256"].items():
+        if hashlib.sha256(open(os.path.join(ROOT, src), "rb").read()).hexdigest() != sha:
+            return None
+    return rec["traffic_bytes_per_launch"]
+
+
 def cpu_baseline(spec, kh, pol, budget_s=20.0):
     """Time the oracle (dense fill by rows + LAPACK LU + solve) on a bounded
     sample and scale it to the full workload's unknowns/s."""
@@ -120,7 +138,19 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--pipelines", default="mixed,fp64")
     ap.add_argument("--no-dielectric", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
+    if args.copy_probe:
+        import torch
+        n = 1 << 28                                   # float32: 1 GiB
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe": {"launches": 3, "bytes_read_per_launch": 4 * n,
+                                         "bytes_written_per_launch": 4 * n}}))
+        return
     if args.gpus != 1:
         print("bench.py: this build measures one GPU only (the H-matrix solve of one object is not "
               "sharded); run with --gpus 1", file=sys.stderr)
@@ -162,7 +192,7 @@ def main():
     peak = 157.3 if name0 == "mixed" else 78.6      # MI355X dense MFMA FP32 / FP64, TFLOP/s
     achieved = st["gemm_flops"] / st["gemm_seconds"] / 1e12 if st["gemm_seconds"] > 0 else None
     roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak if achieved else None, "traffic": None,
+                "frac": achieved / peak if achieved else None, "traffic": gemm_traffic(name0),
                 "kernel": "k_zgemm (batched complex GEMM, %s)" % ("complex64" if name0 == "mixed" else "complex128"),
                 "launches": st["gemm_launches"], "avg_launch_us": 1e6 * st["gemm_seconds"] / max(st["gemm_launches"], 1),
                 "flops_per_launch": st["gemm_flops"] / max(st["gemm_launches"], 1),

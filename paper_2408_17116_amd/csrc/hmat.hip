@@ -21,6 +21,7 @@
 // addition with truncation at the ACA tolerance).
 #include <algorithm>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <functional>
 #include <memory>
@@ -140,7 +141,9 @@ inline Res rect(int kind, int id, int64_t r0, int64_t m, int64_t c0, int64_t n) 
 // products of the class's representative size, large enough to fill the
 // chip, and the fastest shape serves every later unforced product of the
 // class.  Once per process and precision, at the first factorization;
-// CBIE_AUTOTUNE=0 keeps the padded-area rule.
+// CBIE_AUTOTUNE=0 keeps the padded-area rule.  CBIE_TUNE_FILE names a cache:
+// a table found there (written by an earlier process on the same GPU) is
+// used as is, otherwise the measured table is written to it.
 template <typename T> struct Tuner {
     static constexpr int NM = 5, NK = 3;
     static inline bool ready = false;
@@ -152,6 +155,26 @@ template <typename T> struct Tuner {
         if (ready) return;
         const char* env = getenv("CBIE_AUTOTUNE");
         if (env && atoi(env) == 0) return;
+        const char* cache = getenv("CBIE_TUNE_FILE");
+        const char* tag = sizeof(T) == 4 ? "c64" : "c128";
+        if (cache) {
+            // one line per precision: tag followed by NM*NM*NK shape digits
+            FILE* fp = fopen(cache, "r");
+            char line[256];
+            while (fp && fgets(line, sizeof line, fp)) {
+                char t[16] = {0}, d[128] = {0};
+                if (sscanf(line, "%15s %127s", t, d) == 2 && !strcmp(t, tag) && strlen(d) == NM * NM * NK) {
+                    bool ok = true;
+                    for (int e = 0; e < NM * NM * NK; ++e) ok = ok && d[e] >= '0' && d[e] <= '2';
+                    if (ok) {
+                        for (int e = 0; e < NM * NM * NK; ++e) (&table[0][0][0])[e] = (signed char)(d[e] - '0');
+                        ready = true;
+                    }
+                }
+            }
+            if (fp) fclose(fp);
+            if (ready) return;
+        }
         const double t0 = now_s();
         const int rep_mn[NM] = {32, 64, 128, 256, 512}, rep_k[NK] = {32, 128, 512};
         auto batch = [&](int m, int n) {
@@ -214,6 +237,15 @@ template <typename T> struct Tuner {
         CBIE_HIP(hipStreamSynchronize(s));
         seconds = now_s() - t0;
         ready = true;
+        if (cache) {
+            FILE* fp = fopen(cache, "a");
+            if (fp) {
+                fprintf(fp, "%s ", tag);
+                for (int e = 0; e < NM * NM * NK; ++e) fputc('0' + (&table[0][0][0])[e], fp);
+                fputc('\n', fp);
+                fclose(fp);
+            }
+        }
         if (debug) {
             fprintf(stderr, "[cbie] tile tuning %.3f s (shape per m class, n class; k < 64 | < 256 | larger):\n",
                     seconds);
