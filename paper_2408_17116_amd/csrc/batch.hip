@@ -38,8 +38,10 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc<T>* __restrict__ d
     constexpr int NA = BM * BK / 256, NB = BK * BN / 256;
     static_assert(NA >= 1 && NB >= 1 && FM >= 1 && FN >= 1, "tile shape");
     typedef typename Mfma<T>::v4 v4;
-    __shared__ cplx<T> As[BK][BM + PAD];
-    __shared__ cplx<T> Bs[BK][BN + PAD];
+    // two buffers per operand: slice i is read from one while slice i+1 is
+    // written to the other, one barrier per slice
+    __shared__ cplx<T> As[2][BK][BM + PAD];
+    __shared__ cplx<T> Bs[2][BK][BN + PAD];
     // consecutive tiles (which share operand panels) go to one XCD: the
     // hardware deals work-groups round-robin over the 8 XCDs
     const int per = (int)gridDim.x >> 3;
@@ -87,28 +89,33 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc<T>* __restrict__ d
             rb[q] = v;
         }
     };
-    load(0);
-    for (int k0 = 0; k0 < k; k0 += BK) {
-        __syncthreads();
+    auto stash = [&](int buf) {
 #pragma unroll
         for (int q = 0; q < NA; ++q) {
             const int e = tid + 256 * q;
-            if (D.ta == 0) As[e / BM][e % BM] = ra[q]; else As[e % BK][e / BK] = ra[q];
+            if (D.ta == 0) As[buf][e / BM][e % BM] = ra[q]; else As[buf][e % BK][e / BK] = ra[q];
         }
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             const int e = tid + 256 * q;
-            if (D.tb == 0) Bs[e % BK][e / BK] = rb[q]; else Bs[e / BN][e % BN] = rb[q];
+            if (D.tb == 0) Bs[buf][e % BK][e / BK] = rb[q]; else Bs[buf][e / BN][e % BN] = rb[q];
         }
-        __syncthreads();
-        if (k0 + BK < k) load(k0 + BK);
+    };
+    load(0);
+    stash(0);
+    __syncthreads();
+    for (int k0 = 0, cur = 0; k0 < k; k0 += BK, cur ^= 1) {
+        // every wave finished the previous slice (last barrier), so buffer
+        // cur ^ 1 is free; slice k0 is complete in buffer cur
+        const bool more = k0 + BK < k;
+        if (more) load(k0 + BK);
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 4) {
             cplx<T> a[FM], b[FN];
 #pragma unroll
-            for (int i = 0; i < FM; ++i) a[i] = As[kk + kq][wm * WM + 16 * i + r];
+            for (int i = 0; i < FM; ++i) a[i] = As[cur][kk + kq][wm * WM + 16 * i + r];
 #pragma unroll
-            for (int j = 0; j < FN; ++j) b[j] = Bs[kk + kq][wn * WN + 16 * j + r];
+            for (int j = 0; j < FN; ++j) b[j] = Bs[cur][kk + kq][wn * WN + 16 * j + r];
 #pragma unroll
             for (int i = 0; i < FM; ++i) {
                 const T nai = -a[i].im;
@@ -121,25 +128,38 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc<T>* __restrict__ d
                 }
             }
         }
+        if (more) stash(cur ^ 1);
+        __syncthreads();
     }
+    // Epilogue, one column group j at a time: every C value of the group is
+    // loaded before any is stored (C is read and written through the same
+    // pointer, so loads would otherwise wait for each preceding store).
     const bool zb = (D.beta.re == (T)0 && D.beta.im == (T)0);
 #pragma unroll
     for (int j = 0; j < FN; ++j) {
         const int col = n0 + wn * WN + 16 * j + r;
-        if (col >= n) continue;
+        const bool cin = col < n;
+        cplx<T>* ccol = D.C + (int64_t)(cin ? col : 0) * D.ldc;
+        cplx<T> old[FM][4];
+        if (!zb) {
 #pragma unroll
-        for (int i = 0; i < FM; ++i) {
-            const int row0 = m0 + wm * WM + 16 * i;
+            for (int i = 0; i < FM; ++i)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const int row = m0 + wm * WM + 16 * i + Mfma<T>::row(kq, v);
+                    old[i][v] = (cin && row < m) ? ccol[row] : cplx<T>{(T)0, (T)0};
+                }
+        }
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                const int row = row0 + Mfma<T>::row(kq, v);
-                if (row >= m) continue;
-                cplx<T>* cp = D.C + row + (int64_t)col * D.ldc;
+                const int row = m0 + wm * WM + 16 * i + Mfma<T>::row(kq, v);
+                if (!cin || row >= m) continue;
                 cplx<T> o = D.alpha * cplx<T>{cr[i][j][v], ci[i][j][v]};
-                if (!zb) cfma(o, D.beta, *cp);
-                *cp = o;
+                if (!zb) cfma(o, D.beta, old[i][v]);
+                ccol[row] = o;
             }
-        }
     }
 }
 
@@ -148,8 +168,9 @@ void gemm_batched(hipStream_t s, const GemmDesc<T>* d_desc, const GemmTile* d_ti
     if (ntiles <= 0) return;
     const int grid = (ntiles + 7) / 8 * 8;
     constexpr int BKW = sizeof(T) == 4 ? 16 : 8;   // deep slices of the wide tiles fit LDS
+    constexpr int BK64 = 16;
     switch (shape) {
-        case kTile64x64: k_zgemm<T, 64, 64, 2, 16><<<grid, 256, 0, s>>>(d_desc, d_tiles, ntiles); break;
+        case kTile64x64: k_zgemm<T, 64, 64, 2, BK64><<<grid, 256, 0, s>>>(d_desc, d_tiles, ntiles); break;
         case kTile256x32: k_zgemm<T, 256, 32, 4, BKW><<<grid, 256, 0, s>>>(d_desc, d_tiles, ntiles); break;
         case kTile32x256: k_zgemm<T, 32, 256, 1, BKW><<<grid, 256, 0, s>>>(d_desc, d_tiles, ntiles); break;
         default: throw Error{-7, "gemm_batched: unknown tile shape"};

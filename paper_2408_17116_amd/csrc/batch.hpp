@@ -19,7 +19,7 @@ struct GemmTile {
     int desc, m0, n0, pad;
 };
 // output tile shapes of the batched GEMM (rows x columns of C)
-enum { kTile64x64 = 0, kTile256x32 = 1, kTile32x256 = 2 };
+enum { kTile64x64 = 0, kTile256x32 = 1, kTile32x256 = 2, kNumTileShapes = 3 };
 inline int tile_rows(int shape) { return shape == kTile64x64 ? 64 : (shape == kTile256x32 ? 256 : 32); }
 inline int tile_cols(int shape) { return shape == kTile64x64 ? 64 : (shape == kTile256x32 ? 32 : 256); }
 

@@ -149,6 +149,7 @@ template <typename T> struct Tuner {
     static inline bool ready = false;
     static inline signed char table[NM][NM][NK];
     static inline double seconds = 0.0;
+    static inline double tflops[NM][NM][NK];
     static int mb(int m) { return m <= 32 ? 0 : m <= 64 ? 1 : m <= 128 ? 2 : m <= 256 ? 3 : 4; }
     static int kb(int k) { return k < 64 ? 0 : k < 256 ? 1 : 2; }
     static void tune(hipStream_t s, bool debug) {
@@ -165,7 +166,8 @@ template <typename T> struct Tuner {
                 char t[16] = {0}, d[128] = {0};
                 if (sscanf(line, "%15s %127s", t, d) == 2 && !strcmp(t, tag) && strlen(d) == NM * NM * NK) {
                     bool ok = true;
-                    for (int e = 0; e < NM * NM * NK; ++e) ok = ok && d[e] >= '0' && d[e] <= '2';
+                    const char maxd = '0' + kNumTileShapes - 1;
+                    for (int e = 0; e < NM * NM * NK; ++e) ok = ok && d[e] >= '0' && d[e] <= maxd;
                     if (ok) {
                         for (int e = 0; e < NM * NM * NK; ++e) (&table[0][0][0])[e] = (signed char)(d[e] - '0');
                         ready = true;
@@ -206,8 +208,8 @@ template <typename T> struct Tuner {
                         GemmDesc<T>& d = g[b];
                         d = GemmDesc<T>{};
                         d.m = m; d.n = n; d.k = k;
-                        d.alpha = cplx<T>{(T)1, (T)0};
-                        d.beta = cplx<T>{(T)0, (T)0};
+                        d.alpha = cplx<T>{(T)-1, (T)0};   // an update C -= A B, as in the factorization
+                        d.beta = cplx<T>{(T)1, (T)0};
                         d.A = buf.p + off; off += (size_t)m * k; d.lda = m;
                         d.B = buf.p + off; off += (size_t)k * n; d.ldb = k;
                         d.C = buf.p + off; off += (size_t)m * n; d.ldc = m;
@@ -215,7 +217,7 @@ template <typename T> struct Tuner {
                     dd.upload(g, s);
                     float best = 0.f;
                     int best_sh = kTile64x64;
-                    for (int sh = 0; sh < 3; ++sh) {
+                    for (int sh = 0; sh < kNumTileShapes; ++sh) {
                         std::vector<GemmTile> t;
                         for (int b = 0; b < B; ++b)
                             for (int m0 = 0; m0 < m; m0 += tile_rows(sh))
@@ -231,6 +233,7 @@ template <typename T> struct Tuner {
                         if (sh == 0 || ms < best) { best = ms; best_sh = sh; }
                     }
                     table[i][j][l] = (signed char)best_sh;
+                    tflops[i][j][l] = 3.0 * 8.0 * m * n * k * B / (best * 1e-3) / 1e12;
                 }
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
@@ -253,6 +256,13 @@ template <typename T> struct Tuner {
                 fprintf(stderr, "[cbie]  ");
                 for (int j = 0; j < NM; ++j)
                     fprintf(stderr, " %d%d%d", table[i][j][0], table[i][j][1], table[i][j][2]);
+                fprintf(stderr, "\n");
+            }
+            fprintf(stderr, "[cbie] TFLOP/s of the chosen shape (m class rows; n class, k class columns):\n");
+            for (int i = 0; i < NM; ++i) {
+                fprintf(stderr, "[cbie]  ");
+                for (int j = 0; j < NM; ++j)
+                    fprintf(stderr, " %5.1f %5.1f %5.1f |", tflops[i][j][0], tflops[i][j][1], tflops[i][j][2]);
                 fprintf(stderr, "\n");
             }
         }
@@ -471,17 +481,26 @@ template <typename T> struct HF {
     }
     // the GEMMs of one launch per tile shape, plus the split-k reductions
     struct Batch {
-        std::vector<GemmDesc<T>> g[3];
-        std::vector<GemmTile> t[3];
-        double fl[3] = {0.0, 0.0, 0.0};
+        std::vector<GemmDesc<T>> g[kNumTileShapes];
+        std::vector<GemmTile> t[kNumTileShapes];
+        double fl[kNumTileShapes] = {};
         std::vector<ReduceDesc<T>> rd;
         std::vector<CopyTile> rt;
         int64_t ws_left = int64_t(1) << 26;   // partial-product entries one launch may use
     };
     // sh: the product's tile shape; forced: an in-place product, which
     // keeps its shape unless it is split (its partials are not in place)
+    // debug: flops and products per (m, n, k) class of the tuner
+    double hist_fl[Tuner<T>::NM][Tuner<T>::NM][Tuner<T>::NK] = {};
+    int64_t hist_n[Tuner<T>::NM][Tuner<T>::NM][Tuner<T>::NK] = {};
+    int64_t hist_split = 0;
     void add_gemm(Batch& b, const GemmDesc<T>& d, int sh, bool forced, int64_t launch_tiles, Arena<T>& ws) {
+        if (debug) {
+            hist_fl[Tuner<T>::mb(d.m)][Tuner<T>::mb(d.n)][Tuner<T>::kb(d.k)] += 8.0 * d.m * d.n * d.k;
+            ++hist_n[Tuner<T>::mb(d.m)][Tuner<T>::mb(d.n)][Tuner<T>::kb(d.k)];
+        }
         int S = nsplit(d, sh, launch_tiles);
+        if (debug && S > 1) ++hist_split;
         if ((int64_t)S * d.m * d.n > b.ws_left) S = 1;
         if (S <= 1) {
             b.fl[sh] += 8.0 * d.m * d.n * d.k;
@@ -672,9 +691,9 @@ template <typename T> struct HF {
         // one pinned staging buffer: per level and tile shape [gemm descs][gemm
         // tiles], then [copy descs][copy tiles][leaf descs]
         struct Seg {
-            size_t g[3], gt[3], r, rt, c, ct, l;
-            int ng[3], ngt[3], nr, nrt, nc, nct, nl;
-            double fl[3];
+            size_t g[kNumTileShapes], gt[kNumTileShapes], r, rt, c, ct, l;
+            int ng[kNumTileShapes], ngt[kNumTileShapes], nr, nrt, nc, nct, nl;
+            double fl[kNumTileShapes];
         };
         // the program that last used this workspace finished before the
         // previous program was staged
@@ -699,7 +718,7 @@ template <typename T> struct HF {
                 const GemmDesc<T>& d = gd[i];
                 add_gemm(bt, d, gshape[i] >= 0 ? gshape[i] : pick_shape(d.m, d.n, d.k), gshape[i] >= 0, lt, ws);
             }
-            for (int sh = 0; sh < 3; ++sh) {
+            for (int sh = 0; sh < kNumTileShapes; ++sh) {
                 sg.g[sh] = put(bt.g[sh].data(), bt.g[sh].size() * sizeof(GemmDesc<T>));
                 sg.gt[sh] = put(bt.t[sh].data(), bt.t[sh].size() * sizeof(GemmTile));
                 sg.ng[sh] = (int)bt.g[sh].size();
@@ -750,7 +769,7 @@ template <typename T> struct HF {
                 keep([=](hipStream_t st) { leaf_batched<T>(st, dl, n); });
                 ++launches;
             }
-            for (int sh = 0; sh < 3; ++sh)
+            for (int sh = 0; sh < kNumTileShapes; ++sh)
                 if (sg.ngt[sh]) {
                     const GemmDesc<T>* dg = (const GemmDesc<T>*)(dev.p + sg.g[sh]);
                     const GemmTile* dt = (const GemmTile*)(dev.p + sg.gt[sh]);
@@ -849,7 +868,7 @@ template <typename T> struct HF {
         for (const GemmDesc<T>& d : g) lt += ntiles(d, pick_shape(d.m, d.n, d.k));
         wsr.reset();   // the previous launch's reductions precede these products on the stream
         for (const GemmDesc<T>& d : g) add_gemm(bt, d, pick_shape(d.m, d.n, d.k), false, lt, wsr);
-        for (int sh = 0; sh < 3; ++sh) {
+        for (int sh = 0; sh < kNumTileShapes; ++sh) {
             if (bt.t[sh].empty()) continue;
             flops += bt.fl[sh];
             const GemmDesc<T>* dg = stage_upload(bt.g[sh]);
@@ -1770,6 +1789,22 @@ template <typename T> static void run_factor(Ctx& c, HF<T>& f) {
     Tuner<T>::tune(c.stream, f.debug);
     for (int root : c.tree.block_roots) f.hlu(root);
     f.flush_all();
+    if (f.debug) {
+        double tot = 0.0;
+        for (auto& a : f.hist_fl)
+            for (auto& b : a)
+                for (double v : b) tot += v;
+        fprintf(stderr, "[cbie] factor GEMM flops by class (%% of %.3g; products; split-k products %lld):\n", tot,
+                (long long)f.hist_split);
+        for (int i = 0; i < Tuner<T>::NM; ++i) {
+            fprintf(stderr, "[cbie]  ");
+            for (int j = 0; j < Tuner<T>::NM; ++j)
+                for (int l = 0; l < Tuner<T>::NK; ++l)
+                    fprintf(stderr, " %4.1f/%lld%s", 100.0 * f.hist_fl[i][j][l] / tot, (long long)f.hist_n[i][j][l],
+                            l == 2 ? " |" : "");
+            fprintf(stderr, "\n");
+        }
+    }
     std::vector<int> info(c.dblk.size());
     if (!info.empty()) f.info.download(info.data(), info.size(), c.stream);
     c.sync();
