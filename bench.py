@@ -13,8 +13,12 @@ region; every step rebuilds everything from them on the GPU.
 A second workload is reported beside it (not the value): the dielectric
 sphere eps_r = 16, ka = 5, 96 patches q = 8, 24576 unknowns, N-Mueller
 formulation, one plane wave, one step per pipeline after one warmup.
+And a third: the batch of 64 seeded PEC ellipsoids (semi-axes U[0.5, 2] m,
+ka U[2, 12], 24-150 patches, q 6-8; 548208 unknowns in all) with 32 plane
+waves per object, in one context (every stage in shared launches), mixed
+pipeline, one step.
 
-python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-dielectric]
+python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-dielectric] [--no-batch]
 python bench.py --copy-probe   (a plain 1 GiB read + 1 GiB write elementwise
                                 kernel, three launches: the reference for
                                 scaling HBM traffic counters)
@@ -72,6 +76,33 @@ def dielectric(cbie, W, precs, names):
                                                                                "solve")}}
         print(f"[bench] dielectric {name}: {dt:.2f} s", file=sys.stderr, flush=True)
     return out
+
+
+def ellipsoid_batch(cbie, W):
+    """The 64-object batch in one context, mixed pipeline, one step."""
+    import torch
+    objs = W.ellipsoid_batch(64, seed=0)
+    kh, pol = W.plane_waves(32, seed=4)
+    N = sum(o.n_unknowns for o in objs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = cbie.Solver(objs)
+    s.build_tree(leaf_size=256, eta=1.0, near_delta=1.0)
+    s.fill()
+    s.compress(1e-6)
+    s.factor(cbie.PREC_C64_IR)
+    b = s.rhs_planewave(kh, pol)
+    x, it = s.solve(b, tol=1e-10, maxit=20)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = s.stats()
+    res = (torch.linalg.norm(s.matvec(x) - b) / torch.linalg.norm(b)).item()
+    s.close()
+    print(f"[bench] ellipsoid batch: {dt:.2f} s", file=sys.stderr, flush=True)
+    return {"workload": "64 PEC ellipsoids (seed 0), 548208 unknowns, 32 plane waves each, one context, "
+                        "leaf 256, eta 1, ACA 1e-6, mixed pipeline",
+            "seconds": dt, "unknowns_per_s": N / dt, "ir_iterations": it, "residual": res,
+            "phases_s": {p: st["t_" + p] for p in ("tree", "fill", "compress", "factor", "solve")}}
 
 
 def gemm_traffic(pipeline):
@@ -138,6 +169,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--pipelines", default="mixed,fp64")
     ap.add_argument("--no-dielectric", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     args = ap.parse_args()
     if args.copy_probe:
@@ -213,6 +245,8 @@ def main():
         line.setdefault("pipelines", {})[name] = {"seconds": d, "unknowns_per_s": N / d}
     if not args.no_dielectric:
         line["dielectric_sphere"] = dielectric(cbie, W, precs, args.pipelines.split(","))
+    if not args.no_batch:
+        line["ellipsoid_batch"] = ellipsoid_batch(cbie, W)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(spec, kh, pol)
     print(json.dumps(line))
