@@ -126,8 +126,11 @@ __global__ void k_near(const PatchDev* __restrict__ patches, const ObjDev* __res
 // ------------------------------------------------- singular / near quadrature
 // Barycentric Lagrange basis at first-kind Chebyshev points (ascending):
 // ell_l(x) = [lam_l/(x - x_l)] / sum_m [lam_m/(x - x_m)],
-// lam_l = (-1)^l sin((2l+1) pi / (2q)).
-__device__ inline void lagrange(int q, const double* xn, double x, double* L) {
+// lam_l = (-1)^l sin((2l+1) pi / (2q)) (bary_weights, once per thread).
+__device__ inline void bary_weights(int q, double* lam) {
+    for (int l = 0; l < q; ++l) lam[l] = ((l & 1) ? -1.0 : 1.0) * sin((2 * l + 1) * M_PI / (2.0 * q));
+}
+__device__ inline void lagrange(int q, const double* xn, const double* lam, double x, double* L) {
     for (int l = 0; l < q; ++l) {
         if (x == xn[l]) {
             for (int m = 0; m < q; ++m) L[m] = (m == l) ? 1.0 : 0.0;
@@ -136,8 +139,7 @@ __device__ inline void lagrange(int q, const double* xn, double x, double* L) {
     }
     double den = 0.0;
     for (int l = 0; l < q; ++l) {
-        const double lam = ((l & 1) ? -1.0 : 1.0) * sin((2 * l + 1) * M_PI / (2.0 * q));
-        L[l] = lam / (x - xn[l]);
+        L[l] = lam[l] / (x - xn[l]);
         den += L[l];
     }
     const double inv = 1.0 / den;
@@ -158,9 +160,11 @@ __device__ inline void lagrange(int q, const double* xn, double x, double* L) {
 // e = d/|ray|, s1 = min(1/2, 6e), and a plain Fejer rule on [s1, 1].
 // All 1D rules are Fejer-1 on [0, 1] (tables fej_x, fej_w at offset n(n-1)/2).
 //
-// Contraction: thread (b, a, k, l) accumulates
+// Contraction: wave w takes the points w, w+4, ... of each tile staged in
+// LDS; its lane (k, l) accumulates, for all four (b, a),
 //   sum_points w K[b][a](x) ell_k(v) ell_l(u)
-// over point tiles staged in LDS.
+// (the basis product once per point for four outputs); the four waves'
+// partial sums are added through LDS at the end.
 // Triangles of the change of variables around (us, vs): per triangle the
 // legs a, b, L1/L2, asinh(L2/L1) and its kind (which leg carries t).
 __device__ inline int quad_triangles(double us, double vs, double (*tri)[6]) {
@@ -259,6 +263,8 @@ __global__ __launch_bounds__(256) void k_quad(
     const double us = E.us, vs = E.vs;
     const double* xq = fej11_x + q * (q - 1) / 2;   // the patch's own Chebyshev points
     const int tid = threadIdx.x;
+    double lam[8];
+    bary_weights(q, lam);
 
     if (tid == 0) s_ntri = quad_triangles(us, vs, s_tri);
     __syncthreads();
@@ -268,14 +274,12 @@ __global__ __launch_bounds__(256) void k_quad(
     const int nr = E.self ? rule.n_rad : (rule.n_in + rule.n_out);
     const int64_t npts = (int64_t)ntri * nt * nr;
 
-    // output ownership
+    // output ownership: lane (k, l), every (b, a), a quarter of the points
     const int q2 = q * q;
-    const int nout = 4 * q2;
-    const bool owner = tid < nout;
-    const int ba = owner ? tid / q2 : 0;      // b * 2 + a
-    const int kl = owner ? tid % q2 : 0;
-    const int ok = kl / q, ol = kl % q;
-    double acc_re = 0.0, acc_im = 0.0;
+    const int wave = tid >> 6, kl = tid & 63;
+    const bool owner = kl < q2;
+    const int ok = owner ? kl / q : 0, ol = owner ? kl % q : 0;
+    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // (re, im) for ba = 0..3
 
     for (int64_t base = 0; base < npts; base += 256) {
         const int64_t pidx = base + tid;
@@ -295,8 +299,8 @@ __global__ __launch_bounds__(256) void k_quad(
             kw[2] = wgt * K[0][1].re; kw[3] = wgt * K[0][1].im;
             kw[4] = wgt * K[1][0].re; kw[5] = wgt * K[1][0].im;
             kw[6] = wgt * K[1][1].re; kw[7] = wgt * K[1][1].im;
-            lagrange(q, xq, u, Lu);
-            lagrange(q, xq, v, Lv);
+            lagrange(q, xq, lam, u, Lu);
+            lagrange(q, xq, lam, v, Lv);
         }
         __syncthreads();
         for (int c = 0; c < 8; ++c) {
@@ -307,18 +311,31 @@ __global__ __launch_bounds__(256) void k_quad(
         __syncthreads();
         if (owner) {
             const int cnt = (int)min((int64_t)256, npts - base);
-            for (int pnt = 0; pnt < cnt; ++pnt) {
+            for (int pnt = wave; pnt < cnt; pnt += 4) {
                 const double bb = S.lv[pnt][ok] * S.lu[pnt][ol];
-                acc_re = fma(S.kw[pnt][2 * ba], bb, acc_re);
-                acc_im = fma(S.kw[pnt][2 * ba + 1], bb, acc_im);
+#pragma unroll
+                for (int c = 0; c < 8; ++c) acc[c] = fma(S.kw[pnt][c], bb, acc[c]);
             }
         }
     }
-    if (owner) {
+    // sum the four waves' partials (the point tile is no longer needed)
+    __syncthreads();
+    double (*red)[64][8] = reinterpret_cast<double (*)[64][8]>(&S.kw[0][0]);   // [wave][lane][8]
+#pragma unroll
+    for (int c = 0; c < 8; ++c) red[wave][kl][c] = acc[c];
+    __syncthreads();
+    if (tid < 4 * q2) {
+        // thread -> (ba, kl2): output (b, a) of node kl2
+        const int ba = tid / q2, kl2 = tid % q2;
         const int b = ba >> 1, a = ba & 1;
+        double re = 0.0, im = 0.0;
+        for (int w = 0; w < 4; ++w) {
+            re += red[w][kl2][2 * ba];
+            im += red[w][kl2][2 * ba + 1];
+        }
         // identity term 1/2 F^b at the target node itself
-        if (E.self && a == b && (P.node0 + kl) == i) acc_re += 0.5;
-        out[pid * stride + ((int64_t)b * q2 + kl) * 2 + a] = zd{acc_re, acc_im};
+        if (E.self && a == b && (P.node0 + kl2) == i) re += 0.5;
+        out[pid * stride + ((int64_t)b * q2 + kl2) * 2 + a] = zd{re, im};
     }
 }
 
@@ -396,7 +413,8 @@ __global__ void k_near_scatter(const NearDest* __restrict__ dest, int64_t n_pair
 //   ell_m'(x) = (t_m / S^2) sum_{k != m} t_k (x_k - x_m) / ((x - x_k)(x - x_m)),
 // a form without cancellation next to a node (every term is a product).
 // At a node the derivative row comes from the differentiation matrix D.
-__device__ inline void lagrange_d(int q, const double* xn, const double* D, double x, double* L, double* dL) {
+__device__ inline void lagrange_d(int q, const double* xn, const double* lam, const double* D, double x, double* L,
+                                  double* dL) {
     for (int l = 0; l < q; ++l) {
         if (x == xn[l]) {
             for (int m = 0; m < q; ++m) {
@@ -408,8 +426,7 @@ __device__ inline void lagrange_d(int q, const double* xn, const double* D, doub
     }
     double t[8], S = 0.0;
     for (int l = 0; l < q; ++l) {
-        const double lam = ((l & 1) ? -1.0 : 1.0) * sin((2 * l + 1) * M_PI / (2.0 * q));
-        t[l] = lam / (x - xn[l]);
+        t[l] = lam[l] / (x - xn[l]);
         S += t[l];
     }
     const double iS = 1.0 / S;
@@ -461,6 +478,8 @@ __global__ __launch_bounds__(256) void k_quad_nm(
     const double* xq = fej11_x + q * (q - 1) / 2;
     const double* Dq = dmat + dmat_offset(q);
     const int tid = threadIdx.x;
+    double lam[8];
+    bary_weights(q, lam);
     if (tid == 0) s_ntri = quad_triangles(us, vs, s_tri);
     __syncthreads();
     const int ntri = s_ntri;
@@ -501,8 +520,8 @@ __global__ __launch_bounds__(256) void k_quad_nm(
                 vals[24 + 2 * b] = wgt * K.phi[b].re;
                 vals[24 + 2 * b + 1] = wgt * K.phi[b].im;
             }
-            lagrange_d(q, xq, Dq, u, Lu, dLu);
-            lagrange_d(q, xq, Dq, v, Lv, dLv);
+            lagrange_d(q, xq, lam, Dq, u, Lu, dLu);
+            lagrange_d(q, xq, lam, Dq, v, Lv, dLv);
         }
         __syncthreads();
         if (tid < kNmTile) {
