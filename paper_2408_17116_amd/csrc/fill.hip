@@ -444,10 +444,12 @@ __device__ inline int dmat_offset(int q) { return (q - 1) * q * (2 * q - 1) / 6;
 // Self/near integrals of the sixteen N-Mueller entries: one work-group per
 // (target node, source patch) pair, the same change of variables as k_quad.
 // Per point: the twelve distinct kernel values (X0, CH, CE) and the two
-// divergence weights phi; thread-owned outputs (type, b, a, k, l):
+// divergence weights phi.  Wave w takes the points w, w+4, ... of each
+// tile; its lane (k, l) accumulates the twelve outputs of that node:
 //   X:  sum w (X0[b][a] ell_k(v) ell_l(u) + phi[b] d_a(ell_k(v) ell_l(u)))
 //   CH: sum w CH[b][a] ell_k(v) ell_l(u),   CE likewise,
-// written as (4, q^2, 4) [row c, source node, column a]; the identity terms
+// and the four waves' partials are added through LDS.  Written as
+// (4, q^2, 4) [row c, source node, column a]; the identity terms
 // (mu_1 + mu_2)/2 and -(eps_1 + eps_2)/2 are added at the target node.
 constexpr int kNmTile = 128;
 struct QuadNmLDS {
@@ -488,8 +490,11 @@ __global__ __launch_bounds__(256) void k_quad_nm(
     const int nr = E.self ? rule.n_rad : (rule.n_in + rule.n_out);
     const int64_t npts = (int64_t)ntri * nt * nr;
     const int q2 = q * q;
-    const int nout = 12 * q2;
-    double acc[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+    const int wave = tid >> 6, kl = tid & 63;
+    const bool owner = kl < q2;
+    const int ok = owner ? kl / q : 0, ol = owner ? kl % q : 0;
+    double acc[24];   // (re, im) of X[ba], CH[ba], CE[ba], ba = 2b + a
+    for (int c = 0; c < 24; ++c) acc[c] = 0.0;
 
     for (int64_t base = 0; base < npts; base += kNmTile) {
         const int64_t pidx = base + tid;
@@ -535,41 +540,46 @@ __global__ __launch_bounds__(256) void k_quad_nm(
         }
         __syncthreads();
         const int cnt = (int)min((int64_t)kNmTile, npts - base);
-        for (int r = 0; r < 3; ++r) {
-            const int o = tid + 256 * r;
-            if (o >= nout) break;
-            const int type = o / (4 * q2), rem = o % (4 * q2);
-            const int ba = rem / q2, kl = rem % q2;
-            const int b = ba >> 1, a = ba & 1, k = kl / q, l = kl % q;
-            const int e = 8 * type + 2 * ba;
-            double ar = acc[r][0], ai = acc[r][1];
-            if (type == 0) {
-                for (int pnt = 0; pnt < cnt; ++pnt) {
-                    const double bas = S.lv[pnt][k] * S.lu[pnt][l];
-                    const double dbas = a ? S.dlv[pnt][k] * S.lu[pnt][l] : S.lv[pnt][k] * S.dlu[pnt][l];
-                    ar = fma(S.val[pnt][e], bas, fma(S.val[pnt][24 + 2 * b], dbas, ar));
-                    ai = fma(S.val[pnt][e + 1], bas, fma(S.val[pnt][25 + 2 * b], dbas, ai));
-                }
-            } else {
-                for (int pnt = 0; pnt < cnt; ++pnt) {
-                    const double bas = S.lv[pnt][k] * S.lu[pnt][l];
-                    ar = fma(S.val[pnt][e], bas, ar);
-                    ai = fma(S.val[pnt][e + 1], bas, ai);
+        if (owner) {
+            for (int pnt = wave; pnt < cnt; pnt += 4) {
+                const double lv = S.lv[pnt][ok], lu = S.lu[pnt][ol];
+                const double bas = lv * lu;
+                const double du = lv * S.dlu[pnt][ol], dv = S.dlv[pnt][ok] * lu;   // d_u, d_v of the basis
+                const double* V = S.val[pnt];
+#pragma unroll
+                for (int ba = 0; ba < 4; ++ba) {
+                    const int b = ba >> 1;
+                    const double db = (ba & 1) ? dv : du;
+                    acc[2 * ba] = fma(V[2 * ba], bas, fma(V[24 + 2 * b], db, acc[2 * ba]));
+                    acc[2 * ba + 1] = fma(V[2 * ba + 1], bas, fma(V[25 + 2 * b], db, acc[2 * ba + 1]));
+                    acc[8 + 2 * ba] = fma(V[8 + 2 * ba], bas, acc[8 + 2 * ba]);
+                    acc[9 + 2 * ba] = fma(V[9 + 2 * ba], bas, acc[9 + 2 * ba]);
+                    acc[16 + 2 * ba] = fma(V[16 + 2 * ba], bas, acc[16 + 2 * ba]);
+                    acc[17 + 2 * ba] = fma(V[17 + 2 * ba], bas, acc[17 + 2 * ba]);
                 }
             }
-            acc[r][0] = ar;
-            acc[r][1] = ai;
         }
     }
+    // sum the four waves' partials (the point tile is no longer needed)
+    __syncthreads();
+    double (*red)[64][24] = reinterpret_cast<double (*)[64][24]>(&S);   // [wave][lane][24]
+    static_assert(sizeof(double) * 4 * 64 * 24 <= sizeof(QuadNmLDS), "reduction buffer");
+    for (int c = 0; c < 24; ++c) red[wave][kl][c] = acc[c];
+    __syncthreads();
     zd* dst = out + pid * stride;
-    for (int r = 0; r < 3; ++r) {
-        const int o = tid + 256 * r;
-        if (o >= nout) break;
+    for (int o = tid; o < 12 * q2; o += 256) {
         const int type = o / (4 * q2), rem = o % (4 * q2);
-        const int ba = rem / q2, kl = rem % q2;
+        const int ba = rem / q2, kl2 = rem % q2;
         const int b = ba >> 1, a = ba & 1;
+        const int c = 8 * type + 2 * ba;
+        double re = 0.0, im = 0.0;
+        for (int w = 0; w < 4; ++w) {
+            re += red[w][kl2][c];
+            im += red[w][kl2][c + 1];
+        }
+        const int kl = kl2;
         const bool diag = E.self && a == b && (P.node0 + kl) == i;
-        const zd v{acc[r][0], acc[r][1]};
+        const zd v{re, im};
         if (type == 0) {
             dst[((int64_t)b * q2 + kl) * 4 + 2 + a] = v;            // H_b x M^a
             dst[((int64_t)(2 + b) * q2 + kl) * 4 + a] = v;          // E_b x J^a
