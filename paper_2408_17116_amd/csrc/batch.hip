@@ -34,7 +34,9 @@ template <typename T, int BM, int BN, int WGM, int BK>
 __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc<T>* __restrict__ descs,
                                                const GemmTile* __restrict__ tiles, int ntiles) {
     constexpr int WGN = 4 / WGM, WM = BM / WGM, WN = BN / WGN, FM = WM / 16, FN = WN / 16;
-    constexpr int PAD = sizeof(T) == 4 ? 16 : 2;
+    // one-element row padding: rows written lane by lane (transposing
+    // stores) start two (complex64) or four (complex128) banks apart
+    constexpr int PAD = 1;
     constexpr int NA = BM * BK / 256, NB = BK * BN / 256;
     static_assert(NA >= 1 && NB >= 1 && FM >= 1 && FN >= 1, "tile shape");
     typedef typename Mfma<T>::v4 v4;

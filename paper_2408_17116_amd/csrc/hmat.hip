@@ -1546,13 +1546,31 @@ template <typename T> struct HF {
         const cplx<T>* LP = inv.p + inv_off[leaf];
         const cplx<T>* UI = LP + (int64_t)n * n;
         const std::vector<Res> rd = cat({rx, {Res{RES_DENSE, leaf}}});
+        if (inplace_solve) {
+            // full-height / full-width tiles: each tile reads the rows or
+            // columns of X it overwrites
+            if (which == 'R') {
+                rec_gemm(0, 0, k, n, n, one(), X, ldx, UI, n, zero(), X, ldx, rd, rx, kTile32x256);
+            } else {
+                const int ta = which == 'T' ? 1 : 0;
+                rec_gemm(ta, 0, n, k, n, one(), which == 'L' ? LP : UI, n, X, ldx, zero(), X, ldx, rd, rx, kTile256x32);
+            }
+            return;
+        }
+        // into a temporary with any tile shape (split-k allowed), then copied
+        // back: full-height tiles would give a launch few work-groups
+        const int tm = which == 'R' ? k : n, tn = which == 'R' ? n : k;
+        cplx<T>* Tp = scratch.alloc((size_t)tm * tn);
+        const Res tr = rect(RES_TEMP, temp().id, 0, tm, 0, tn);
         if (which == 'R') {
-            rec_gemm(0, 0, k, n, n, one(), X, ldx, UI, n, zero(), X, ldx, rd, rx, kTile32x256);
+            rec_gemm(0, 0, k, n, n, one(), X, ldx, UI, n, zero(), Tp, tm, rd, {tr});
         } else {
             const int ta = which == 'T' ? 1 : 0;
-            rec_gemm(ta, 0, n, k, n, one(), which == 'L' ? LP : UI, n, X, ldx, zero(), X, ldx, rd, rx, kTile256x32);
+            rec_gemm(ta, 0, n, k, n, one(), which == 'L' ? LP : UI, n, X, ldx, zero(), Tp, tm, rd, {tr});
         }
+        rec_copy(0, tm, tn, one(), Tp, tm, X, ldx, {tr}, rx);
     }
+    bool inplace_solve = getenv("CBIE_INPLACE_SOLVE") && atoi(getenv("CBIE_INPLACE_SOLVE")) != 0;
     // X (|d| x ncol) := L_dd^{-1} X
     void solveL(int d, const View& X) {
         const Block& D = T_.blocks[d];
