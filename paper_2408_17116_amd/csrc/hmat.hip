@@ -1773,6 +1773,8 @@ template <typename T> static std::shared_ptr<HF<T>> make_factor(Ctx& c) {
     convert<double, T>(s, c.stats.dense_entries, c.dense.p, f->dense.p);
     f->lr.resize(c.lblk.size());
     f->lr_busy.assign(c.lblk.size(), 0);
+    std::vector<ConvDesc<double, T>> conv;
+    conv.reserve(2 * c.lblk.size());
     for (size_t b = 0; b < c.lblk.size(); ++b) {
         auto& L = f->lr[b];
         L.m = c.upn * c.lblk[b].row_nodes;
@@ -1781,9 +1783,10 @@ template <typename T> static std::shared_ptr<HF<T>> make_factor(Ctx& c) {
         L.cap = std::max(L.r, 1);
         L.U = f->store.alloc((size_t)L.m * L.cap);
         L.V = f->store.alloc((size_t)L.n * L.cap);
-        convert<double, T>(s, (int64_t)L.m * L.r, c.lr.mem.p + c.lr.u_off[b], L.U);
-        convert<double, T>(s, (int64_t)L.n * L.r, c.lr.mem.p + c.lr.v_off[b], L.V);
+        conv.push_back(ConvDesc<double, T>{c.lr.mem.p + c.lr.u_off[b], L.U, (int64_t)L.m * L.r});
+        conv.push_back(ConvDesc<double, T>{c.lr.mem.p + c.lr.v_off[b], L.V, (int64_t)L.n * L.r});
     }
+    convert_batched<double, T>(s, conv);
     f->piv_off.assign(c.dblk.size(), -1);
     f->inv_off.assign(c.dblk.size(), -1);
     int64_t np = 0, ni = 0;

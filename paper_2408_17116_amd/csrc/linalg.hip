@@ -298,6 +298,35 @@ __global__ void k_convert(int64_t n, const cplx<Tin>* __restrict__ a, cplx<Tout>
     if (e < n) b[e] = cplx<Tout>{(Tout)a[e].re, (Tout)a[e].im};
 }
 
+// many conversions in one launch: work-group t converts elements
+// [e0, e0 + 4096) of array desc
+struct ConvTile {
+    int desc, pad;
+    int64_t e0;
+};
+template <typename Tin, typename Tout>
+__global__ void k_convert_b(const ConvDesc<Tin, Tout>* __restrict__ d, const ConvTile* __restrict__ t, int nt) {
+    if ((int)blockIdx.x >= nt) return;
+    const ConvTile tl = t[blockIdx.x];
+    const ConvDesc<Tin, Tout> D = d[tl.desc];
+    const int64_t e1 = min(D.n, tl.e0 + 4096);
+    for (int64_t e = tl.e0 + threadIdx.x; e < e1; e += 256) D.b[e] = cplx<Tout>{(Tout)D.a[e].re, (Tout)D.a[e].im};
+}
+template <typename Tin, typename Tout>
+void convert_batched(hipStream_t s, const std::vector<ConvDesc<Tin, Tout>>& v) {
+    std::vector<ConvTile> t;
+    for (size_t i = 0; i < v.size(); ++i)
+        for (int64_t e0 = 0; e0 < v[i].n; e0 += 4096) t.push_back(ConvTile{(int)i, 0, e0});
+    if (t.empty()) return;
+    DBuf<ConvDesc<Tin, Tout>> dd;
+    DBuf<ConvTile> dt;
+    dd.upload(v, s);
+    dt.upload(t, s);
+    k_convert_b<Tin, Tout><<<(unsigned)t.size(), 256, 0, s>>>(dd.p, dt.p, (int)t.size());
+    check_launch("k_convert_b");
+    CBIE_HIP(hipStreamSynchronize(s));   // the descriptor buffers are released on return
+}
+
 template <typename Tin, typename Tout>
 void convert(hipStream_t s, int64_t n, const cplx<Tin>* a, cplx<Tout>* b) {
     if (n <= 0) return;
@@ -504,6 +533,8 @@ void leaf_inverse(hipStream_t s, int n, const cplx<T>* LU, int ld, const int* pi
     template void leaf_inverse<T>(hipStream_t, int, const cplx<T>*, int, const int*, cplx<T>*, cplx<T>*);
 CBIE_LINALG_INST(double)
 CBIE_LINALG_INST(float)
+template void convert_batched<double, float>(hipStream_t, const std::vector<ConvDesc<double, float>>&);
+template void convert_batched<double, double>(hipStream_t, const std::vector<ConvDesc<double, double>>&);
 template void convert<double, float>(hipStream_t, int64_t, const zd*, zf*);
 template void convert<float, double>(hipStream_t, int64_t, const zf*, zd*);
 template void convert<double, double>(hipStream_t, int64_t, const zd*, zd*);

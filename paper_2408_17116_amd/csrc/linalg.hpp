@@ -1,6 +1,7 @@
 // Dense complex kernels used by the H-LU (column-major, complex64 or
 // complex128).  Every routine enqueues work on `s` and returns at once.
 #pragma once
+#include <vector>
 #include "common.hpp"
 
 namespace cbie {
@@ -35,6 +36,14 @@ void copy_scale(hipStream_t s, int m, int n, cplx<T> alpha, const cplx<T>* A, in
 // element-wise precision conversion of a contiguous array
 template <typename Tin, typename Tout>
 void convert(hipStream_t s, int64_t n, const cplx<Tin>* a, cplx<Tout>* b);
+// b_i[0, n_i) = (Tout) a_i[0, n_i) for every descriptor, one launch
+template <typename Tin, typename Tout> struct ConvDesc {
+    const cplx<Tin>* a;
+    cplx<Tout>* b;
+    int64_t n;
+};
+template <typename Tin, typename Tout>
+void convert_batched(hipStream_t s, const std::vector<ConvDesc<Tin, Tout>>& v);
 
 // ACA of an implicit product M = Uc Vc^T (m x n, inner K <= 2048): writes
 // U (m x cap) and V (n x cap), cap <= 1024, with M ~ U V^T to relative
