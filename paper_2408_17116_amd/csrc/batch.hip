@@ -62,20 +62,26 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc<T>* __restrict__ d
         for (int j = 0; j < FN; ++j)
             for (int v = 0; v < 4; ++v) { cr[i][j][v] = (T)0; ci[i][j][v] = (T)0; }
 
+    // The next slice is fetched into registers while the current one is
+    // multiplied: every load is issued unconditionally (out-of-range
+    // elements read element 0 of the operand, which always exists), and the
+    // range mask and the conjugation are applied only when the registers
+    // are written to LDS, so no wait for the loads sits before the MFMAs.
     cplx<T> ra[NA], rb[NB];
+    unsigned ma = 0, mb = 0;
     auto load = [&](int k0) {
+        ma = 0;
+        mb = 0;
 #pragma unroll
         for (int q = 0; q < NA; ++q) {
             const int e = tid + 256 * q;
             int i, kk;
             if (D.ta == 0) { i = e % BM; kk = e / BM; } else { kk = e % BK; i = e / BK; }
             const int gi = m0 + i, gk = k0 + kk;
-            cplx<T> v{(T)0, (T)0};
-            if (gi < m && gk < k) {
-                v = D.ta == 0 ? D.A[gi + (int64_t)gk * D.lda] : D.A[gk + (int64_t)gi * D.lda];
-                if (D.ta == 2) v.im = -v.im;
-            }
-            ra[q] = v;
+            const bool ok = gi < m && gk < k;
+            const int64_t off = !ok ? 0 : D.ta == 0 ? gi + (int64_t)gk * D.lda : gk + (int64_t)gi * D.lda;
+            ra[q] = D.A[off];
+            ma |= (unsigned)ok << q;
         }
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
@@ -83,24 +89,27 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc<T>* __restrict__ d
             int j, kk;
             if (D.tb == 0) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
             const int gj = n0 + j, gk = k0 + kk;
-            cplx<T> v{(T)0, (T)0};
-            if (gj < n && gk < k) {
-                v = D.tb == 0 ? D.B[gk + (int64_t)gj * D.ldb] : D.B[gj + (int64_t)gk * D.ldb];
-                if (D.tb == 2) v.im = -v.im;
-            }
-            rb[q] = v;
+            const bool ok = gj < n && gk < k;
+            const int64_t off = !ok ? 0 : D.tb == 0 ? gk + (int64_t)gj * D.ldb : gj + (int64_t)gk * D.ldb;
+            rb[q] = D.B[off];
+            mb |= (unsigned)ok << q;
         }
     };
     auto stash = [&](int buf) {
+        const T sa = D.ta == 2 ? (T)-1 : (T)1, sb = D.tb == 2 ? (T)-1 : (T)1;
 #pragma unroll
         for (int q = 0; q < NA; ++q) {
             const int e = tid + 256 * q;
-            if (D.ta == 0) As[buf][e / BM][e % BM] = ra[q]; else As[buf][e % BK][e / BK] = ra[q];
+            const bool ok = (ma >> q) & 1u;
+            const cplx<T> v{ok ? ra[q].re : (T)0, ok ? sa * ra[q].im : (T)0};
+            if (D.ta == 0) As[buf][e / BM][e % BM] = v; else As[buf][e % BK][e / BK] = v;
         }
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
             const int e = tid + 256 * q;
-            if (D.tb == 0) Bs[buf][e % BK][e / BK] = rb[q]; else Bs[buf][e / BN][e % BN] = rb[q];
+            const bool ok = (mb >> q) & 1u;
+            const cplx<T> v{ok ? rb[q].re : (T)0, ok ? sb * rb[q].im : (T)0};
+            if (D.tb == 0) Bs[buf][e % BK][e / BK] = v; else Bs[buf][e / BN][e % BN] = v;
         }
     };
     load(0);
@@ -149,7 +158,7 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc<T>* __restrict__ d
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int row = m0 + wm * WM + 16 * i + Mfma<T>::row(kq, v);
-                    old[i][v] = (cin && row < m) ? ccol[row] : cplx<T>{(T)0, (T)0};
+                    old[i][v] = ccol[(cin && row < m) ? row : 0];   // masked below
                 }
         }
 #pragma unroll
