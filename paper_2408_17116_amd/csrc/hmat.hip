@@ -471,11 +471,14 @@ template <typename T> struct HF {
     static int64_t ntiles(const GemmDesc<T>& d, int sh) {
         return (int64_t)((d.m + tile_rows(sh) - 1) / tile_rows(sh)) * ((d.n + tile_cols(sh) - 1) / tile_cols(sh));
     }
-    static int nsplit(const GemmDesc<T>& d, int sh, int64_t launch_tiles) {
+    // k thresholds: the substitution's thin products (few tiles, deep k)
+    // are split sooner than the factorization's (set around a solve)
+    int split_k1 = 1536, split_k2 = 512;
+    int nsplit(const GemmDesc<T>& d, int sh, int64_t launch_tiles) const {
         const int64_t cap = std::max<int64_t>(1, (int64_t(1) << 22) / ((int64_t)d.m * d.n));   // <= 4M partial entries
         int64_t S = 1;
-        if (d.k >= 768 && ntiles(d, sh) < 128) S = std::min<int64_t>((d.k + 255) / 256, 32);
-        if (launch_tiles < 256 && d.k >= 128)
+        if (d.k >= split_k1 && ntiles(d, sh) < 128) S = std::min<int64_t>((d.k + 255) / 256, 32);
+        if (launch_tiles < 256 && d.k >= split_k2)
             S = std::max<int64_t>(S, std::min<int64_t>((d.k + 63) / 64, std::max<int64_t>(1, 512 / launch_tiles)));
         return (int)std::min<int64_t>({S, 32, cap});
     }
@@ -1872,6 +1875,12 @@ void stage_factor(Ctx& c, int prec) {
 // X (tree order, N x nrhs, ld N) := LU^{-1} X in the working precision
 template <typename T> static void lu_solve_tree(Ctx& c, HF<T>& f, cplx<T>* X, int nrhs) {
     const int ld = (int)c.n_unk;
+    struct Thresholds {   // solve thresholds for this program, restored on exit
+        HF<T>& f;
+        int k1, k2;
+        Thresholds(HF<T>& ff) : f(ff), k1(ff.split_k1), k2(ff.split_k2) { f.split_k1 = 768; f.split_k2 = 128; }
+        ~Thresholds() { f.split_k1 = k1; f.split_k2 = k2; }
+    } th(f);
     for (int root : c.tree.block_roots) {
         const int cl = c.tree.blocks[root].t;
         const Cluster& C = c.tree.clusters[cl];
