@@ -184,7 +184,7 @@ def main():
                                          "bytes_written_per_launch": 4 * n}}))
         return
     if args.gpus != 1:
-        print("bench.py: this build measures one GPU only (the H-matrix solve of one object is not "
+        print("bench.py: measures one GPU only (the H-matrix solve of one object is not "
               "sharded); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
