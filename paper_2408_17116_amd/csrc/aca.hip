@@ -6,6 +6,7 @@
 #include "ctx.hpp"
 #include "lowrank.hpp"
 #include "mlp.hpp"
+#include "linalg.hpp"
 
 namespace cbie {
 
@@ -259,91 +260,118 @@ __global__ void k_export_lr(const DenseBlockDev* __restrict__ blocks, int n_bloc
     }
 }
 
-// ACA of the given blocks with the given widths: ranks and convergence
-// flags, factors in the workspace (U then V per block)
+// ACA of the given blocks with the given widths, in rounds whose workspace
+// (U: m x width and V: n x width per block) stays within a budget
+// (CBIE_ACA_BUDGET elements, default 2^30); each round's factors are packed
+// (U then V, rank columns each) into a buffer of their own before the
+// workspace is reused.  N-Mueller blocks are filled explicitly per round
+// (the surface divergence couples whole source patches), at most kAcaDense
+// entries, and compressed from their copies.
 struct AcaPass {
-    std::vector<AcaJob> jobs;
-    DBuf<zd> ws;
-    DBuf<unsigned char> used;
-    DBuf<AcaJob> d_jobs;
-    DBuf<int> d_rank, d_flag;
     std::vector<int> rank, flag;
-    int64_t ws_elems = 0;
+    std::vector<int> round;        // per block: the buffer holding its factors
+    std::vector<int64_t> off;      // per block: offset of its factors there
+    std::vector<DBuf<zd>> fac;     // packed factors, one buffer per round
+    double ws_elems = 0.0;         // workspace the widths ask for, all rounds
+    int rounds = 0;
 };
 static void aca_pass(Ctx& c, double tol, const std::vector<int>& blocks, const std::vector<int>& width, AcaPass& P) {
     const int nb = (int)blocks.size();
-    P.jobs.assign(nb, AcaJob{});
-    int64_t off = 0, uoff = 0;
-    for (int q = 0; q < nb; ++q) {
-        const DenseBlockDev& d = c.lblk[blocks[q]];
-        AcaJob& J = P.jobs[q];
-        J.row_node0 = d.row_node0;
-        J.row_nodes = d.row_nodes;
-        J.col_node0 = d.col_node0;
-        J.col_nodes = d.col_nodes;
-        J.obj = d.obj;
-        J.upn = d.upn;
-        const int m = d.upn * d.row_nodes, n = d.upn * d.col_nodes;
-        J.cap = width[q];
-        J.u_off = off;
-        off += (int64_t)m * J.cap;
-        J.v_off = off;
-        off += (int64_t)n * J.cap;
-        J.used_off = uoff;
-        uoff += m;
-    }
-    P.ws_elems = off;
-    P.ws.alloc(std::max<int64_t>(off, 1));
-    P.used.alloc(std::max<int64_t>(uoff, 1));
-    P.d_rank.alloc(std::max(nb, 1));
-    P.d_flag.alloc(std::max(nb, 1));
-    if (c.upn == 2) {
-        P.d_jobs.upload(P.jobs, c.stream);
-        k_aca<<<nb, 256, 0, c.stream>>>(P.d_jobs.p, nb, c.d_tree_node.p, c.nd, c.d_objs.p, tol, P.ws.p, P.used.p,
-                                        P.d_rank.p, P.d_flag.p, nullptr);
-        check_launch("k_aca");
-    } else {
-        // N-Mueller: the blocks are filled explicitly (the surface divergence
-        // couples whole source patches), in rounds of at most kAcaDense
-        // entries, and compressed from their copies.
-        DBuf<zd> dense;
-        int q0 = 0;
-        while (q0 < nb) {
-            int q1 = q0;
-            int64_t tot = 0;
-            std::vector<DenseBlockDev> blk;
-            while (q1 < nb) {
-                const DenseBlockDev& d = c.lblk[blocks[q1]];
-                const int64_t e = (int64_t)c.upn * d.row_nodes * c.upn * d.col_nodes;
-                if (q1 > q0 && tot + e > kAcaDense) break;
+    const char* eb = getenv("CBIE_ACA_BUDGET");
+    const int64_t budget = eb ? std::max<int64_t>(1, atoll(eb)) : int64_t(1) << 30;
+    P.rank.assign(nb, 0);
+    P.flag.assign(nb, 0);
+    P.round.assign(nb, -1);
+    P.off.assign(nb, 0);
+    P.fac.clear();
+    P.ws_elems = 0.0;
+    DBuf<zd> ws, dense;
+    DBuf<unsigned char> used;
+    int q0 = 0;
+    while (q0 < nb) {
+        // the round: blocks [q0, q1)
+        std::vector<AcaJob> jobs;
+        std::vector<DenseBlockDev> blk;
+        int64_t off = 0, uoff = 0, doff = 0;
+        int q1 = q0;
+        while (q1 < nb) {
+            const DenseBlockDev& d = c.lblk[blocks[q1]];
+            const int m = d.upn * d.row_nodes, n = d.upn * d.col_nodes;
+            const int64_t w = (int64_t)(m + n) * width[q1];
+            const int64_t e = c.upn == 4 ? (int64_t)m * n : 0;
+            if (q1 > q0 && (off + w > budget || doff + e > kAcaDense)) break;
+            AcaJob J{};
+            J.row_node0 = d.row_node0;
+            J.row_nodes = d.row_nodes;
+            J.col_node0 = d.col_node0;
+            J.col_nodes = d.col_nodes;
+            J.obj = d.obj;
+            J.upn = d.upn;
+            J.cap = width[q1];
+            J.u_off = off;
+            off += (int64_t)m * J.cap;
+            J.v_off = off;
+            off += (int64_t)n * J.cap;
+            J.used_off = uoff;
+            uoff += m;
+            if (c.upn == 4) {
                 DenseBlockDev x = d;
-                x.offset = tot;
-                x.ld = c.upn * d.row_nodes;
+                x.offset = doff;
+                x.ld = m;
                 blk.push_back(x);
-                P.jobs[q1].a_off = tot;
-                tot += e;
-                ++q1;
+                J.a_off = doff;
+                doff += e;
             }
-            if ((int64_t)dense.n < tot) dense.alloc(tot);
-            DBuf<DenseBlockDev> d_blk;
+            jobs.push_back(J);
+            ++q1;
+        }
+        const int nq = q1 - q0;
+        P.ws_elems += (double)off;
+        if ((int64_t)ws.n < off) ws.alloc(off);
+        if ((int64_t)used.n < uoff) used.alloc(uoff);
+        DBuf<AcaJob> d_jobs;
+        d_jobs.upload(jobs, c.stream);
+        DBuf<int> d_rank, d_flag;
+        d_rank.alloc(nq);
+        d_flag.alloc(nq);
+        const zd* src = nullptr;
+        DBuf<DenseBlockDev> d_blk;
+        if (c.upn == 4) {
+            if ((int64_t)dense.n < doff) dense.alloc(doff);
             d_blk.upload(blk, c.stream);
             fill_blocks_nm(c, blk, d_blk.p, dense.p);
-            DBuf<AcaJob> d_sub;
-            std::vector<AcaJob> sub(P.jobs.begin() + q0, P.jobs.begin() + q1);
-            d_sub.upload(sub, c.stream);
-            k_aca<<<q1 - q0, 256, 0, c.stream>>>(d_sub.p, q1 - q0, c.d_tree_node.p, c.nd, c.d_objs.p, tol, P.ws.p,
-                                                 P.used.p, P.d_rank.p + q0, P.d_flag.p + q0, dense.p);
-            check_launch("k_aca");
-            c.sync();
-            q0 = q1;
+            src = dense.p;
         }
-        P.d_jobs.upload(P.jobs, c.stream);
+        k_aca<<<nq, 256, 0, c.stream>>>(d_jobs.p, nq, c.d_tree_node.p, c.nd, c.d_objs.p, tol, ws.p, used.p, d_rank.p,
+                                        d_flag.p, src);
+        check_launch("k_aca");
+        d_rank.download(P.rank.data() + q0, nq, c.stream);
+        d_flag.download(P.flag.data() + q0, nq, c.stream);
+        c.sync();
+        // pack the round's factors
+        std::vector<int64_t> uo(nq), vo(nq);
+        int64_t tot = 0;
+        for (int q = 0; q < nq; ++q) {
+            const DenseBlockDev& d = c.lblk[blocks[q0 + q]];
+            const int64_t m = d.upn * (int64_t)d.row_nodes, n = d.upn * (int64_t)d.col_nodes, r = P.rank[q0 + q];
+            P.round[q0 + q] = (int)P.fac.size();
+            P.off[q0 + q] = tot;
+            uo[q] = tot;
+            vo[q] = tot + m * r;
+            tot += (m + n) * r;
+        }
+        DBuf<zd> packed;
+        packed.alloc(std::max<int64_t>(tot, 1));
+        DBuf<int64_t> du, dv;
+        du.upload(uo, c.stream);
+        dv.upload(vo, c.stream);
+        k_lr_compact<<<dim3(32, nq), 256, 0, c.stream>>>(d_jobs.p, nq, ws.p, d_rank.p, du.p, dv.p, packed.p);
+        check_launch("k_lr_compact");
+        c.sync();
+        P.fac.push_back(std::move(packed));
+        ++P.rounds;
+        q0 = q1;
     }
-    P.rank.resize(nb);
-    P.flag.resize(nb);
-    P.d_rank.download(P.rank.data(), nb, c.stream);
-    P.d_flag.download(P.flag.data(), nb, c.stream);
-    c.sync();
 }
 
 void stage_compress(Ctx& c, double tol, int mode) {
@@ -388,7 +416,7 @@ void stage_compress(Ctx& c, double tol, int mode) {
         }
         AcaPass P;
         aca_pass(c, tol, all, width, P);
-        double ws_bytes = (double)P.ws_elems * sizeof(zd);
+        double ws_elems = P.ws_elems;
         // blocks that filled a predicted width without converging: full width
         std::vector<int> redo, redo_w;
         for (int b = 0; b < nb; ++b)
@@ -400,53 +428,34 @@ void stage_compress(Ctx& c, double tol, int mode) {
         std::vector<int> src(nb, -1);   // block -> job in the redo pass
         if (!redo.empty()) {
             aca_pass(c, tol, redo, redo_w, R);
-            ws_bytes += (double)R.ws_elems * sizeof(zd);
+            ws_elems += R.ws_elems;
             for (size_t q = 0; q < redo.size(); ++q) src[redo[q]] = (int)q;
         }
         c.stats.aca_fallbacks = (int64_t)redo.size();
-        c.stats.aca_workspace_bytes = ws_bytes;
+        c.stats.aca_workspace_bytes = ws_elems * sizeof(zd);
         int64_t so = 0;
+        std::vector<ConvDesc<double, double>> place;   // packed factors -> final offsets
+        place.reserve(nb);
         for (int b = 0; b < nb; ++b) {
             const int64_t m = c.upn * (int64_t)c.lblk[b].row_nodes, n = c.upn * (int64_t)c.lblk[b].col_nodes;
-            const int r = src[b] >= 0 ? R.rank[src[b]] : P.rank[b];
-            const int fl = src[b] >= 0 ? R.flag[src[b]] : P.flag[b];
+            const AcaPass& Q = src[b] >= 0 ? R : P;
+            const int qb = src[b] >= 0 ? src[b] : b;
+            const int r = Q.rank[qb];
             c.lr.rank[b] = r;
             c.lr.cap[b] = r;
             c.lr.u_off[b] = so;
-            so += m * r;
-            c.lr.v_off[b] = so;
-            so += n * r;
+            c.lr.v_off[b] = so + m * r;
+            if (r > 0) place.push_back(ConvDesc<double, double>{Q.fac[Q.round[qb]].p + Q.off[qb], nullptr, (m + n) * r});
+            so += (m + n) * r;
             lr_entries += (m + n) * r;
             max_rank = std::max<int64_t>(max_rank, r);
             sum_rank += r;
-            c.stats_unconverged += fl ? 0 : 1;
+            c.stats_unconverged += Q.flag[qb] ? 0 : 1;
         }
         c.lr.mem.alloc(std::max<int64_t>(so, 1));
-        // compact both passes' factors (the redone blocks from the second)
-        auto compact = [&](AcaPass& Q, const std::vector<int>& blocks, bool second) {
-            const int nq = (int)blocks.size();
-            if (nq == 0) return;
-            std::vector<int64_t> uo(nq), vo(nq);
-            std::vector<int> rk(nq);
-            for (int q = 0; q < nq; ++q) {
-                const int b = blocks[q];
-                const bool mine = second ? true : src[b] < 0;
-                uo[q] = c.lr.u_off[b];
-                vo[q] = c.lr.v_off[b];
-                rk[q] = mine ? c.lr.rank[b] : 0;
-            }
-            DBuf<int64_t> du, dv;
-            DBuf<int> dr;
-            du.upload(uo, c.stream);
-            dv.upload(vo, c.stream);
-            dr.upload(rk, c.stream);
-            dim3 grid(32, nq);
-            k_lr_compact<<<grid, 256, 0, c.stream>>>(Q.d_jobs.p, nq, Q.ws.p, dr.p, du.p, dv.p, c.lr.mem.p);
-            check_launch("k_lr_compact");
-            c.sync();
-        };
-        compact(P, all, false);
-        compact(R, redo, true);
+        for (int b = 0, i = 0; b < nb; ++b)
+            if (c.lr.rank[b] > 0) place[i++].b = c.lr.mem.p + c.lr.u_off[b];
+        convert_batched<double, double>(c.stream, place);
         c.lr.d_u_off.upload(c.lr.u_off, c.stream);
         c.lr.d_v_off.upload(c.lr.v_off, c.stream);
         c.lr.d_rank.upload(c.lr.rank, c.stream);

@@ -1811,8 +1811,24 @@ template <typename T> static std::shared_ptr<HF<T>> make_factor(Ctx& c) {
 
 template <typename T> static void run_factor(Ctx& c, HF<T>& f) {
     Tuner<T>::tune(c.stream, f.debug);
-    for (int root : c.tree.block_roots) f.hlu(root);
-    f.flush_all();
+    try {
+        for (int root : c.tree.block_roots) f.hlu(root);
+        f.flush_all();
+    } catch (const Error&) {
+        size_t mfree = 0, mtot = 0;
+        if (f.debug && hipMemGetInfo(&mfree, &mtot) == hipSuccess)
+            fprintf(stderr, "[cbie] device memory %.2f GB free of %.2f GB\n", 1e-9 * mfree, 1e-9 * mtot);
+        if (f.debug)
+            fprintf(stderr,
+                    "[cbie] factorization stopped: storage %.2f GB live (peak %.2f GB, arena %.2f GB), scratch %.2f GB, "
+                    "recompression scratch %.2f GB, split-k %.2f GB, levels %lld, flushes %lld\n",
+                    1e-9 * (double)f.store.live * sizeof(cplx<T>), 1e-9 * (double)f.store.peak * sizeof(cplx<T>),
+                    1e-9 * f.store.bump.capacity() * sizeof(cplx<T>), 1e-9 * f.scratch.capacity() * sizeof(cplx<T>),
+                    1e-9 * f.rscratch.capacity() * sizeof(cplx<T>),
+                    1e-9 * (f.wsp[0].capacity() + f.wsp[1].capacity() + f.wsr.capacity()) * sizeof(cplx<T>),
+                    (long long)f.levels_run, (long long)f.flushes);
+        throw;
+    }
     if (f.debug) {
         double tot = 0.0;
         for (auto& a : f.hist_fl)

@@ -97,3 +97,43 @@ def test_matvec_after_recompression_at_other_tolerances():
         err = (torch.linalg.norm(y - yd) / torch.linalg.norm(yd)).item()
         print(f"tol {tol:g}: max rank {s.stats()['max_rank']}, matvec vs dense {err:.1e}")
         assert err < 1e-13
+
+
+@pytest.mark.parametrize("form", ["mfie", "nmuller"])
+def test_aca_in_rounds_of_a_small_workspace_budget(form, monkeypatch):
+    """The ACA workspace is used in rounds that fit a budget (elements, here
+    small enough for a few blocks per round): ranks, factors and the
+    recorded workspace must equal those of a single round, also for the
+    full-width redo of blocks whose predicted width was too small (a
+    network with zero weights predicts log-rank 0, width 8)."""
+    import torch
+    from paper_2408_17116_amd import cbie
+    if form == "mfie":
+        spec, leaf = W.tiny_sphere(s=4, q=4, k0=6.0), 64
+    else:
+        spec = W.ObjectSpec(axes=(1.2, 0.8, 0.6), center=(0.0, 0.0, 0.0), s=3, q=4, k0=3.0,
+                            form=W.FORM_NMULLER, eps_r=4.0, mu_r=1.0)
+        leaf = 64
+    s, _ = _filled(spec, leaf=leaf)
+    s.set_rank_model(np.zeros(cbie.MLP_NPARAMS, np.float32), np.zeros(cbie.MLP_NFEAT, np.float32),
+                     np.ones(cbie.MLP_NFEAT, np.float32), margin=0.0)
+    out = {}
+    for budget in (None, 20000):
+        if budget is not None:
+            monkeypatch.setenv("CBIE_ACA_BUDGET", str(budget))
+        for mode in (cbie.RANK_ADAPTIVE, cbie.RANK_PREDICTED):
+            s.compress(1e-6, mode=mode)
+            _, r = s.block_features(1e-6)
+            st = s.stats()
+            out[budget, mode] = (s.export_dense(), r, st["aca_workspace_bytes"], st["aca_fallbacks"])
+    ref = out[None, cbie.RANK_ADAPTIVE]
+    assert ref[3] == 0 and ref[1].max() > 8
+    print(f"{form}: {ref[1].size} blocks, max rank {ref[1].max()}, "
+          f"fallbacks at width 8 {out[None, cbie.RANK_PREDICTED][3]}")
+    for key, (A, r, ws, fb) in out.items():
+        assert torch.equal(A, ref[0]), key
+        assert np.array_equal(r, ref[1]), key
+    for mode in (cbie.RANK_ADAPTIVE, cbie.RANK_PREDICTED):
+        assert out[20000, mode][2:] == out[None, mode][2:]
+    assert out[None, cbie.RANK_PREDICTED][3] > 0
+    s.close()
