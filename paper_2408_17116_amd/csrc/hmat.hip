@@ -24,6 +24,8 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <map>
+#include <set>
 #include <memory>
 #include <unordered_map>
 
@@ -70,48 +72,96 @@ template <typename T> struct Arena {
     }
 };
 
-// Device storage of the factors: size classes of four steps per power of
-// two (at least 4096 elements) carved from a bump arena, with free lists.  A released buffer
-// may still be read or written by tasks recorded before its release, so it
-// is reused only after the stream has completed them: released while a
-// program is being recorded -> waiting for that program's launch ->
-// free once the stream has been synchronized after the launch.
+// Device storage of the factors: buffers (multiples of 32 elements) carved
+// best-fit from device chunks, freed ranges merged with free neighbours of
+// the same chunk, so that the memory of factors whose rank changed serves
+// factors of any other size.  A released buffer may still be read or
+// written by tasks recorded before its release, so it is reused only after
+// the stream has completed them: released while a program is being recorded
+// -> waiting for that program's launch -> free once the stream has been
+// synchronized after the launch.
 template <typename T> struct Pool {
-    Arena<T> bump;
-    std::vector<std::vector<cplx<T>*>> free_cls = std::vector<std::vector<cplx<T>*>>(256);
-    std::vector<std::pair<cplx<T>*, int>> rec, run;
+    using P = cplx<T>*;
+    struct Range {
+        size_t n;
+        int chunk;
+    };
+    std::vector<DBuf<cplx<T>>> chunks;
+    std::map<P, int> chunk_at;                    // chunk base -> index
+    std::map<P, Range> free_at;                   // free ranges by address
+    std::set<std::pair<size_t, P>> free_by_size;  // the same, by size
+    std::vector<std::pair<P, size_t>> rec, run;
+    size_t chunk_elems = size_t(1) << 26;
     size_t live = 0, peak = 0;
-    // class c holds (4 + c % 4) 2^(c / 4 - 2) elements
-    static size_t cls_size(int c) { return (size_t)(4 + c % 4) << (c / 4 - 2); }
-    static int cls(size_t n) {
-        int c = 48;                        // 4096 elements
-        while (cls_size(c) < n) ++c;
-        return c;
-    }
-    cplx<T>* alloc(size_t n) {
-        const int c = cls(n);
-        live += cls_size(c);
-        peak = std::max(peak, live);
-        if (!free_cls[c].empty()) {
-            cplx<T>* p = free_cls[c].back();
-            free_cls[c].pop_back();
-            return p;
+    static size_t rounded(size_t n) { return std::max<size_t>(32, (n + 31) & ~size_t(31)); }
+    void add_free(P p, size_t n, int chunk) {
+        auto nx = free_at.find(p + n);
+        if (nx != free_at.end() && nx->second.chunk == chunk) {
+            free_by_size.erase({nx->second.n, nx->first});
+            n += nx->second.n;
+            free_at.erase(nx);
         }
-        return bump.alloc(cls_size(c));
+        auto it = free_at.lower_bound(p);
+        if (it != free_at.begin()) {
+            auto pv = std::prev(it);
+            if (pv->second.chunk == chunk && pv->first + pv->second.n == p) {
+                free_by_size.erase({pv->second.n, pv->first});
+                p = pv->first;
+                n += pv->second.n;
+                free_at.erase(pv);
+            }
+        }
+        free_at[p] = Range{n, chunk};
+        free_by_size.insert({n, p});
+    }
+    P alloc(size_t n) {
+        n = rounded(n);
+        auto it = free_by_size.lower_bound({n, nullptr});
+        if (it == free_by_size.end()) {
+            DBuf<cplx<T>> b;
+            b.alloc(std::max(n, chunk_elems));
+            const int id = (int)chunks.size();
+            chunks.push_back(std::move(b));
+            chunk_at[chunks.back().p] = id;
+            add_free(chunks.back().p, chunks.back().n, id);
+            it = free_by_size.lower_bound({n, nullptr});
+        }
+        const size_t have = it->first;
+        const P p = it->second;
+        free_by_size.erase(it);
+        auto fr = free_at.find(p);
+        const int chunk = fr->second.chunk;
+        free_at.erase(fr);
+        if (have > n) {
+            free_at[p + n] = Range{have - n, chunk};
+            free_by_size.insert({have - n, p + n});
+        }
+        live += n;
+        peak = std::max(peak, live);
+        return p;
     }
     // n: the size passed to alloc
-    void release(cplx<T>* p, size_t n) {
+    void release(P p, size_t n) {
         if (!p) return;
-        rec.push_back({p, cls(n)});
-        live -= cls_size(cls(n));
+        n = rounded(n);
+        rec.push_back({p, n});
+        live -= n;
     }
     void launched() {
         run.insert(run.end(), rec.begin(), rec.end());
         rec.clear();
     }
     void completed() {
-        for (auto& x : run) free_cls[x.second].push_back(x.first);
+        for (auto& x : run) {
+            auto c = std::prev(chunk_at.upper_bound(x.first));
+            add_free(x.first, x.second, c->second);
+        }
         run.clear();
+    }
+    double capacity() const {
+        double c = 0;
+        for (const auto& b : chunks) c += (double)b.n;
+        return c;
     }
 };
 
@@ -1823,7 +1873,7 @@ template <typename T> static void run_factor(Ctx& c, HF<T>& f) {
                     "[cbie] factorization stopped: storage %.2f GB live (peak %.2f GB, arena %.2f GB), scratch %.2f GB, "
                     "recompression scratch %.2f GB, split-k %.2f GB, levels %lld, flushes %lld\n",
                     1e-9 * (double)f.store.live * sizeof(cplx<T>), 1e-9 * (double)f.store.peak * sizeof(cplx<T>),
-                    1e-9 * f.store.bump.capacity() * sizeof(cplx<T>), 1e-9 * f.scratch.capacity() * sizeof(cplx<T>),
+                    1e-9 * f.store.capacity() * sizeof(cplx<T>), 1e-9 * f.scratch.capacity() * sizeof(cplx<T>),
                     1e-9 * f.rscratch.capacity() * sizeof(cplx<T>),
                     1e-9 * (f.wsp[0].capacity() + f.wsp[1].capacity() + f.wsr.capacity()) * sizeof(cplx<T>),
                     (long long)f.levels_run, (long long)f.flushes);
@@ -1866,7 +1916,7 @@ template <typename T> static void run_factor(Ctx& c, HF<T>& f) {
                 (long long)f.recompress_rounds, f.width_lr_a,
                 f.width_lr_b, f.width_dd, f.flush_k, f.t_wait, now_s() - f.t_start, f.t_level,
                 (long long)f.n_level_calls, (long long)f.n_scanned, f.t_exec, f.t_recomp,
-                1e-9 * (double)f.store.bump.live * sizeof(cplx<T>), 1e-9 * (double)f.store.peak * sizeof(cplx<T>),
+                1e-9 * f.store.capacity() * sizeof(cplx<T>), 1e-9 * (double)f.store.peak * sizeof(cplx<T>),
                 1e-9 * f.scratch.capacity() * sizeof(cplx<T>), 1e-9 * f.rscratch.capacity() * sizeof(cplx<T>),
                 1e-9 * (f.wsp[0].capacity() + f.wsp[1].capacity() + f.wsr.capacity()) * sizeof(cplx<T>), f.gpu_prog,
                 f.gpu_recomp);
