@@ -19,6 +19,13 @@ waves per object, in one context (every stage in shared launches), mixed
 pipeline, one step.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-dielectric] [--no-batch]
+python bench.py --large-ellipsoid   (the PEC ellipsoid of semi-axes (8, 4, 2) m,
+                                ka = 40, 196608 unknowns, ACA 1e-6: the rank
+                                network trained on the GPU from the adaptive
+                                ranks of the small sphere and 24 seeded
+                                ellipsoids; adaptive vs predicted-width
+                                compression; complex64 H-LU + refinement and
+                                a one-wave solve; one JSON line, about 2 min)
 python bench.py --copy-probe   (a plain 1 GiB read + 1 GiB write elementwise
                                 kernel, three launches: the reference for
                                 scaling HBM traffic counters)
@@ -105,6 +112,75 @@ def ellipsoid_batch(cbie, W):
             "phases_s": {p: st["t_" + p] for p in ("tree", "fill", "compress", "factor", "solve")}}
 
 
+def large_ellipsoid(cbie, W):
+    """Rank network trained on the GPU, then the 196608-unknown ellipsoid
+    compressed adaptively and with predicted widths (same ranks), factored
+    in complex64 and solved with FP64 refinement."""
+    import numpy as np
+    import torch
+    tols = [10.0 ** -e for e in range(3, 10)]
+    dev = lambda a: torch.from_numpy(np.ascontiguousarray(a)).cuda()
+    t0 = time.perf_counter()
+    F, R = [], []
+    for objs in ([W.sphere_pec_small()], W.ellipsoid_batch(24, seed=3)):
+        s = cbie.Solver(objs)
+        s.build_tree(leaf_size=256, eta=1.0, near_delta=1.0)
+        s.fill()
+        for tol in tols:
+            s.compress(tol)
+            f, r = s.block_features(tol)
+            F.append(f)
+            R.append(r)
+        s.close()
+    F, R = np.concatenate(F), np.concatenate(R)
+    mean = F.mean(0).astype(np.float32)
+    sdev = np.maximum(F.std(0), 1e-3).astype(np.float32)
+    steps, batch = 4000, 256
+    rng = np.random.default_rng(0)
+    order = np.concatenate([rng.permutation(F.shape[0]) for _ in range(steps * batch // F.shape[0] + 1)])
+    p = dev(W.mlp_initial_weights(0))
+    losses = cbie.mlp_train(p, dev(mean), dev(sdev), dev(F), dev(np.log(np.maximum(R, 1)).astype(np.float32)),
+                            dev(order[:steps * batch].astype(np.int32)), batch, 2e-3)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    print(f"[bench] rank network: {F.shape[0]} samples, {t_train:.1f} s", file=sys.stderr, flush=True)
+
+    spec = W.ellipsoid_pec_large()
+    s = cbie.Solver([spec])
+    s.build_tree(leaf_size=256, eta=1.0, near_delta=1.0)
+    s.fill()
+    out = {"workload": "PEC ellipsoid semi-axes (8, 4, 2) m, ka = 40, 1536 patches q = 8, 196608 unknowns, "
+                       "leaf 256, eta 1, ACA 1e-6, 1 plane wave, mixed pipeline",
+           "training": {"samples": int(F.shape[0]), "steps": steps, "seconds": t_train,
+                        "loss_first": float(losses[:20].mean()), "loss_last": float(losses[-100:].mean())},
+           "fill_s": s.stats()["t_fill"]}
+    ranks = {}
+    s.set_rank_model(p.cpu().numpy(), mean, sdev, margin=0.25)
+    for name, mode in (("adaptive", cbie.RANK_ADAPTIVE), ("predicted", cbie.RANK_PREDICTED)):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.compress(1e-6, mode=mode)
+        torch.cuda.synchronize()
+        st = s.stats()
+        ranks[name] = s.block_features(1e-6)[1]
+        out[name] = {"seconds": time.perf_counter() - t1, "aca_workspace_GiB": st["aca_workspace_bytes"] / 2 ** 30,
+                     "fallbacks": st["aca_fallbacks"], "lr_blocks": st["n_lr_blocks"], "max_rank": st["max_rank"]}
+        print(f"[bench] large ellipsoid, {name} compress: {out[name]['seconds']:.2f} s", file=sys.stderr, flush=True)
+    out["ranks_equal"] = bool(np.array_equal(ranks["adaptive"], ranks["predicted"]))
+    kh, pol = W.plane_waves(1, seed=0)
+    t1 = time.perf_counter()
+    s.factor(cbie.PREC_C64_IR)
+    b = s.rhs_planewave(kh, pol)
+    x, it = s.solve(b, tol=1e-10, maxit=30)
+    torch.cuda.synchronize()
+    st = s.stats()
+    out["factor_solve"] = {"seconds": time.perf_counter() - t1, "factor_s": st["t_factor"], "solve_s": st["t_solve"],
+                           "factor_flops": st["factor_flops"], "ir_iterations": it,
+                           "residual": (torch.linalg.norm(s.matvec(x) - b) / torch.linalg.norm(b)).item()}
+    s.close()
+    return out
+
+
 def gemm_traffic(pipeline):
     """HBM bytes per k_zgemm launch from the committed counter runs
     (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known size), or
@@ -171,6 +247,7 @@ def main():
     ap.add_argument("--no-dielectric", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--large-ellipsoid", action="store_true")
     args = ap.parse_args()
     if args.copy_probe:
         import torch
@@ -192,6 +269,9 @@ def main():
     from paper_2408_17116_amd import cbie
     from synth import workloads as W
 
+    if args.large_ellipsoid:
+        print(json.dumps({"large_ellipsoid": large_ellipsoid(cbie, W)}))
+        return
     spec = W.sphere_pec_ka20()
     kh, pol = W.plane_waves(16, seed=0)
     N = spec.n_unknowns

@@ -135,6 +135,17 @@ def ellipsoid_batch(n: int = 64, seed: int = 0) -> List[ObjectSpec]:
     return out
 
 
+def mlp_initial_weights(seed: int = 0) -> np.ndarray:
+    """Seeded initial parameters of the 8-64-64-1 rank network in the
+    library's packing (W1 64x8 row-major, b1, W2 64x64 row-major, b2, W3,
+    b3), float32: He-normal weights (std sqrt(2 / fan_in)), zero biases."""
+    rng = np.random.default_rng(seed)
+    w1 = rng.standard_normal((64, 8)) * math.sqrt(2.0 / 8)
+    w2 = rng.standard_normal((64, 64)) * math.sqrt(2.0 / 64)
+    w3 = rng.standard_normal(64) * math.sqrt(2.0 / 64)
+    return np.concatenate([w1.ravel(), np.zeros(64), w2.ravel(), np.zeros(64), w3, np.zeros(1)]).astype(np.float32)
+
+
 def tiny_sphere(s: int = 1, q: int = 4, k0: float = 1.0) -> ObjectSpec:
     """Small spheres for brute-force checks (6 s^2 patches)."""
     return ObjectSpec(axes=(1.0, 1.0, 1.0), center=(0.0, 0.0, 0.0), s=s, q=q,

@@ -63,3 +63,13 @@ def test_training_fits_a_smooth_target():
     p, losses = mlp.train(X, t, order, batch=128, lr=3e-3, seed=1)
     assert losses[-20:].mean() < 0.05 * losses[:5].mean()
     assert mlp.loss(p, X, t) < 0.02
+
+
+def test_seeded_initial_weights_share_the_oracle_layout():
+    """The input generator's initial parameters (used by the benchmark) are
+    the oracle's He-normal draw in the same packing, rounded to float32."""
+    from synth import workloads as W
+    for seed in (0, 5):
+        a = W.mlp_initial_weights(seed)
+        assert a.dtype == np.float32 and a.size == mlp.N_PARAMS
+        assert np.array_equal(a, mlp.init(seed).astype(np.float32))
