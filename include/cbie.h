@@ -102,18 +102,28 @@ cbie_status cbie_create(const cbie_object* objs, int n_objs, void* hip_stream,
  * cluster holds <= leaf_size unknowns or one patch, and block cluster tree
  * with admissibility min(diam_t, diam_s) <= eta dist(t, s) on bounding
  * boxes (eq. 21); a block holding a near pair is never admissible.
- * Errors: EINVAL (leaf_size < 2 q^2, eta <= 0, near_delta <= 0), ENOMEM, EHIP. */
+ * Errors: EINVAL (leaf_size below the unknowns of one patch, upn q^2 with
+ * upn = 2 (MFIE) or 4 (N-Mueller), or above 256; eta <= 0, near_delta <= 0),
+ * ENOMEM, EHIP. */
 cbie_status cbie_build_tree(cbie_ctx* ctx, int leaf_size, double eta, double near_delta);
 
 /* Fill the inadmissible (dense) blocks: far entries by the Fejer rule,
- * self/near entries by the change-of-variables quadrature, 1/2 identity.
+ * self/near entries by the change-of-variables quadrature, plus the identity
+ * term (1/2 for the MFIE; (mu1 + mu2)/2 and -(eps1 + eps2)/2 for N-Mueller).
  * n_ang / n_rad: points of the singular rule per angular / radial direction
  * (0 = defaults 40 / 32).  Errors: ESTATE, ENOMEM, EHIP. */
 cbie_status cbie_fill(cbie_ctx* ctx, int n_ang, int n_rad);
 
-/* Compress the admissible blocks by partial-pivot ACA to relative Frobenius
- * tolerance aca_tol, then recompress each block (QR + SVD truncation at the
- * same tolerance).  Errors: ESTATE, EINVAL, ENOMEM, EHIP. */
+/* Compress the admissible blocks by partial-pivot ACA (Sec. III-A) to the
+ * relative Frobenius tolerance aca_tol; each block keeps its ACA factors
+ * U (m x r) and V (n x r) at the rank where ACA stopped (at most 512).
+ * mode CBIE_RANK_ADAPTIVE sizes each block's workspace at full width,
+ * CBIE_RANK_PREDICTED at the width the rank model predicts (see
+ * cbie_set_rank_model); both give the same factors.  Blocks are processed in
+ * rounds whose ACA workspace fits 2^30 complex elements (environment
+ * variable CBIE_ACA_BUDGET: another element count), so the workspace stays
+ * bounded at any problem size.  Errors: ESTATE, EINVAL (aca_tol outside (0, 1),
+ * CBIE_RANK_PREDICTED without a model), ENOMEM, EHIP. */
 cbie_status cbie_compress(cbie_ctx* ctx, double aca_tol, cbie_rank_mode mode);
 
 /* H-LU factorization (eqs. 23-28): partial pivoting inside diagonal leaves,
