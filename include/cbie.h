@@ -153,14 +153,17 @@ cbie_status cbie_solve(cbie_ctx* ctx, int nrhs, const void* b_dev, void* x_dev, 
 cbie_status cbie_matvec(cbie_ctx* ctx, int nrhs, const void* x_dev, void* y_dev, long ld);
 
 /* Right-hand sides of eq. (22) for nw plane waves E = pol e^{-j k khat.r},
- * H = khat x E: b_u = -a_v . H, b_v = a_u . H.  khat, pol: host arrays of
- * 3*nw doubles.  b_dev: complex128 device array n_unknowns x nw, ld.
+ * H = khat x E: b_u = -a_v . H, b_v = a_u . H per node; N-Mueller objects
+ * (eq. 19, exterior vacuum) add the electric rows -a_v . E, a_u . E after
+ * them.  khat, pol: host arrays of 3*nw doubles.  b_dev: complex128 device array n_unknowns x nw, ld.
  * Errors: ESTATE (before build_tree), EINVAL, EHIP. */
 cbie_status cbie_rhs_planewave(cbie_ctx* ctx, int nw, const double* khat, const double* pol,
                                void* b_dev, long ld);
 
-/* Far field r e^{j k r} E_s = -j k N_perp / (4 pi), N = sum_nodes
- * w (F^u a_u + F^v a_v) e^{j k rhat.r}, for nrhs solutions x_dev (device,
+/* Far field r e^{j k r} E_s = -j k (N_perp - rhat x L) / (4 pi), N = sum_nodes
+ * w (F^u a_u + F^v a_v) e^{j k rhat.r} from the electric current and L the
+ * same sum from the magnetic current (N-Mueller objects; L = 0 on a
+ * conductor), for nrhs solutions x_dev (device,
  * ld) at ndir directions rhat (host, 3*ndir doubles).  E_out: host array of
  * 3 * ndir * nrhs complex128 (x,y,z fastest, then direction, then rhs).
  * Errors: ESTATE, EINVAL, EHIP. */
@@ -189,7 +192,9 @@ typedef struct {
     double gemm_flops;
     double gemm_seconds;
     /* compress: admissible blocks redone with the full width because the
-     * predicted width was too small; ACA workspace of the pass(es), bytes */
+     * predicted width was too small; ACA workspace the widths asked for,
+     * bytes, summed over every round of both passes (at any time at most
+     * one round's budget is allocated) */
     int64_t aca_fallbacks;
     double aca_workspace_bytes;
     /* solve: substitutions run as a replay of the captured HIP graph of the
