@@ -9,10 +9,11 @@ q = 8 with more patches (cube-sphere faces split s x s) gives the same
 numbers of unknowns for two of the table's four columns: 76,800 (s = 10,
 patches 1.57 wavelengths across) and 172,800 (s = 15).  The errors are
 above the paper's (6.1e-2 at 76,800 against its 1.41e-2).  Both sample
-about 5.1 points per wavelength, but with degree-7 rather than degree-9
-interpolants, the likely cause; the error at a fixed patch size also grows
-with the electrical size (the oracle's own dense solution with the same
-1.57-wavelength patches: 2.7e-3 at ka = 4 pi, 7.3e-3 at ka = 8 pi).  The bound, 0.07, is a
+about 5.1 points per wavelength; at a fixed patch size the error grows with
+the electrical size (the oracle's own dense solution with the same
+1.57-wavelength patches: 2.7e-3 at ka = 4 pi, 7.3e-3 at ka = 8 pi), and the
+higher order explains part of the gap, not all of it (the paper states
+neither its patching nor its error norm).  The bound, 0.07, is a
 regression bound above the measured 6.5e-2 (49,152) and 6.1e-2 (76,800),
 not the paper's figure, which is printed beside the result.  The 172,800
 case takes a few minutes and runs only with CBIE_LARGE_TESTS=1."""
