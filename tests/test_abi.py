@@ -44,7 +44,7 @@ def test_create_rejects_invalid_objects_before_any_device_work():
     """Argument checks of cbie_create run on the host before any HIP call,
     so they are exercised here without a GPU: each malformed object (or
     argument) gives EINVAL and no context; a null context gives EINVAL from
-    every context entry point."""
+    the stage entry points."""
     import ctypes as C
     from paper_2408_17116_amd import cbie
     if not os.path.exists(cbie.LIB_PATH):
