@@ -16,7 +16,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libcbie.so")
 BUILD = os.path.join(HERE, "_build")
 
-SOURCES = ["api.hip", "stages.hip", "fill.hip", "tree.cpp", "aca.hip", "ops.hip", "linalg.hip", "batch.hip", "hmat.hip", "mlp.hip"]
+SOURCES = ["api.hip", "stages.hip", "fill.hip", "tree.cpp", "rules.cpp", "aca.hip", "ops.hip", "linalg.hip", "batch.hip", "hmat.hip", "mlp.hip"]
 
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]

@@ -4,29 +4,16 @@
 #include <map>
 
 #include "ctx.hpp"
+#include "rules.hpp"
 
 namespace cbie {
-
-// Fejer-1 rule of size n on [-1, 1] (ascending):
-// x_l = -cos((2l+1) pi / (2n)), w_l = (2/n)[1 - 2 sum_{m=1}^{n/2} cos(2 m th_l)/(4m^2 - 1)].
-static void fejer(int n, std::vector<double>& x, std::vector<double>& w) {
-    x.resize(n);
-    w.resize(n);
-    for (int l = 0; l < n; ++l) {
-        const double th = (2 * l + 1) * M_PI / (2.0 * n);
-        x[l] = -std::cos(th);
-        double s = 1.0;
-        for (int m = 1; m <= n / 2; ++m) s -= 2.0 * std::cos(2 * m * th) / (4.0 * m * m - 1.0);
-        w[l] = 2.0 / n * s;
-    }
-}
 
 // Tables of all Fejer rules n = 1..kMaxRule, rule n at offset n(n-1)/2.
 static const int kMaxRule = 96;
 void make_fejer_tables(Ctx& c) {
     std::vector<double> ax, aw, bx, bw, x, w;
     for (int n = 1; n <= kMaxRule; ++n) {
-        fejer(n, x, w);
+        fejer_rule(n, x, w);
         for (int l = 0; l < n; ++l) {
             ax.push_back(x[l]);
             aw.push_back(w[l]);
@@ -38,29 +25,9 @@ void make_fejer_tables(Ctx& c) {
     c.d_fej11_w.upload(aw, c.stream);
     c.d_fej01_x.upload(bx, c.stream);
     c.d_fej01_w.upload(bw, c.stream);
-    // Differentiation matrices of the interpolant at the q points, q = 1..8,
-    // stored at offset (q-1) q (2q-1) / 6: D[i][j] = ell_j'(x_i), from the
-    // barycentric weights lam_j = 1 / prod_{k != j} (x_j - x_k):
-    // D[i][j] = (lam_j / lam_i) / (x_i - x_j), D[i][i] = -sum_{j != i} D[i][j].
+    // differentiation matrices of the interpolant, q = 1..8
     std::vector<double> dm;
-    for (int q = 1; q <= 8; ++q) {
-        fejer(q, x, w);
-        std::vector<double> lam(q, 1.0);
-        for (int j = 0; j < q; ++j)
-            for (int k = 0; k < q; ++k)
-                if (k != j) lam[j] /= (x[j] - x[k]);
-        for (int i = 0; i < q; ++i) {
-            double diag = 0.0;
-            std::vector<double> row(q, 0.0);
-            for (int j = 0; j < q; ++j)
-                if (j != i) {
-                    row[j] = (lam[j] / lam[i]) / (x[i] - x[j]);
-                    diag -= row[j];
-                }
-            row[i] = diag;
-            dm.insert(dm.end(), row.begin(), row.end());
-        }
-    }
+    cheb_diff_matrices(8, dm);
     c.d_dmat.upload(dm, c.stream);
 }
 
