@@ -81,3 +81,16 @@ def test_create_rejects_invalid_objects_before_any_device_work():
     assert lib.cbie_fill(None, 0, 0) == cbie.EINVAL
     assert lib.cbie_compress(None, 1e-6, 0) == cbie.EINVAL
     assert lib.cbie_factor(None, 0) == cbie.EINVAL
+
+
+def test_library_leaves_none_of_its_own_symbols_undefined():
+    """A shared library links with undefined symbols and fails only when one
+    is first called: every function of the library's own namespace must be
+    defined in it."""
+    import shutil
+    import subprocess
+    from paper_2408_17116_amd import cbie
+    if not os.path.exists(cbie.LIB_PATH) or shutil.which("nm") is None:
+        pytest.skip("libcbie.so not built or nm missing")
+    out = subprocess.run(["nm", "-C", "-u", cbie.LIB_PATH], capture_output=True, text=True, check=True).stdout
+    assert [l for l in out.splitlines() if "cbie::" in l or " cbie_" in l] == []
