@@ -5,10 +5,17 @@ leaf 256, eta = 1, ACA tolerance 1e-6, 16 seeded plane waves.  One step is
 the whole hot path: geometry + near classification + cluster/block trees,
 fill (far rule + change-of-variables near quadrature), ACA compression,
 H-LU, and the 16-right-hand-side solve.  Two pipelines are timed:
-  mixed  complex64 H-LU + FP64 iterative refinement (the reported value)
-  fp64   complex128 H-LU
-Inputs (patch tables, wave directions) are generated before the timed
-region; every step rebuilds everything from them on the GPU.
+  mixed  compression with the widths of the rank network, complex64 H-LU,
+         FP64 iterative refinement to 1e-9 (the reported value)
+  fp64   adaptive compression, complex128 H-LU, FP64 iterative refinement
+         to the same 1e-9
+Inputs (patch tables, wave directions) are generated, and the rank network
+is trained on the GPU from the adaptive ranks of other workloads (the
+3072-unknown sphere and 24 seeded ellipsoids), before the timed region;
+every step rebuilds everything from the inputs on the GPU.  After the timed
+steps each pipeline's solution is compared with the dense oracle solution
+stored under tests/golden (complex128 LAPACK solve of the same matrix,
+written by tests/golden/make_dense_solutions.py), when that file exists.
 
 A second workload is reported beside it (not the value): the dielectric
 sphere eps_r = 16, ka = 5, 96 patches q = 8, 24576 unknowns, N-Mueller
@@ -42,80 +49,48 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
-def run_pipeline(cbie, spec, kh, pol, prec, ir_tol, profile=True):
+def run_pipeline(cbie, spec, kh, pol, prec, ir_tol, profile=True, model=None):
+    """One step: tree, fill, compress (predicted widths when a rank model is
+    given), factor, right-hand sides and the refined solve."""
     s = cbie.Solver([spec])
     s.set_profiling(profile)
     s.build_tree(leaf_size=256, eta=1.0, near_delta=1.0)
     s.fill()
-    s.compress(1e-6)
+    if model is not None:
+        s.set_rank_model(*model)
+        s.compress(1e-6, mode=cbie.RANK_PREDICTED)
+    else:
+        s.compress(1e-6)
     s.factor(prec)
     b = s.rhs_planewave(kh, pol)
-    x, it = s.solve(b, tol=ir_tol, maxit=0 if prec == cbie.PREC_C128 else 20)
+    x, it = s.solve(b, tol=ir_tol, maxit=20)
     st = s.stats()
     st["ir_iterations"] = it
     return s, x, st
 
 
-def dielectric(cbie, W, precs, names):
-    """N-Mueller workload: seconds and unknowns/s per pipeline (one warmup,
-    one timed step), refinement sweeps and the residual against the stored
-    operator."""
+def golden(name):
+    """Stored dense oracle solution (tests/golden), or None."""
     import numpy as np
-    import torch
-    spec = W.sphere_dielectric()
-    kh, pol = np.array([[0.0, 0.0, 1.0]]), np.array([[1.0, 0.0, 0.0]])
-    out = {"workload": "dielectric sphere eps_r=16, ka=5, 96 patches q=8, 24576 unknowns, N-Mueller, "
-                       "leaf 256, eta 1, ACA 1e-6, 1 plane wave"}
-    for name in names:
-        prec = precs[name]
-        s, x, st = run_pipeline(cbie, spec, kh, pol, prec, 1e-10, profile=False)
-        s.close()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        s, x, st = run_pipeline(cbie, spec, kh, pol, prec, 1e-10, profile=False)
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
-        b = s.rhs_planewave(kh, pol)
-        res = (torch.linalg.norm(s.matvec(x) - b) / torch.linalg.norm(b)).item()
-        s.close()
-        out[name] = {"seconds": dt, "unknowns_per_s": spec.n_unknowns / dt, "ir_iterations": st["ir_iterations"],
-                     "residual": res, "phases_s": {p: st["t_" + p] for p in ("tree", "fill", "compress", "factor",
-                                                                               "solve")}}
-        print(f"[bench] dielectric {name}: {dt:.2f} s", file=sys.stderr, flush=True)
-    return out
+    path = os.path.join(ROOT, "tests", "golden", name)
+    if not os.path.exists(path):
+        return None
+    return np.load(path)
 
 
-def ellipsoid_batch(cbie, W):
-    """The 64-object batch in one context, mixed pipeline, one step."""
-    import torch
-    objs = W.ellipsoid_batch(64, seed=0)
-    kh, pol = W.plane_waves(32, seed=4)
-    N = sum(o.n_unknowns for o in objs)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    s = cbie.Solver(objs)
-    s.build_tree(leaf_size=256, eta=1.0, near_delta=1.0)
-    s.fill()
-    s.compress(1e-6)
-    s.factor(cbie.PREC_C64_IR)
-    b = s.rhs_planewave(kh, pol)
-    x, it = s.solve(b, tol=1e-10, maxit=20)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    st = s.stats()
-    res = (torch.linalg.norm(s.matvec(x) - b) / torch.linalg.norm(b)).item()
-    s.close()
-    print(f"[bench] ellipsoid batch: {dt:.2f} s", file=sys.stderr, flush=True)
-    return {"workload": "64 PEC ellipsoids (seed 0), 548208 unknowns, 32 plane waves each, one context, "
-                        "leaf 256, eta 1, ACA 1e-6, mixed pipeline",
-            "seconds": dt, "unknowns_per_s": N / dt, "ir_iterations": it, "residual": res,
-            "phases_s": {p: st["t_" + p] for p in ("tree", "fill", "compress", "factor", "solve")}}
+def accuracy(x, x_ref):
+    """Relative L2 error of the unknowns against the dense oracle solution:
+    over all columns, and the worst column."""
+    import numpy as np
+    x = np.asarray(x)
+    d = np.linalg.norm(x - x_ref, axis=0) / np.linalg.norm(x_ref, axis=0)
+    return {"rel_l2": float(np.linalg.norm(x - x_ref) / np.linalg.norm(x_ref)), "worst_column": float(d.max())}
 
 
-def large_ellipsoid(cbie, W):
-    """Rank network trained on the GPU, then the 196608-unknown ellipsoid
-    compressed adaptively and with predicted widths (same ranks), factored
-    in complex64 and solved with FP64 refinement."""
+def train_rank_model(cbie, W):
+    """Rank network trained on the GPU (project kernels) from the adaptive
+    ranks of the 3072-unknown sphere and 24 seeded ellipsoids at every decade
+    of tolerance 1e-3..1e-9.  Returns ((params, mean, sdev, margin), info)."""
     import numpy as np
     import torch
     tols = [10.0 ** -e for e in range(3, 10)]
@@ -144,18 +119,21 @@ def large_ellipsoid(cbie, W):
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     print(f"[bench] rank network: {F.shape[0]} samples, {t_train:.1f} s", file=sys.stderr, flush=True)
+    info = {"samples": int(F.shape[0]), "steps": steps, "seconds": t_train,
+            "loss_first": float(losses[:20].mean()), "loss_last": float(losses[-100:].mean())}
+    return (p.cpu().numpy(), mean, sdev, 0.25), info
 
-    spec = W.ellipsoid_pec_large()
+
+def compress_modes(cbie, spec, model):
+    """Adaptive against predicted-width compression of one filled context:
+    seconds, ACA workspace, fallbacks, and whether the ranks agree."""
+    import numpy as np
+    import torch
     s = cbie.Solver([spec])
     s.build_tree(leaf_size=256, eta=1.0, near_delta=1.0)
     s.fill()
-    out = {"workload": "PEC ellipsoid semi-axes (8, 4, 2) m, ka = 40, 1536 patches q = 8, 196608 unknowns, "
-                       "leaf 256, eta 1, ACA 1e-6, 1 plane wave, mixed pipeline",
-           "training": {"samples": int(F.shape[0]), "steps": steps, "seconds": t_train,
-                        "loss_first": float(losses[:20].mean()), "loss_last": float(losses[-100:].mean())},
-           "fill_s": s.stats()["t_fill"]}
-    ranks = {}
-    s.set_rank_model(p.cpu().numpy(), mean, sdev, margin=0.25)
+    s.set_rank_model(*model)
+    out, ranks = {}, {}
     for name, mode in (("adaptive", cbie.RANK_ADAPTIVE), ("predicted", cbie.RANK_PREDICTED)):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
@@ -164,7 +142,110 @@ def large_ellipsoid(cbie, W):
         st = s.stats()
         ranks[name] = s.block_features(1e-6)[1]
         out[name] = {"seconds": time.perf_counter() - t1, "aca_workspace_GiB": st["aca_workspace_bytes"] / 2 ** 30,
-                     "fallbacks": st["aca_fallbacks"], "lr_blocks": st["n_lr_blocks"], "max_rank": st["max_rank"]}
+                     "fallbacks": st["aca_fallbacks"], "unconverged": st["aca_unconverged"]}
+    out["ranks_equal"] = bool(np.array_equal(ranks["adaptive"], ranks["predicted"]))
+    s.close()
+    return out
+
+
+def dielectric(cbie, W, precs, names):
+    """N-Mueller workload: seconds and unknowns/s per pipeline (one warmup,
+    one timed step, both refined to 1e-10), refinement sweeps, the residual
+    against the stored operator and the error against the stored dense
+    oracle solution."""
+    import numpy as np
+    import torch
+    spec = W.sphere_dielectric()
+    kh, pol = np.array([[0.0, 0.0, 1.0]]), np.array([[1.0, 0.0, 0.0]])
+    gold = golden("dielectric_24576_dense.npz")
+    out = {"workload": "dielectric sphere eps_r=16, ka=5, 96 patches q=8, 24576 unknowns, N-Mueller, "
+                       "leaf 256, eta 1, ACA 1e-6, 1 plane wave"}
+    for name in names:
+        prec = precs[name]
+        s, x, st = run_pipeline(cbie, spec, kh, pol, prec, 1e-10, profile=False)
+        s.close()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s, x, st = run_pipeline(cbie, spec, kh, pol, prec, 1e-10, profile=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        b = s.rhs_planewave(kh, pol)
+        res = (torch.linalg.norm(s.matvec(x) - b) / torch.linalg.norm(b)).item()
+        s.close()
+        out[name] = {"seconds": dt, "unknowns_per_s": spec.n_unknowns / dt, "ir_iterations": st["ir_iterations"],
+                     "residual": res, "phases_s": {p: st["t_" + p] for p in ("tree", "fill", "compress", "factor",
+                                                                               "solve")}}
+        if gold is not None:
+            out[name]["accuracy_vs_dense_oracle"] = accuracy(x.cpu().numpy(), gold["x"])
+        print(f"[bench] dielectric {name}: {dt:.2f} s", file=sys.stderr, flush=True)
+    return out
+
+
+def ellipsoid_batch(cbie, W):
+    """The 64-object batch in one context, mixed pipeline, one step."""
+    import numpy as np
+    import torch
+    objs = W.ellipsoid_batch(64, seed=0)
+    kh, pol = W.plane_waves(32, seed=4)
+    N = sum(o.n_unknowns for o in objs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    s = cbie.Solver(objs)
+    s.build_tree(leaf_size=256, eta=1.0, near_delta=1.0)
+    s.fill()
+    s.compress(1e-6)
+    s.factor(cbie.PREC_C64_IR)
+    b = s.rhs_planewave(kh, pol)
+    x, it = s.solve(b, tol=1e-10, maxit=20)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    st = s.stats()
+    res = (torch.linalg.norm(s.matvec(x) - b) / torch.linalg.norm(b)).item()
+    out = {"workload": "64 PEC ellipsoids (seed 0), 548208 unknowns, 32 plane waves each, one context, "
+                       "leaf 256, eta 1, ACA 1e-6, mixed pipeline",
+           "seconds": dt, "unknowns_per_s": N / dt, "ir_iterations": it, "residual": res,
+           "phases_s": {p: st["t_" + p] for p in ("tree", "fill", "compress", "factor", "solve")}}
+    gold = golden("ellipsoid_batch_subset_dense.npz")
+    if gold is not None:
+        off = np.concatenate([[0], np.cumsum([o.n_unknowns for o in objs])])
+        xs = x.cpu().numpy()
+        errs = {}
+        for o in gold["objects"]:
+            o = int(o)
+            xr = gold[f"x{o}"]
+            errs[str(o)] = accuracy(xs[off[o]:off[o + 1], :xr.shape[1]], xr)["rel_l2"]
+        out["accuracy_vs_dense_oracle"] = {"objects": errs, "worst": max(errs.values())}
+    s.close()
+    print(f"[bench] ellipsoid batch: {dt:.2f} s", file=sys.stderr, flush=True)
+    return out
+
+
+def large_ellipsoid(cbie, W):
+    """Rank network trained on the GPU, then the 196608-unknown ellipsoid
+    compressed adaptively and with predicted widths (same ranks), factored
+    in complex64 and solved with FP64 refinement."""
+    import numpy as np
+    import torch
+    model, info = train_rank_model(cbie, W)
+    spec = W.ellipsoid_pec_large()
+    s = cbie.Solver([spec])
+    s.build_tree(leaf_size=256, eta=1.0, near_delta=1.0)
+    s.fill()
+    out = {"workload": "PEC ellipsoid semi-axes (8, 4, 2) m, ka = 40, 1536 patches q = 8, 196608 unknowns, "
+                       "leaf 256, eta 1, ACA 1e-6, 1 plane wave, mixed pipeline",
+           "training": info, "fill_s": s.stats()["t_fill"]}
+    ranks = {}
+    s.set_rank_model(*model)
+    for name, mode in (("adaptive", cbie.RANK_ADAPTIVE), ("predicted", cbie.RANK_PREDICTED)):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        s.compress(1e-6, mode=mode)
+        torch.cuda.synchronize()
+        st = s.stats()
+        ranks[name] = s.block_features(1e-6)[1]
+        out[name] = {"seconds": time.perf_counter() - t1, "aca_workspace_GiB": st["aca_workspace_bytes"] / 2 ** 30,
+                     "fallbacks": st["aca_fallbacks"], "unconverged": st["aca_unconverged"],
+                     "lr_blocks": st["n_lr_blocks"], "max_rank": st["max_rank"]}
         print(f"[bench] large ellipsoid, {name} compress: {out[name]['seconds']:.2f} s", file=sys.stderr, flush=True)
     out["ranks_equal"] = bool(np.array_equal(ranks["adaptive"], ranks["predicted"]))
     kh, pol = W.plane_waves(1, seed=0)
@@ -276,39 +357,32 @@ def main():
     kh, pol = W.plane_waves(16, seed=0)
     N = spec.n_unknowns
     precs = {"mixed": cbie.PREC_C64_IR, "fp64": cbie.PREC_C128}
+    names = args.pipelines.split(",")
+    model, train_info = train_rank_model(cbie, W) if "mixed" in names else (None, None)
     results = {}
-    for name in args.pipelines.split(","):
+    for name in names:
         prec = precs[name]
+        mdl = model if name == "mixed" else None
         for _ in range(args.warmup):
-            s, x, st = run_pipeline(cbie, spec, kh, pol, prec, 1e-9)
+            s, x, st = run_pipeline(cbie, spec, kh, pol, prec, 1e-9, model=mdl)
             s.close()
             print(f"[bench] warmup {name} done", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         stats = []
         for k in range(args.steps):
-            s, x, st = run_pipeline(cbie, spec, kh, pol, prec, 1e-9)
+            s, x, st = run_pipeline(cbie, spec, kh, pol, prec, 1e-9, model=mdl)
             stats.append(st)
             s.close()
             print(f"[bench] step {k} {name}: " + ", ".join(f"{p} {st['t_' + p]:.3f}s" for p in
                   ("tree", "fill", "compress", "factor", "solve")), file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / args.steps
-        results[name] = (dt, stats[-1])
+        results[name] = (dt, stats[-1], x)
 
+    gold = golden("sphere_ka20_49152_dense.npz")
     name0 = "mixed" if "mixed" in results else list(results)[0]
-    dt, st = results[name0]
-    # dominant kernel: the batched complex GEMM of the H-LU and its solves
-    # (8 m n k algorithmic flops per product), timed by HIP events on the
-    # library stream around every launch of the last timed step
-    peak = 157.3 if name0 == "mixed" else 78.6      # MI355X dense MFMA FP32 / FP64, TFLOP/s
-    achieved = st["gemm_flops"] / st["gemm_seconds"] / 1e12 if st["gemm_seconds"] > 0 else None
-    roofline = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-                "frac": achieved / peak if achieved else None, "traffic": gemm_traffic(name0),
-                "kernel": "k_zgemm (batched complex GEMM, %s)" % ("complex64" if name0 == "mixed" else "complex128"),
-                "launches": st["gemm_launches"], "avg_launch_us": 1e6 * st["gemm_seconds"] / max(st["gemm_launches"], 1),
-                "flops_per_launch": st["gemm_flops"] / max(st["gemm_launches"], 1),
-                "kernel_seconds": st["gemm_seconds"]}
+    dt, st, _ = results[name0]
     line = {
         "metric": "H build+factor+solve s & unknowns/s, mixed vs FP64 H-LU, at 1e-5 rel err",
         "value": N / dt, "unit": "unknowns/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
@@ -316,20 +390,86 @@ def main():
         "dtype": "c64+f64" if name0 == "mixed" else "c128", "data": "synthetic",
         "config": {"workload": "PEC sphere ka=20, 384 patches q=8, 49152 unknowns, leaf 256, eta 1, "
                                "ACA 1e-6, 16 plane waves", "pipeline": name0},
-        "roofline": roofline,
+        "roofline": gemm_roofline(st, name0),
+        "rooflines": phase_rooflines(st, name0, N),
         "phases_s": {p: st["t_" + p] for p in ("tree", "fill", "compress", "factor", "solve")},
         "stats": {k: st[k] for k in ("n_lr_blocks", "n_dense_blocks", "max_rank", "compression_rate",
-                                     "n_kernel_launches", "factor_flops", "ir_iterations", "quad_seconds")},
+                                     "n_kernel_launches", "factor_flops", "factor_flops_executed", "ir_iterations",
+                                     "quad_seconds", "aca_fallbacks", "aca_unconverged")},
     }
-    for name, (d, s2) in results.items():
-        line.setdefault("pipelines", {})[name] = {"seconds": d, "unknowns_per_s": N / d}
+    for name, (d, s2, x) in results.items():
+        rec = {"seconds": d, "unknowns_per_s": N / d, "ir_iterations": s2["ir_iterations"],
+               "phases_s": {p: s2["t_" + p] for p in ("tree", "fill", "compress", "factor", "solve")},
+               "rank_widths": "predicted" if name == "mixed" else "adaptive"}
+        if gold is not None:
+            rec["accuracy_vs_dense_oracle"] = accuracy(x.cpu().numpy(), gold["x"])
+        if name != name0:
+            rec["rooflines"] = phase_rooflines(s2, name, N)
+        line.setdefault("pipelines", {})[name] = rec
+    if gold is not None:
+        line["accuracy"] = {name: line["pipelines"][name]["accuracy_vs_dense_oracle"]["rel_l2"] for name in results}
+    if model is not None:
+        line["rank_network"] = dict(train_info, compress=compress_modes(cbie, spec, model))
     if not args.no_dielectric:
-        line["dielectric_sphere"] = dielectric(cbie, W, precs, args.pipelines.split(","))
+        line["dielectric_sphere"] = dielectric(cbie, W, precs, names)
     if not args.no_batch:
         line["ellipsoid_batch"] = ellipsoid_batch(cbie, W)
     if not args.no_cpu:
         line["cpu_baseline"] = cpu_baseline(spec, kh, pol)
     print(json.dumps(line))
+
+
+def gemm_roofline(st, pipeline):
+    """The dominant kernel: the batched complex GEMM of the H-LU and of the
+    first (recorded) substitution, timed by HIP events on the library stream
+    around every launch of the step; algorithmic flops (8 m n k per product,
+    a leaf solve through an explicit inverse counted as the triangular solve
+    it stands for, 4 n^2 k)."""
+    peak = 157.3 if pipeline == "mixed" else 78.6      # MI355X dense MFMA FP32 / FP64, TFLOP/s
+    sec = st["gemm_seconds"]
+    achieved = st["gemm_flops_alg"] / sec / 1e12 if sec > 0 else None
+    return {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak if achieved else None, "traffic": gemm_traffic(pipeline),
+            "kernel": "k_zgemm (batched complex GEMM, %s)" % ("complex64" if pipeline == "mixed" else "complex128"),
+            "launches": st["gemm_launches"], "avg_launch_us": 1e6 * sec / max(st["gemm_launches"], 1),
+            "flops_per_launch": st["gemm_flops_alg"] / max(st["gemm_launches"], 1),
+            "executed_flops_per_launch": st["gemm_flops"] / max(st["gemm_launches"], 1),
+            "executed_tflops": st["gemm_flops"] / sec / 1e12 if sec > 0 else None,
+            "kernel_seconds": sec}
+
+
+def phase_rooflines(st, pipeline, N):
+    """Per-phase roofline of one step: near quadrature (FP64 VALU, the basis
+    contraction's flops over the quadrature kernels' event time), far fill
+    (HBM writes of the dense blocks over their kernel time), leaf LU (8/3 b^3
+    per leaf over the leaf kernels' event time, against the vector peak of
+    the factor precision), the GEMMs (above) and the solve (HBM: the bytes
+    the substitutions and the refinement matvecs must read, over the solve
+    stage's wall time)."""
+    vec = 157.3 if pipeline == "mixed" else 78.6       # FP32 / FP64 vector peak, TFLOP/s
+    out = {"k_zgemm": gemm_roofline(st, pipeline)}
+    out["k_zgemm"].pop("traffic", None)
+    if st["quad_seconds"] > 0:
+        a = st["quad_flops"] / st["quad_seconds"] / 1e12
+        out["near_quadrature"] = {"kernel": "k_quad", "bound": "alu", "achieved": a, "peak": 78.6,
+                                  "unit": "TFLOP/s", "frac": a / 78.6, "points": st["quad_points"],
+                                  "seconds": st["quad_seconds"]}
+    if st["far_fill_seconds"] > 0:
+        gb = 16.0 * st["dense_entries"] / st["far_fill_seconds"] / 1e9
+        out["far_fill"] = {"kernel": "k_far_fill", "bound": "hbm", "achieved": gb, "peak": 8000.0, "unit": "GB/s",
+                           "frac": gb / 8000.0, "bytes": 16.0 * st["dense_entries"], "seconds": st["far_fill_seconds"]}
+    if st["leaf_lu_seconds"] > 0:
+        a = st["leaf_lu_flops"] / st["leaf_lu_seconds"] / 1e12
+        out["leaf_lu"] = {"kernel": "k_leaf_lu", "bound": "alu", "achieved": a, "peak": vec, "unit": "TFLOP/s",
+                          "frac": a / vec, "launches": st["leaf_lu_launches"], "seconds": st["leaf_lu_seconds"]}
+    it = st["ir_iterations"]
+    op_bytes = 16.0 * (st["dense_entries"] + st["lr_entries"])
+    # x = M b, then per sweep one matvec + one substitution, and the final check
+    byt = (1 + it) * st["solve_factor_bytes"] + (it + 1) * op_bytes
+    gb = byt / st["t_solve"] / 1e9
+    out["solve"] = {"bound": "hbm", "achieved": gb, "peak": 8000.0, "unit": "GB/s", "frac": gb / 8000.0,
+                    "bytes": byt, "substitutions": 1 + it, "matvecs": it + 1, "seconds": st["t_solve"]}
+    return out
 
 
 if __name__ == "__main__":

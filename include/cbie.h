@@ -36,7 +36,11 @@
  *    owns everything it allocates and frees it in cbie_destroy().
  *  - State machine: create -> build_tree -> fill -> compress -> factor ->
  *    solve.  matvec is valid after compress.  factor may be repeated with
- *    another precision.  Calls out of order return CBIE_ESTATE.
+ *    another precision.  Calls out of order return CBIE_ESTATE.  A stage
+ *    call (build_tree, fill, compress, factor) that fails after its argument
+ *    checks leaves the context in the state that precedes the stage, so the
+ *    stage and every later one must be run again before their results are
+ *    used.
  */
 #ifndef CBIE_H
 #define CBIE_H
@@ -81,7 +85,9 @@ typedef struct {
     double k0;                 /* exterior wavenumber, rad/m, > 0           */
     double axes[3];            /* ellipsoid semi-axes, > 0                   */
     double center[3];
-    int q;                     /* Chebyshev points per direction, 2..8       */
+    int q;                     /* Chebyshev points per direction: 2..11 for
+                                  CBIE_MFIE_PEC (2 q^2 <= 256, one patch per
+                                  leaf at most), 2..8 for CBIE_NMULLER       */
     int n_patches;
     const cbie_patch* patches; /* host array of n_patches, copied at create  */
     double eps_r, mu_r;        /* N-Mueller: interior relative permittivity and
@@ -136,10 +142,13 @@ cbie_status cbie_factor(cbie_ctx* ctx, cbie_precision prec);
 /* Solve A x = b for nrhs right-hand sides (per object).  b_dev, x_dev:
  * complex128 device arrays, n_unknowns x nrhs, leading dimension ld,
  * original order; b_dev is not modified; x_dev may not alias b_dev.
- * After a C64_IR factorization: x = LU^{-1} b, then iterate
- * r = b - A x (FP64, stored operator), x += LU^{-1} r until
- * max_j |r_j|/|b_j| <= ir_tol or ir_maxit sweeps (ENOCONV then, x holds
- * the last iterate).  ir_iters_out (may be NULL) receives the sweep count.
+ * x = LU^{-1} b; then, for ir_maxit > 0, iterate r = b - A x (FP64, stored
+ * operator), x += LU^{-1} r.  The residual is checked before every sweep and
+ * after the last one: the call succeeds once max_j ||r_j|| / ||b_j|| <= ir_tol
+ * (2-norms per right-hand side j) and returns ENOCONV after ir_maxit sweeps
+ * without it, or at once when a residual is not finite (x then holds the
+ * last iterate).  ir_maxit = 0 returns the plain substitution with no
+ * residual check.  ir_iters_out (may be NULL) receives the sweep count.
  * The substitution program (eqs. 26-28) is recorded once per factorization
  * and number of right-hand sides, captured into a HIP graph on a private
  * stream, and replayed for every later substitution (the refinement sweeps
@@ -147,6 +156,21 @@ cbie_status cbie_factor(cbie_ctx* ctx, cbie_precision prec);
  * Errors: ESTATE, EINVAL, ENOCONV, EHIP. */
 cbie_status cbie_solve(cbie_ctx* ctx, int nrhs, const void* b_dev, void* x_dev, long ld,
                        double ir_tol, int ir_maxit, int* ir_iters_out);
+
+/* The same system solved by GMRES-based refinement (an addition to the
+ * paper's direct solve, for operators close to a resonance where the
+ * stationary refinement of cbie_solve stops contracting): restarted GMRES in
+ * FP64 on A M y = b, x = M y, with A the stored FP64 operator and M the
+ * forward/back substitutions with the factorization (either precision) as
+ * a right preconditioner, one right-hand side at a time, starting from
+ * x = M b.  Each column stops when ||b - A x|| <= tol ||b|| (true residual,
+ * recomputed) or after maxit Krylov steps; every cycle builds at most
+ * `restart` basis vectors (device memory: restart + 2 vectors of
+ * n_unknowns complex128 per cycle).  iters_out (may be NULL) receives the
+ * Krylov steps summed over the columns.  Errors: ESTATE, EINVAL (restart
+ * <= 0, maxit < 0, tol <= 0), ENOCONV (x holds the last iterates), EHIP. */
+cbie_status cbie_solve_gmres(cbie_ctx* ctx, int nrhs, const void* b_dev, void* x_dev, long ld, double tol,
+                             int restart, int maxit, int* iters_out);
 
 /* y = A_H x with the compressed operator in FP64 arithmetic (complex128),
  * nrhs columns, original order, leading dimension ld.  Errors: ESTATE, EINVAL, EHIP. */
@@ -180,7 +204,11 @@ typedef struct {
     int64_t max_rank, sum_rank;
     double compression_rate;         /* 1 - stored / N^2 (Sec. IV-A)          */
     double t_tree, t_fill, t_compress, t_factor, t_solve;  /* seconds          */
-    int64_t factor_flops;            /* algorithmic flops of the last factor  */
+    int64_t factor_flops;            /* algorithmic flops of the last factor:
+                                        products 8 m n k, leaf LU 8/3 b^3, a
+                                        leaf triangular solve (n x n, k
+                                        columns) 4 n^2 k although it runs as a
+                                        product with the explicit inverse      */
     int64_t n_kernel_launches;       /* launches in the last factor           */
     int64_t ir_iterations;           /* sweeps of the last solve              */
     double quad_seconds;             /* near/self quadrature kernel time      */
@@ -201,6 +229,35 @@ typedef struct {
      * program recorded by the first solve with this factorization and this
      * number of right-hand sides (cumulative over the factorization) */
     int64_t solve_replays;
+    /* compress: admissible blocks whose ACA stopped at the rank cap (512),
+     * below the block's full rank min(m, n), without meeting aca_tol (last
+     * compress only; a block that reached min(m, n) is reproduced exactly) */
+    int64_t aca_unconverged;
+    /* algorithmic flops of the batched GEMM launches since create (leaf
+     * solves through explicit inverses counted as triangular solves,
+     * 4 n^2 k); gemm_flops counts what the launches execute, 8 m n k */
+    double gemm_flops_alg;
+    /* flops the last factor executed: every product at 8 m n k and every
+     * leaf at LU plus both inverses (16/3 b^3) */
+    int64_t factor_flops_executed;
+    /* batched leaf LU launches since create, their algorithmic flops
+     * (8/3 b^3 per leaf) and, with profiling on, their summed kernel time */
+    int64_t leaf_lu_launches;
+    double leaf_lu_flops;
+    double leaf_lu_seconds;
+    /* fill: quadrature points of the near/self rule summed over the pairs,
+     * and the FP64 flops of their basis contraction (per point and source
+     * node 16 for the MFIE, 64 for N-Mueller; the kernel evaluations come
+     * on top), done in quad_seconds */
+    double quad_points;
+    double quad_flops;
+    /* factor: bytes one forward/back substitution reads (explicit leaf
+     * inverses, off-diagonal dense blocks, low-rank factors, in the factor
+     * precision) */
+    double solve_factor_bytes;
+    /* fill: kernel time of the far (Fejer-rule) entries of the dense blocks,
+     * dense_entries complex128 values written */
+    double far_fill_seconds;
 } cbie_stats;
 cbie_status cbie_get_stats(cbie_ctx* ctx, void* stats_out, size_t bytes);
 
@@ -250,9 +307,10 @@ cbie_status cbie_mlp_train(void* hip_stream, float* params, const float* mean, c
                            const float* t, const int32_t* order, int64_t nsteps, int batch, float lr,
                            float* losses);
 
-/* Kernel timing: on != 0 brackets every batched GEMM launch with HIP events
- * on the context stream (their sum is reported as gemm_seconds).  Costs a
- * little host time per launch; off by default.  Errors: EINVAL, EHIP. */
+/* Kernel timing: on != 0 brackets every batched GEMM launch and every
+ * batched leaf LU launch of the factorization with HIP events on the context
+ * stream (their sums are reported as gemm_seconds and leaf_lu_seconds).
+ * Costs a little host time per launch; off by default.  Errors: EINVAL, EHIP. */
 cbie_status cbie_set_profiling(cbie_ctx* ctx, int on);
 
 /* Parity hooks (small problems; no effect on the solver state).

@@ -25,7 +25,7 @@ EXPORTED = ["cbie_create", "cbie_build_tree", "cbie_fill", "cbie_compress", "cbi
             "cbie_solve", "cbie_matvec", "cbie_rhs_planewave", "cbie_farfield", "cbie_get_stats",
             "cbie_set_profiling", "cbie_get_near_pairs", "cbie_export_dense", "cbie_last_error",
             "cbie_destroy", "cbie_get_block_features", "cbie_set_rank_model", "cbie_mlp_forward",
-            "cbie_mlp_grad", "cbie_mlp_train"]
+            "cbie_mlp_grad", "cbie_mlp_train", "cbie_solve_gmres"]
 
 MLP_NFEAT, MLP_NPARAMS = 8, 4801
 
@@ -56,7 +56,11 @@ class Stats(C.Structure):
         ("factor_flops", C.c_int64), ("n_kernel_launches", C.c_int64),
         ("ir_iterations", C.c_int64), ("quad_seconds", C.c_double),
         ("gemm_launches", C.c_int64), ("gemm_flops", C.c_double), ("gemm_seconds", C.c_double),
-        ("aca_fallbacks", C.c_int64), ("aca_workspace_bytes", C.c_double), ("solve_replays", C.c_int64)]
+        ("aca_fallbacks", C.c_int64), ("aca_workspace_bytes", C.c_double), ("solve_replays", C.c_int64),
+        ("aca_unconverged", C.c_int64), ("gemm_flops_alg", C.c_double), ("factor_flops_executed", C.c_int64),
+        ("leaf_lu_launches", C.c_int64), ("leaf_lu_flops", C.c_double), ("leaf_lu_seconds", C.c_double),
+        ("quad_points", C.c_double), ("quad_flops", C.c_double),
+        ("solve_factor_bytes", C.c_double), ("far_fill_seconds", C.c_double)]
 
 
 _lib = None
@@ -79,6 +83,7 @@ def load(path: str = LIB_PATH):
         "cbie_factor": ([vp, i32], i32),
         "cbie_solve": ([vp, i32, vp, vp, C.c_long, dbl, i32, C.POINTER(i32)], i32),
         "cbie_matvec": ([vp, i32, vp, vp, C.c_long], i32),
+        "cbie_solve_gmres": ([vp, i32, vp, vp, C.c_long, dbl, i32, i32, C.POINTER(i32)], i32),
         "cbie_rhs_planewave": ([vp, i32, vp, vp, vp, C.c_long], i32),
         "cbie_farfield": ([vp, i32, vp, C.c_long, i32, vp, vp], i32),
         "cbie_get_stats": ([vp, vp, C.c_size_t], i32),
@@ -184,6 +189,19 @@ class Solver:
         x = self.torch.empty_like(bc)
         it = C.c_int(0)
         st = self.lib.cbie_solve(self.h, bc.shape[0], _ptr(bc), _ptr(x), self.n, tol, maxit, C.byref(it))
+        if st == ENOCONV and not raise_on_noconv:
+            return x.t(), it.value
+        self._check(st)
+        return x.t(), it.value
+
+    def solve_gmres(self, b, tol=1e-10, restart=30, maxit=200, raise_on_noconv=True):
+        """GMRES-based refinement (the factorization as right preconditioner
+        of FP64 GMRES); returns (x, Krylov steps over all columns)."""
+        bc = self._cols(b)
+        x = self.torch.empty_like(bc)
+        it = C.c_int(0)
+        st = self.lib.cbie_solve_gmres(self.h, bc.shape[0], _ptr(bc), _ptr(x), self.n, tol, restart, maxit,
+                                       C.byref(it))
         if st == ENOCONV and not raise_on_noconv:
             return x.t(), it.value
         self._check(st)

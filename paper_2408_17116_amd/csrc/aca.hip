@@ -379,7 +379,7 @@ void stage_compress(Ctx& c, double tol, int mode) {
     const int nb = (int)c.lblk.size();
     CBIE_REQUIRE(mode != CBIE_RANK_PREDICTED || c.rank_model.set, CBIE_EINVAL, "predicted ranks without a rank model");
     c.aca_tol = tol;
-    ++c.lr_version;
+    c.lr_prefix.assign(nb + 1, 0);
     c.lr.u_off.assign(nb, 0);
     c.lr.v_off.assign(nb, 0);
     c.lr.rank.assign(nb, 0);
@@ -387,6 +387,7 @@ void stage_compress(Ctx& c, double tol, int mode) {
     int64_t lr_entries = 0, max_rank = 0, sum_rank = 0;
     c.stats.aca_fallbacks = 0;
     c.stats.aca_workspace_bytes = 0.0;
+    c.stats.aca_unconverged = 0;
     if (nb > 0) {
         std::vector<int> all(nb), full(nb), width(nb);
         for (int b = 0; b < nb; ++b) {
@@ -450,7 +451,10 @@ void stage_compress(Ctx& c, double tol, int mode) {
             lr_entries += (m + n) * r;
             max_rank = std::max<int64_t>(max_rank, r);
             sum_rank += r;
-            c.stats_unconverged += Q.flag[qb] ? 0 : 1;
+            // a block that stopped at its full width min(m, n) is reproduced
+            // exactly (every column interpolated); one stopped by the rank cap
+            // below that may miss the tolerance
+            c.stats.aca_unconverged += (!Q.flag[qb] && r < std::min(m, n)) ? 1 : 0;
         }
         c.lr.mem.alloc(std::max<int64_t>(so, 1));
         for (int b = 0, i = 0; b < nb; ++b)
@@ -459,6 +463,8 @@ void stage_compress(Ctx& c, double tol, int mode) {
         c.lr.d_u_off.upload(c.lr.u_off, c.stream);
         c.lr.d_v_off.upload(c.lr.v_off, c.stream);
         c.lr.d_rank.upload(c.lr.rank, c.stream);
+        for (int b = 0; b < nb; ++b) c.lr_prefix[b + 1] = c.lr_prefix[b] + c.lr.rank[b];
+        c.d_lr_prefix.upload(c.lr_prefix, c.stream);
         c.sync();
     }
     cbie_stats& st = c.stats;

@@ -62,7 +62,8 @@ cbie_status cbie_create(const cbie_object* objs, int n_objs, void* hip_stream, c
         if (ob.form == CBIE_NMULLER &&
             !(ob.eps_r > 0 && ob.mu_r > 0 && std::isfinite(ob.eps_r) && std::isfinite(ob.mu_r)))
             return CBIE_EINVAL;
-        if (!(ob.k0 > 0) || ob.q < 2 || ob.q > 8 || ob.n_patches <= 0 || !ob.patches) return CBIE_EINVAL;
+        if (!(ob.k0 > 0) || ob.q < 2 || ob.q > 11 || ob.n_patches <= 0 || !ob.patches) return CBIE_EINVAL;
+        if (ob.form == CBIE_NMULLER && ob.q > 8) return CBIE_EINVAL;
         for (int d = 0; d < 3; ++d)
             if (!(ob.axes[d] > 0)) return CBIE_EINVAL;
         for (int p = 0; p < ob.n_patches; ++p) {
@@ -78,8 +79,12 @@ cbie_status cbie_create(const cbie_object* objs, int n_objs, void* hip_stream, c
     } catch (...) {
         return CBIE_ENOMEM;
     }
+    // the context lives on the caller's current device
+    if (hipGetDevice(&ctx->c.device) != hipSuccess) {
+        delete ctx;
+        return CBIE_EHIP;
+    }
     cbie_status st = guarded(ctx, [&](Ctx& c) {
-        CBIE_HIP(hipGetDevice(&c.device));
         c.stream = (hipStream_t)hip_stream;
         int node = 0;
         for (int o = 0; o < n_objs; ++o) {
@@ -138,6 +143,7 @@ cbie_status cbie_build_tree(cbie_ctx* ctx, int leaf_size, double eta, double nea
         CBIE_REQUIRE(leaf_size >= c.upn * qmax * qmax && leaf_size <= 256 && eta > 0 && near_delta > 0,
                      CBIE_EINVAL, "leaf_size outside [unknowns of one patch, 256], eta <= 0 or near_delta <= 0");
         c.hm.reset();
+        c.state = ST_CREATED;   // a stage that fails part-way must be redone
         stage_build_tree(c, leaf_size, eta, near_delta);
         c.state = ST_TREE;
     });
@@ -148,6 +154,7 @@ cbie_status cbie_fill(cbie_ctx* ctx, int n_ang, int n_rad) {
         CBIE_REQUIRE(c.state >= ST_TREE, CBIE_ESTATE, "fill before build_tree");
         CBIE_REQUIRE(n_ang >= 0 && n_rad >= 0, CBIE_EINVAL, "negative rule size");
         c.hm.reset();
+        c.state = ST_TREE;
         stage_fill(c, n_ang, n_rad);
         c.state = ST_FILLED;
     });
@@ -159,6 +166,7 @@ cbie_status cbie_compress(cbie_ctx* ctx, double aca_tol, cbie_rank_mode mode) {
         CBIE_REQUIRE(aca_tol > 0 && aca_tol < 1, CBIE_EINVAL, "aca_tol outside (0, 1)");
         CBIE_REQUIRE(mode == CBIE_RANK_ADAPTIVE || mode == CBIE_RANK_PREDICTED, CBIE_EINVAL, "rank mode");
         c.hm.reset();
+        c.state = ST_FILLED;
         stage_compress(c, aca_tol, (int)mode);
         c.state = ST_COMPRESSED;
     });
@@ -168,6 +176,7 @@ cbie_status cbie_factor(cbie_ctx* ctx, cbie_precision prec) {
     return guarded(ctx, [&](Ctx& c) {
         CBIE_REQUIRE(c.state >= ST_COMPRESSED, CBIE_ESTATE, "factor before compress");
         CBIE_REQUIRE(prec == CBIE_PREC_C128 || prec == CBIE_PREC_C64_IR, CBIE_EINVAL, "precision");
+        c.state = ST_COMPRESSED;
         stage_factor(c, (int)prec);
         c.state = ST_FACTORED;
     });
@@ -180,6 +189,17 @@ cbie_status cbie_solve(cbie_ctx* ctx, int nrhs, const void* b_dev, void* x_dev, 
         CBIE_REQUIRE(nrhs > 0 && b_dev && x_dev && ld >= c.n_unk && b_dev != x_dev && ir_maxit >= 0,
                      CBIE_EINVAL, "solve arguments");
         stage_solve(c, nrhs, (const zd*)b_dev, (zd*)x_dev, ld, ir_tol, ir_maxit, ir_iters_out);
+    });
+}
+
+cbie_status cbie_solve_gmres(cbie_ctx* ctx, int nrhs, const void* b_dev, void* x_dev, long ld, double tol,
+                             int restart, int maxit, int* iters_out) {
+    return guarded(ctx, [&](Ctx& c) {
+        CBIE_REQUIRE(c.state >= ST_FACTORED, CBIE_ESTATE, "solve before factor");
+        CBIE_REQUIRE(nrhs > 0 && b_dev && x_dev && ld >= c.n_unk && b_dev != x_dev && restart > 0 && maxit >= 0 &&
+                         tol > 0,
+                     CBIE_EINVAL, "solve_gmres arguments");
+        stage_solve_gmres(c, nrhs, (const zd*)b_dev, (zd*)x_dev, ld, tol, restart, maxit, iters_out);
     });
 }
 
@@ -218,7 +238,7 @@ cbie_status cbie_get_stats(cbie_ctx* ctx, void* stats_out, size_t bytes) {
 }
 
 cbie_status cbie_set_profiling(cbie_ctx* ctx, int on) {
-    return guarded(ctx, [&](Ctx& c) { c.gemm_timer.on = on != 0; });
+    return guarded(ctx, [&](Ctx& c) { c.gemm_timer.on = c.leaf_timer.on = on != 0; });
 }
 
 cbie_status cbie_get_near_pairs(cbie_ctx* ctx, int64_t cap, int32_t* targets, int32_t* patches,

@@ -5,6 +5,22 @@ namespace cbie {
 
 template <typename T> __device__ inline cplx<T> bz() { return cplx<T>{(T)0, (T)0}; }
 
+// Operand pointers read from descriptors carry no address space, so their
+// loads would be flat instructions, which count against the LDS wait
+// counter as well: a wait for LDS reads would then also wait for every
+// global load in flight (the prefetch of the next slice).  These casts say
+// the memory is global.
+template <typename T> using gptr = __attribute__((address_space(1))) cplx<T>*;
+template <typename T> using gcptr = const __attribute__((address_space(1))) cplx<T>*;
+template <typename T> __device__ inline gcptr<T> as_global(const cplx<T>* p) { return (gcptr<T>)p; }
+template <typename T> __device__ inline gptr<T> as_global(cplx<T>* p) { return (gptr<T>)p; }
+template <typename T> __device__ inline cplx<T> gld(gcptr<T> p) { return cplx<T>{p->re, p->im}; }
+template <typename T> __device__ inline cplx<T> gld(gptr<T> p) { return cplx<T>{p->re, p->im}; }
+template <typename T> __device__ inline void gst(gptr<T> p, cplx<T> v) {
+    p->re = v.re;
+    p->im = v.im;
+}
+
 // ---------------------------------------------------------------- GEMM
 // Complex GEMM on the matrix cores.  A complex product is four real
 // 16x16x4 MFMAs into separate real and imaginary accumulators:
@@ -69,29 +85,41 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc<T>* __restrict__ d
     // are written to LDS, so no wait for the loads sits before the MFMAs.
     cplx<T> ra[NA], rb[NB];
     unsigned ma = 0, mb = 0;
+    // element q of a slice: operand row i (column j) and depth kk, fixed for
+    // the whole product; its offset is i ri + (k0 + kk) rk with the strides
+    // of the operand's storage order, so no branch sits in the loop
+    const gcptr<T> Ag = as_global(D.A);
+    const gcptr<T> Bg = as_global(D.B);
+    const int64_t a_ri = D.ta == 0 ? 1 : D.lda, a_rk = D.ta == 0 ? D.lda : 1;
+    const int64_t b_rj = D.tb == 0 ? D.ldb : 1, b_rk = D.tb == 0 ? 1 : D.ldb;
+    int ai[NA], ak[NA], bj[NB], bk[NB];
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+        const int e = tid + 256 * q;
+        ai[q] = D.ta == 0 ? e % BM : e / BK;
+        ak[q] = D.ta == 0 ? e / BM : e % BK;
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+        const int e = tid + 256 * q;
+        bk[q] = D.tb == 0 ? e % BK : e / BN;
+        bj[q] = D.tb == 0 ? e / BK : e % BN;
+    }
     auto load = [&](int k0) {
         ma = 0;
         mb = 0;
 #pragma unroll
         for (int q = 0; q < NA; ++q) {
-            const int e = tid + 256 * q;
-            int i, kk;
-            if (D.ta == 0) { i = e % BM; kk = e / BM; } else { kk = e % BK; i = e / BK; }
-            const int gi = m0 + i, gk = k0 + kk;
+            const int gi = m0 + ai[q], gk = k0 + ak[q];
             const bool ok = gi < m && gk < k;
-            const int64_t off = !ok ? 0 : D.ta == 0 ? gi + (int64_t)gk * D.lda : gk + (int64_t)gi * D.lda;
-            ra[q] = D.A[off];
+            ra[q] = gld<T>(Ag + (ok ? gi * a_ri + gk * a_rk : 0));
             ma |= (unsigned)ok << q;
         }
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
-            const int e = tid + 256 * q;
-            int j, kk;
-            if (D.tb == 0) { kk = e % BK; j = e / BK; } else { j = e % BN; kk = e / BN; }
-            const int gj = n0 + j, gk = k0 + kk;
+            const int gj = n0 + bj[q], gk = k0 + bk[q];
             const bool ok = gj < n && gk < k;
-            const int64_t off = !ok ? 0 : D.tb == 0 ? gk + (int64_t)gj * D.ldb : gj + (int64_t)gk * D.ldb;
-            rb[q] = D.B[off];
+            rb[q] = gld<T>(Bg + (ok ? gj * b_rj + gk * b_rk : 0));
             mb |= (unsigned)ok << q;
         }
     };
@@ -99,17 +127,13 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc<T>* __restrict__ d
         const T sa = D.ta == 2 ? (T)-1 : (T)1, sb = D.tb == 2 ? (T)-1 : (T)1;
 #pragma unroll
         for (int q = 0; q < NA; ++q) {
-            const int e = tid + 256 * q;
             const bool ok = (ma >> q) & 1u;
-            const cplx<T> v{ok ? ra[q].re : (T)0, ok ? sa * ra[q].im : (T)0};
-            if (D.ta == 0) As[buf][e / BM][e % BM] = v; else As[buf][e % BK][e / BK] = v;
+            As[buf][ak[q]][ai[q]] = cplx<T>{ok ? ra[q].re : (T)0, ok ? sa * ra[q].im : (T)0};
         }
 #pragma unroll
         for (int q = 0; q < NB; ++q) {
-            const int e = tid + 256 * q;
             const bool ok = (mb >> q) & 1u;
-            const cplx<T> v{ok ? rb[q].re : (T)0, ok ? sb * rb[q].im : (T)0};
-            if (D.tb == 0) Bs[buf][e % BK][e / BK] = v; else Bs[buf][e / BN][e % BN] = v;
+            Bs[buf][bk[q]][bj[q]] = cplx<T>{ok ? rb[q].re : (T)0, ok ? sb * rb[q].im : (T)0};
         }
     };
     load(0);
@@ -150,7 +174,7 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc<T>* __restrict__ d
     for (int j = 0; j < FN; ++j) {
         const int col = n0 + wn * WN + 16 * j + r;
         const bool cin = col < n;
-        cplx<T>* ccol = D.C + (int64_t)(cin ? col : 0) * D.ldc;
+        const gptr<T> ccol = as_global(D.C) + (int64_t)(cin ? col : 0) * D.ldc;
         cplx<T> old[FM][4];
         if (!zb) {
 #pragma unroll
@@ -158,7 +182,7 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc<T>* __restrict__ d
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const int row = m0 + wm * WM + 16 * i + Mfma<T>::row(kq, v);
-                    old[i][v] = ccol[(cin && row < m) ? row : 0];   // masked below
+                    old[i][v] = gld<T>(ccol + ((cin && row < m) ? row : 0));   // masked below
                 }
         }
 #pragma unroll
@@ -169,7 +193,7 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc<T>* __restrict__ d
                 if (!cin || row >= m) continue;
                 cplx<T> o = D.alpha * cplx<T>{cr[i][j][v], ci[i][j][v]};
                 if (!zb) cfma(o, D.beta, old[i][v]);
-                ccol[row] = o;
+                gst<T>(ccol + row, o);
             }
     }
 }
@@ -202,8 +226,11 @@ __global__ __launch_bounds__(256) void k_copy_b(const CopyDesc<T>* __restrict__ 
     for (unsigned e = (unsigned)tl.e0 + threadIdx.x; e < e1; e += 256) {
         const int i = (int)(e % m), j = (int)(e / m);
         cplx<T> v = bz<T>();
-        if (D.A) v = D.alpha * (D.trans ? D.A[j + (int64_t)i * D.lda] : D.A[i + (int64_t)j * D.lda]);
-        D.B[i + (int64_t)j * D.ldb] = v;
+        if (D.A) {
+            const gcptr<T> A = as_global(D.A);
+            v = D.alpha * gld<T>(A + (D.trans ? j + (int64_t)i * D.lda : i + (int64_t)j * D.lda));
+        }
+        gst<T>(as_global(D.B) + i + (int64_t)j * D.ldb, v);
     }
 }
 
@@ -226,12 +253,13 @@ __global__ __launch_bounds__(256) void k_reduce_b(const ReduceDesc<T>* __restric
     const bool zb = D.beta.re == (T)0 && D.beta.im == (T)0;
     for (unsigned e = (unsigned)tl.e0 + threadIdx.x; e < e1; e += 256) {
         cplx<T> acc = bz<T>();
-        for (int q = 0; q < D.nsplit; ++q) acc = acc + D.W[e + (size_t)q * tot];
+        const gcptr<T> W = as_global(D.W);
+        for (int q = 0; q < D.nsplit; ++q) acc = acc + gld<T>(W + e + (size_t)q * tot);
         const int i = (int)(e % m), j = (int)(e / m);
-        cplx<T>* cp = D.C + i + (int64_t)j * D.ldc;
+        const gptr<T> cp = as_global(D.C) + i + (int64_t)j * D.ldc;
         cplx<T> o = D.alpha * acc;
-        if (!zb) cfma(o, D.beta, *cp);
-        *cp = o;
+        if (!zb) cfma(o, D.beta, gld<T>(cp));
+        gst<T>(cp, o);
     }
 }
 template <typename T>
@@ -265,14 +293,14 @@ __global__ __launch_bounds__(256) void k_leaf_lu(const LeafDesc<T>* __restrict__
     if ((int)blockIdx.x >= nd) return;
     const LeafDesc<T> D = descs[blockIdx.x];
     const int n = D.n, lda = D.lda;
-    cplx<T>* A = D.A;
+    const gptr<T> A = as_global(D.A);
     const int tid = threadIdx.x;
     int first_zero = 0;
     for (int j0 = 0; j0 < n; j0 += NB) {
         const int jb = min(NB, n - j0), R0 = n - j0, R1 = R0 - jb;
         for (int e = tid; e < R0 * jb; e += 256) {
             const int r = e % R0, t = e / R0;
-            PT[t * NMAX + r] = A[j0 + r + (int64_t)(j0 + t) * lda];
+            PT[t * NMAX + r] = gld<T>(A + j0 + r + (int64_t)(j0 + t) * lda);
         }
         __syncthreads();
         for (int jj = 0; jj < jb; ++jj) {
@@ -346,7 +374,7 @@ __global__ __launch_bounds__(256) void k_leaf_lu(const LeafDesc<T>* __restrict__
         }
         for (int e = tid; e < R0 * jb; e += 256) {
             const int r = e % R0, t = e / R0;
-            A[j0 + r + (int64_t)(j0 + t) * lda] = PT[t * NMAX + r];
+            gst<T>(A + j0 + r + (int64_t)(j0 + t) * lda, PT[t * NMAX + r]);
         }
         if (tid < jb) D.piv[j0 + tid] = spiv[tid];
         __syncthreads();
@@ -355,10 +383,10 @@ __global__ __launch_bounds__(256) void k_leaf_lu(const LeafDesc<T>* __restrict__
             cplx<T> v[2 * NB];
 #pragma unroll
             for (int q = 0; q < 2 * NB; ++q)
-                if (src[q] >= 0) v[q] = A[src[q] + (int64_t)c * lda];
+                if (src[q] >= 0) v[q] = gld<T>(A + src[q] + (int64_t)c * lda);
 #pragma unroll
             for (int q = 0; q < 2 * NB; ++q)
-                if (src[q] >= 0) A[aff[q] + (int64_t)c * lda] = v[q];
+                if (src[q] >= 0) gst<T>(A + aff[q] + (int64_t)c * lda, v[q]);
         }
         __syncthreads();
         // U12 := L11^{-1} A12, one column per thread
@@ -367,7 +395,7 @@ __global__ __launch_bounds__(256) void k_leaf_lu(const LeafDesc<T>* __restrict__
             cplx<T> v[NB];
 #pragma unroll
             for (int t = 0; t < NB; ++t)
-                if (t < jb) v[t] = A[j0 + t + (int64_t)c * lda];
+                if (t < jb) v[t] = gld<T>(A + j0 + t + (int64_t)c * lda);
 #pragma unroll
             for (int t = 1; t < NB; ++t)
 #pragma unroll
@@ -377,7 +405,7 @@ __global__ __launch_bounds__(256) void k_leaf_lu(const LeafDesc<T>* __restrict__
             for (int t = 0; t < NB; ++t)
                 if (t < jb) {
                     S[t * NMAX + tid] = v[t];
-                    A[j0 + t + (int64_t)c * lda] = v[t];
+                    gst<T>(A + j0 + t + (int64_t)c * lda, v[t]);
                 }
         }
         __syncthreads();
@@ -397,7 +425,7 @@ __global__ __launch_bounds__(256) void k_leaf_lu(const LeafDesc<T>* __restrict__
                     for (int v = 0; v < 4; ++v) {
                         const int row = r0 + Mfma<T>::row(g, v);
                         cv[q][v] = (tile < ntt && row < R1 && col < R1)
-                                       ? A[j0 + jb + row + (int64_t)(j0 + jb + col) * lda]
+                                       ? gld<T>(A + j0 + jb + row + (int64_t)(j0 + jb + col) * lda)
                                        : bz<T>();
                     }
                 }
@@ -422,8 +450,8 @@ __global__ __launch_bounds__(256) void k_leaf_lu(const LeafDesc<T>* __restrict__
                     for (int v = 0; v < 4; ++v) {
                         const int row = r0 + Mfma<T>::row(g, v);
                         if (row < R1 && col < R1)
-                            A[j0 + jb + row + (int64_t)(j0 + jb + col) * lda] =
-                                cplx<T>{cv[q][v].re - cr[v], cv[q][v].im - ci[v]};
+                            gst<T>(A + j0 + jb + row + (int64_t)(j0 + jb + col) * lda,
+                                   cplx<T>{cv[q][v].re - cr[v], cv[q][v].im - ci[v]});
                     }
                 }
             }
@@ -452,7 +480,7 @@ __global__ __launch_bounds__(256) void k_leaf_inv(const LeafDesc<T>* __restrict_
     const LeafDesc<T> D = descs[leaf];
     const int n = D.n, lda = D.lda, c0 = chunk * CH;
     if (c0 >= n) return;
-    const cplx<T>* A = D.A;
+    const gcptr<T> A = as_global(D.A);
     const int tid = threadIdx.x, cw = min(CH, n - c0);
     for (int e = tid; e < n * CH; e += 256) X[e] = bz<T>();
     if (blockIdx.y == 0) {
@@ -462,7 +490,7 @@ __global__ __launch_bounds__(256) void k_leaf_inv(const LeafDesc<T>* __restrict_
             __syncthreads();
             for (int e = tid; e < 16 * (rows - i0); e += 256) {
                 const int r = e % 16, k = i0 + e / 16;
-                if (i0 + r < i1) B[r * NMAX + k] = A[i0 + r + (int64_t)k * lda];
+                if (i0 + r < i1) B[r * NMAX + k] = gld<T>(A + i0 + r + (int64_t)k * lda);
             }
             __syncthreads();
             for (int e = tid; e < 16 * CH; e += 256) {
@@ -485,7 +513,7 @@ __global__ __launch_bounds__(256) void k_leaf_inv(const LeafDesc<T>* __restrict_
         __syncthreads();
         for (int e = tid; e < n * cw; e += 256) {
             const int i = e % n, cc = e / n;
-            D.UI[i + (int64_t)(c0 + cc) * n] = X[i * CH + cc];
+            gst<T>(as_global(D.UI) + i + (int64_t)(c0 + cc) * n, X[i * CH + cc]);
         }
         return;
     }
@@ -504,7 +532,7 @@ __global__ __launch_bounds__(256) void k_leaf_inv(const LeafDesc<T>* __restrict_
         __syncthreads();
         for (int e = tid; e < 16 * (i1 - c0); e += 256) {
             const int r = e % 16, k = c0 + e / 16;
-            if (i0 + r < i1) B[r * NMAX + k] = A[i0 + r + (int64_t)k * lda];
+            if (i0 + r < i1) B[r * NMAX + k] = gld<T>(A + i0 + r + (int64_t)k * lda);
         }
         __syncthreads();
         for (int e = tid; e < 16 * CH; e += 256) {
@@ -527,7 +555,7 @@ __global__ __launch_bounds__(256) void k_leaf_inv(const LeafDesc<T>* __restrict_
     __syncthreads();
     for (int e = tid; e < n * cw; e += 256) {
         const int i = e % n, cc = e / n;
-        D.LP[i + (int64_t)perm[c0 + cc] * n] = X[i * CH + cc];
+        gst<T>(as_global(D.LP) + i + (int64_t)perm[c0 + cc] * n, X[i * CH + cc]);
     }
 }
 

@@ -73,16 +73,13 @@ struct Ctx {
     std::vector<DenseBlockDev> lblk;        // geometry of low-rank blocks (same layout)
     DBuf<DenseBlockDev> d_lblk;
     double aca_tol = 1e-6;
-    int64_t stats_unconverged = 0;          // ACA blocks that hit the rank cap
 
-    // matvec scratch (V^T x per low-rank block)
-    std::vector<int64_t> mv_tmp_off;
-    DBuf<int64_t> d_mv_tmp_off;
-    DBuf<zd> mv_tmp;
-    int mv_tmp_nrhs = 0;
-    // bumped whenever the low-rank ranks change (compress); the matvec
-    // scratch layout above is valid for one version only
-    int64_t lr_version = 0, mv_tmp_version = -1;
+    // exclusive prefix sums of the low-rank ranks (nl + 1 entries, set by
+    // compress): block b's V^T x occupies rows prefix[b] * nrhs .. of the
+    // matvec scratch
+    std::vector<int64_t> lr_prefix;
+    DBuf<int64_t> d_lr_prefix;
+    DBuf<zd> mv_tmp;                        // matvec scratch of the allocating path
 
     // factorization
     std::shared_ptr<HMat> hm;   // type-erased deleter: HMat stays incomplete here
@@ -109,7 +106,7 @@ struct Ctx {
         void end(hipStream_t s);
         void harvest();
         ~KernelTimer();
-    } gemm_timer;
+    } gemm_timer, leaf_timer;
 
     Ctx();
     ~Ctx();
@@ -122,6 +119,8 @@ void stage_fill(Ctx& c, int n_ang, int n_rad);
 void stage_compress(Ctx& c, double tol, int mode);
 void stage_factor(Ctx& c, int prec);
 void stage_solve(Ctx& c, int nrhs, const zd* b, zd* x, long ld, double tol, int maxit, int* iters);
+void stage_solve_gmres(Ctx& c, int nrhs, const zd* b, zd* x, long ld, double tol, int restart, int maxit,
+                       int* iters);
 void stage_matvec(Ctx& c, int nrhs, const zd* x, zd* y, long ld);
 void stage_export_dense(Ctx& c, zd* A, long ld);
 void stage_rhs(Ctx& c, int nw, const double* khat, const double* pol, zd* b, long ld);

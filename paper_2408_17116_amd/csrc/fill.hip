@@ -236,18 +236,25 @@ __device__ inline void quad_point(const double (*tri)[6], int nt, int nr, int se
     wgt = wt * ws * s * fabs(a * b);
 }
 
-struct QuadPointLDS {
-    double kw[256][8];   // w K (4 complex) per point
-    double lu[256][8];
-    double lv[256][8];
+// Point tile of k_quad: w K (4 complex) and the two interpolation bases of
+// every point (QM: the largest order the instance handles).
+template <int QM> struct QuadPointLDS {
+    double kw[256][8];
+    double lu[256][QM];
+    double lv[256][QM];
 };
 
+// QM = 8: lane kl of each wave owns node kl (q^2 <= 64).  QM = 11: lane kl
+// owns nodes kl and kl + 64 (q^2 <= 121, up to 242 unknowns per patch, the
+// most a 256-unknown leaf holds).
+template <int QM>
 __global__ __launch_bounds__(256) void k_quad(
     const PatchDev* __restrict__ patches, const ObjDev* __restrict__ objs, NodeArrays nd,
     const NearPair* __restrict__ pairs, int64_t n_pairs, const double* __restrict__ fej11_x,
     const double* __restrict__ fej_x, const double* __restrict__ fej_w, QuadRule rule,
     int64_t stride, zd* __restrict__ out) {
-    __shared__ QuadPointLDS S;
+    constexpr int NPL = (QM * QM + 63) / 64;   // nodes per lane
+    __shared__ QuadPointLDS<QM> S;
     __shared__ double s_tri[8][6];   // per triangle: a, b, L1/L2, hi, kind(0/1), valid
     __shared__ int s_ntri;
     const int64_t pid = blockIdx.x;
@@ -263,7 +270,7 @@ __global__ __launch_bounds__(256) void k_quad(
     const double us = E.us, vs = E.vs;
     const double* xq = fej11_x + q * (q - 1) / 2;   // the patch's own Chebyshev points
     const int tid = threadIdx.x;
-    double lam[8];
+    double lam[QM];
     bary_weights(q, lam);
 
     if (tid == 0) s_ntri = quad_triangles(us, vs, s_tri);
@@ -274,18 +281,31 @@ __global__ __launch_bounds__(256) void k_quad(
     const int nr = E.self ? rule.n_rad : (rule.n_in + rule.n_out);
     const int64_t npts = (int64_t)ntri * nt * nr;
 
-    // output ownership: lane (k, l), every (b, a), a quarter of the points
+    // output ownership: lane (k, l) (and (k, l) + 64), every (b, a), a
+    // quarter of the points
     const int q2 = q * q;
     const int wave = tid >> 6, kl = tid & 63;
-    const bool owner = kl < q2;
-    const int ok = owner ? kl / q : 0, ol = owner ? kl % q : 0;
-    double acc[8] = {0, 0, 0, 0, 0, 0, 0, 0};   // (re, im) for ba = 0..3
+    int ok[NPL], ol[NPL];
+    bool owner[NPL];
+#pragma unroll
+    for (int h = 0; h < NPL; ++h) {
+        const int nn = kl + 64 * h;
+        owner[h] = nn < q2;
+        ok[h] = owner[h] ? nn / q : 0;
+        ol[h] = owner[h] ? nn % q : 0;
+    }
+    double acc[NPL][8];   // (re, im) for ba = 0..3
+#pragma unroll
+    for (int h = 0; h < NPL; ++h)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) acc[h][c] = 0.0;
 
     for (int64_t base = 0; base < npts; base += 256) {
         const int64_t pidx = base + tid;
         double kw[8];
-        double Lu[8], Lv[8];
-        for (int c = 0; c < 8; ++c) { kw[c] = 0.0; Lu[c] = 0.0; Lv[c] = 0.0; }
+        double Lu[QM], Lv[QM];
+        for (int c = 0; c < 8; ++c) kw[c] = 0.0;
+        for (int c = 0; c < QM; ++c) { Lu[c] = 0.0; Lv[c] = 0.0; }
         if (pidx < npts) {
             double du, dv, wgt;
             quad_point(s_tri, nt, nr, E.self, dpar, rule, fej_x, fej_w, pidx, du, dv, wgt);
@@ -303,30 +323,35 @@ __global__ __launch_bounds__(256) void k_quad(
             lagrange(q, xq, lam, v, Lv);
         }
         __syncthreads();
-        for (int c = 0; c < 8; ++c) {
-            S.kw[tid][c] = kw[c];
+        for (int c = 0; c < 8; ++c) S.kw[tid][c] = kw[c];
+        for (int c = 0; c < QM; ++c) {
             S.lu[tid][c] = Lu[c];
             S.lv[tid][c] = Lv[c];
         }
         __syncthreads();
-        if (owner) {
-            const int cnt = (int)min((int64_t)256, npts - base);
-            for (int pnt = wave; pnt < cnt; pnt += 4) {
-                const double bb = S.lv[pnt][ok] * S.lu[pnt][ol];
+        const int cnt = (int)min((int64_t)256, npts - base);
 #pragma unroll
-                for (int c = 0; c < 8; ++c) acc[c] = fma(S.kw[pnt][c], bb, acc[c]);
+        for (int h = 0; h < NPL; ++h) {
+            if (!owner[h]) continue;
+            for (int pnt = wave; pnt < cnt; pnt += 4) {
+                const double bb = S.lv[pnt][ok[h]] * S.lu[pnt][ol[h]];
+#pragma unroll
+                for (int c = 0; c < 8; ++c) acc[h][c] = fma(S.kw[pnt][c], bb, acc[h][c]);
             }
         }
     }
     // sum the four waves' partials (the point tile is no longer needed)
     __syncthreads();
-    double (*red)[64][8] = reinterpret_cast<double (*)[64][8]>(&S.kw[0][0]);   // [wave][lane][8]
+    double (*red)[64 * NPL][8] = reinterpret_cast<double (*)[64 * NPL][8]>(&S.kw[0][0]);   // [wave][node][8]
+    static_assert(sizeof(double) * 4 * 64 * NPL * 8 <= sizeof(QuadPointLDS<QM>), "reduction buffer");
 #pragma unroll
-    for (int c = 0; c < 8; ++c) red[wave][kl][c] = acc[c];
+    for (int h = 0; h < NPL; ++h)
+#pragma unroll
+        for (int c = 0; c < 8; ++c) red[wave][kl + 64 * h][c] = acc[h][c];
     __syncthreads();
-    if (tid < 4 * q2) {
+    for (int o = tid; o < 4 * q2; o += 256) {
         // thread -> (ba, kl2): output (b, a) of node kl2
-        const int ba = tid / q2, kl2 = tid % q2;
+        const int ba = o / q2, kl2 = o % q2;
         const int b = ba >> 1, a = ba & 1;
         double re = 0.0, im = 0.0;
         for (int w = 0; w < 4; ++w) {
@@ -338,6 +363,10 @@ __global__ __launch_bounds__(256) void k_quad(
         out[pid * stride + ((int64_t)b * q2 + kl2) * 2 + a] = zd{re, im};
     }
 }
+template __global__ void k_quad<8>(const PatchDev*, const ObjDev*, NodeArrays, const NearPair*, int64_t,
+                                   const double*, const double*, const double*, QuadRule, int64_t, zd*);
+template __global__ void k_quad<11>(const PatchDev*, const ObjDev*, NodeArrays, const NearPair*, int64_t,
+                                    const double*, const double*, const double*, QuadRule, int64_t, zd*);
 
 // ------------------------------------------------------------- far fill
 // Dense block tile: 64 row nodes x 16 column nodes per work-group; thread

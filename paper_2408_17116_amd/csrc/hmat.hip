@@ -24,12 +24,15 @@
 #include <cstdio>
 #include <cstring>
 #include <functional>
+#include <type_traits>
 #include <memory>
 #include <unordered_map>
 
 #include "batch.hpp"
 #include "ctx.hpp"
 #include "linalg.hpp"
+#include "gmres.hpp"
+#include "refine.hpp"
 #include "ops.hpp"
 #include "pool.hpp"
 
@@ -258,7 +261,11 @@ template <typename T> struct HF {
     int pin = 0;               // > 0: recorded temporaries are still referenced
     DBuf<AcaProdJob<T>> jobbuf;
     int64_t launches = 0;
-    double flops = 0.0;
+    // flops: every launched product at 8 m n k and every leaf at its LU plus
+    // inverses (16/3 b^3); alg_flops: the algorithmic count, a leaf solve
+    // through an explicit inverse at 4 n^2 k (a triangular solve with an
+    // n x n triangle and k right-hand sides) and a leaf LU at 8/3 b^3
+    double flops = 0.0, alg_flops = 0.0;
     // accumulated width that triggers recompression (tuning: CBIE_KMAX)
     int kmax = getenv("CBIE_KMAX") ? std::max(64, atoi(getenv("CBIE_KMAX"))) : 3072;
     bool debug = getenv("CBIE_DEBUG") != nullptr;
@@ -276,6 +283,7 @@ template <typename T> struct HF {
     std::vector<int64_t> gseq, cseq, lseq;   // recording order
     int64_t seq = 0;
     std::vector<int> gshape;            // forced tile shape or -1
+    std::vector<double> galg;           // algorithmic flops of each recorded product
     // per owner: rectangles with the last level that wrote or read them
     struct Ent {
         int64_t r0, r1, c0, c1;
@@ -368,7 +376,7 @@ template <typename T> struct HF {
     // products need full-height or full-width tiles)
     void rec_gemm(int ta, int tb, int m, int n, int k, cplx<T> al, const cplx<T>* A, int lda, const cplx<T>* B,
                   int ldb, cplx<T> be, cplx<T>* C, int ldc, const std::vector<Res>& rd, const std::vector<Res>& wr,
-                  int shape = -1) {
+                  int shape = -1, double alg = -1.0) {
         if (m <= 0 || n <= 0) return;
         const bool b0 = be.re == (T)0 && be.im == (T)0, b1 = be.re == (T)1 && be.im == (T)0;
         if (k <= 0) {
@@ -384,6 +392,8 @@ template <typename T> struct HF {
         gseq.push_back(seq++);
         gd.push_back(g);
         flops += 8.0 * m * n * k;
+        galg.push_back(alg >= 0.0 ? alg : 8.0 * m * n * k);
+        alg_flops += galg.back();
     }
     void rec_copy(int trans, int m, int n, cplx<T> al, const cplx<T>* A, int lda, cplx<T>* B, int ldb,
                   const std::vector<Res>& rd, const std::vector<Res>& wr) {
@@ -403,6 +413,7 @@ template <typename T> struct HF {
         llev.push_back(level_of({r}, {r}));
         lseq.push_back(seq++);
         flops += 16.0 / 3.0 * (double)db.ld * db.ld * db.ld;
+        alg_flops += 8.0 / 3.0 * (double)db.ld * db.ld * db.ld;
     }
 
     // tile shape with the least padding; the square tile on ties
@@ -445,7 +456,7 @@ template <typename T> struct HF {
     struct Batch {
         std::vector<GemmDesc<T>> g[kNumTileShapes];
         std::vector<GemmTile> t[kNumTileShapes];
-        double fl[kNumTileShapes] = {};
+        double fl[kNumTileShapes] = {}, alg[kNumTileShapes] = {};
         std::vector<ReduceDesc<T>> rd;
         std::vector<CopyTile> rt;
         int64_t ws_left = int64_t(1) << 26;   // partial-product entries one launch may use
@@ -456,7 +467,9 @@ template <typename T> struct HF {
     double hist_fl[Tuner<T>::NM][Tuner<T>::NM][Tuner<T>::NK] = {};
     int64_t hist_n[Tuner<T>::NM][Tuner<T>::NM][Tuner<T>::NK] = {};
     int64_t hist_split = 0;
-    void add_gemm(Batch& b, const GemmDesc<T>& d, int sh, bool forced, int64_t launch_tiles, Arena<T>& ws) {
+    void add_gemm(Batch& b, const GemmDesc<T>& d, int sh, bool forced, int64_t launch_tiles, Arena<T>& ws,
+                  double alg = -1.0) {
+        const double a = alg >= 0.0 ? alg : 8.0 * d.m * d.n * d.k;
         if (debug) {
             hist_fl[Tuner<T>::mb(d.m)][Tuner<T>::mb(d.n)][Tuner<T>::kb(d.k)] += 8.0 * d.m * d.n * d.k;
             ++hist_n[Tuner<T>::mb(d.m)][Tuner<T>::mb(d.n)][Tuner<T>::kb(d.k)];
@@ -466,12 +479,14 @@ template <typename T> struct HF {
         if ((int64_t)S * d.m * d.n > b.ws_left) S = 1;
         if (S <= 1) {
             b.fl[sh] += 8.0 * d.m * d.n * d.k;
+            b.alg[sh] += a;
             add_tiles(b.t[sh], (int)b.g[sh].size(), d, sh);
             b.g[sh].push_back(d);
             return;
         }
         if (forced) sh = pick_shape(d.m, d.n, d.k);
         b.fl[sh] += 8.0 * d.m * d.n * d.k;
+        b.alg[sh] += a;
         const int64_t mn = (int64_t)d.m * d.n;
         b.ws_left -= mn * S;
         cplx<T>* W = ws.alloc((size_t)(mn * S));
@@ -550,8 +565,9 @@ template <typename T> struct HF {
         ++replays;
     }
 
-    // one batched GEMM launch of algorithmic flops fl, timed when profiling
-    void launch_gemm(const GemmDesc<T>* d, const GemmTile* t, int ntiles, int sh, double fl) {
+    // one batched GEMM launch of fl flops (8 m n k per product) standing for
+    // alg algorithmic flops, timed when profiling
+    void launch_gemm(const GemmDesc<T>* d, const GemmTile* t, int ntiles, int sh, double fl, double alg) {
         Ctx::KernelTimer& tm = c.gemm_timer;
         if (tm.on) tm.begin(s);
         gemm_batched<T>(s, d, t, ntiles, sh);
@@ -559,6 +575,7 @@ template <typename T> struct HF {
         ++launches;
         ++c.stats.gemm_launches;
         c.stats.gemm_flops += fl;
+        c.stats.gemm_flops_alg += alg;
     }
 
     // Dependency audit (CBIE_CHECK_DEPS).  From the memory each recorded
@@ -654,8 +671,9 @@ template <typename T> struct HF {
         // tiles], then [copy descs][copy tiles][leaf descs]
         struct Seg {
             size_t g[kNumTileShapes], gt[kNumTileShapes], r, rt, c, ct, l;
+            double lfl;   // algorithmic flops of the level's leaf LUs (8/3 b^3 each)
             int ng[kNumTileShapes], ngt[kNumTileShapes], nr, nrt, nc, nct, nl;
-            double fl[kNumTileShapes];
+            double fl[kNumTileShapes], alg[kNumTileShapes];
         };
         // the program that last used this workspace finished before the
         // previous program was staged
@@ -678,7 +696,7 @@ template <typename T> struct HF {
                 lt += ntiles(gd[i], gshape[i] >= 0 ? gshape[i] : pick_shape(gd[i].m, gd[i].n, gd[i].k));
             for (int i : gl[lv]) {
                 const GemmDesc<T>& d = gd[i];
-                add_gemm(bt, d, gshape[i] >= 0 ? gshape[i] : pick_shape(d.m, d.n, d.k), gshape[i] >= 0, lt, ws);
+                add_gemm(bt, d, gshape[i] >= 0 ? gshape[i] : pick_shape(d.m, d.n, d.k), gshape[i] >= 0, lt, ws, galg[i]);
             }
             for (int sh = 0; sh < kNumTileShapes; ++sh) {
                 sg.g[sh] = put(bt.g[sh].data(), bt.g[sh].size() * sizeof(GemmDesc<T>));
@@ -686,6 +704,7 @@ template <typename T> struct HF {
                 sg.ng[sh] = (int)bt.g[sh].size();
                 sg.ngt[sh] = (int)bt.t[sh].size();
                 sg.fl[sh] = bt.fl[sh];
+                sg.alg[sh] = bt.alg[sh];
             }
             sg.r = put(bt.rd.data(), bt.rd.size() * sizeof(ReduceDesc<T>));
             sg.rt = put(bt.rt.data(), bt.rt.size() * sizeof(CopyTile));
@@ -700,7 +719,11 @@ template <typename T> struct HF {
                 for (int64_t e0 = 0; e0 < (int64_t)d.m * d.n; e0 += kCopyChunk) ct.push_back(CopyTile{di, (int)e0});
             }
             std::vector<LeafDesc<T>> lf;
-            for (int i : ll[lv]) lf.push_back(ld[i]);
+            sg.lfl = 0.0;
+            for (int i : ll[lv]) {
+                lf.push_back(ld[i]);
+                sg.lfl += 8.0 / 3.0 * (double)ld[i].n * ld[i].n * ld[i].n;
+            }
             sg.c = put(cc.data(), cc.size() * sizeof(CopyDesc<T>));
             sg.ct = put(ct.data(), ct.size() * sizeof(CopyTile));
             sg.l = put(lf.data(), lf.size() * sizeof(LeafDesc<T>));
@@ -727,7 +750,12 @@ template <typename T> struct HF {
             if (sg.nl) {
                 const LeafDesc<T>* dl = (const LeafDesc<T>*)(dev.p + sg.l);
                 const int n = sg.nl;
+                Ctx::KernelTimer& tm = c.leaf_timer;
+                if (tm.on) tm.begin(s);
                 leaf_batched<T>(s, dl, n);
+                if (tm.on) tm.end(s);
+                ++c.stats.leaf_lu_launches;
+                c.stats.leaf_lu_flops += sg.lfl;
                 keep([=](hipStream_t st) { leaf_batched<T>(st, dl, n); });
                 ++launches;
             }
@@ -736,7 +764,7 @@ template <typename T> struct HF {
                     const GemmDesc<T>* dg = (const GemmDesc<T>*)(dev.p + sg.g[sh]);
                     const GemmTile* dt = (const GemmTile*)(dev.p + sg.gt[sh]);
                     const int nt = sg.ngt[sh];
-                    launch_gemm(dg, dt, nt, sh, sg.fl[sh]);
+                    launch_gemm(dg, dt, nt, sh, sg.fl[sh], sg.alg[sh]);
                     keep([=](hipStream_t st) { gemm_batched<T>(st, dg, dt, nt, sh); });
                 }
             if (sg.nrt) {
@@ -758,7 +786,7 @@ template <typename T> struct HF {
         }
         levels_run += L;
         store.launched();
-        gd.clear(); glev.clear(); gshape.clear(); gseq.clear();
+        gd.clear(); glev.clear(); gshape.clear(); gseq.clear(); galg.clear();
         cd.clear(); clev.clear(); ld.clear(); llev.clear(); cseq.clear(); lseq.clear();
         st.clear();
         max_level = -1;
@@ -833,11 +861,12 @@ template <typename T> struct HF {
         for (int sh = 0; sh < kNumTileShapes; ++sh) {
             if (bt.t[sh].empty()) continue;
             flops += bt.fl[sh];
+            alg_flops += bt.alg[sh];
             const GemmDesc<T>* dg = stage_upload(bt.g[sh]);
             const GemmTile* dt = stage_upload(bt.t[sh]);
             const int nt = (int)bt.t[sh].size();
-            const double fl = bt.fl[sh];
-            launch([=] { launch_gemm(dg, dt, nt, sh, fl); });
+            const double fl = bt.fl[sh], al = bt.alg[sh];
+            launch([=] { launch_gemm(dg, dt, nt, sh, fl, al); });
         }
         if (!bt.rt.empty()) {
             const ReduceDesc<T>* dr = stage_upload(bt.rd);
@@ -1508,14 +1537,15 @@ template <typename T> struct HF {
         const cplx<T>* LP = inv.p + inv_off[leaf];
         const cplx<T>* UI = LP + (int64_t)n * n;
         const std::vector<Res> rd = cat({rx, {Res{RES_DENSE, leaf}}});
+        const double alg = 4.0 * n * n * k;   // the triangular solve this product stands for
         if (inplace_solve) {
             // full-height / full-width tiles: each tile reads the rows or
             // columns of X it overwrites
             if (which == 'R') {
-                rec_gemm(0, 0, k, n, n, one(), X, ldx, UI, n, zero(), X, ldx, rd, rx, kTile32x256);
+                rec_gemm(0, 0, k, n, n, one(), X, ldx, UI, n, zero(), X, ldx, rd, rx, kTile32x256, alg);
             } else {
                 const int ta = which == 'T' ? 1 : 0;
-                rec_gemm(ta, 0, n, k, n, one(), which == 'L' ? LP : UI, n, X, ldx, zero(), X, ldx, rd, rx, kTile256x32);
+                rec_gemm(ta, 0, n, k, n, one(), which == 'L' ? LP : UI, n, X, ldx, zero(), X, ldx, rd, rx, kTile256x32, alg);
             }
             return;
         }
@@ -1525,10 +1555,10 @@ template <typename T> struct HF {
         cplx<T>* Tp = scratch.alloc((size_t)tm * tn);
         const Res tr = rect(RES_TEMP, temp().id, 0, tm, 0, tn);
         if (which == 'R') {
-            rec_gemm(0, 0, k, n, n, one(), X, ldx, UI, n, zero(), Tp, tm, rd, {tr});
+            rec_gemm(0, 0, k, n, n, one(), X, ldx, UI, n, zero(), Tp, tm, rd, {tr}, -1, alg);
         } else {
             const int ta = which == 'T' ? 1 : 0;
-            rec_gemm(ta, 0, n, k, n, one(), which == 'L' ? LP : UI, n, X, ldx, zero(), Tp, tm, rd, {tr});
+            rec_gemm(ta, 0, n, k, n, one(), which == 'L' ? LP : UI, n, X, ldx, zero(), Tp, tm, rd, {tr}, -1, alg);
         }
         rec_copy(0, tm, tn, one(), Tp, tm, X, ldx, {tr}, rx);
     }
@@ -1811,10 +1841,13 @@ template <typename T> static void run_factor(Ctx& c, HF<T>& f) {
         CBIE_REQUIRE(info[b] == 0, CBIE_ESINGULAR, "zero pivot in diagonal leaf " + std::to_string(b));
     CBIE_REQUIRE(f.audit_conflicts == 0, -7,
                  "dependency audit: " + std::to_string(f.audit_conflicts) + " conflicting task pairs in one level");
-    c.stats.factor_flops = (int64_t)f.flops;
+    c.stats.factor_flops = (int64_t)f.alg_flops;
+    c.stats.factor_flops_executed = (int64_t)f.flops;
     c.stats.n_kernel_launches = f.launches;
     c.gemm_timer.harvest();
     c.stats.gemm_seconds = c.gemm_timer.seconds;
+    c.leaf_timer.harvest();
+    c.stats.leaf_lu_seconds = c.leaf_timer.seconds;
     if (getenv("CBIE_DEBUG"))
         fprintf(stderr,
                 "[cbie] levels %lld flushes %lld (width overflows %lld) rounds %lld widths lrA %.0f lrB %.0f dd %.0f flushK %.0f; "
@@ -1844,6 +1877,21 @@ void stage_factor(Ctx& c, int prec) {
         run_factor(c, *hm->f32);
     }
     c.hm = hm;
+    // bytes one substitution reads (eqs. 26-28): the explicit leaf inverses,
+    // the off-diagonal dense blocks and the final low-rank factors
+    auto subst_bytes = [&](auto& f) {
+        using E = typename std::remove_reference<decltype(*f.dense.p)>::type;
+        double el = 0.0;
+        for (const auto& L : f.lr) el += (double)(L.m + L.n) * L.r;
+        const Tree& T_ = c.tree;
+        for (size_t b = 0; b < T_.dense_blocks.size(); ++b) {
+            const Block& B = T_.blocks[T_.dense_blocks[b]];
+            const double e = (double)c.upn * c.dblk[b].row_nodes * c.upn * c.dblk[b].col_nodes;
+            el += B.t == B.s ? 2.0 * e : e;   // diagonal leaf: L^{-1} P and U^{-1}
+        }
+        return el * sizeof(E);
+    };
+    c.stats.solve_factor_bytes = prec == CBIE_PREC_C128 ? subst_bytes(*hm->f64) : subst_bytes(*hm->f32);
     c.stats.t_factor = now_s() - t0;
 }
 
@@ -1958,23 +2006,36 @@ void stage_solve(Ctx& c, int nrhs, const zd* b, zd* x, long ld, double tol, int 
         }
     };
     correction(bt.p, xt.p);
-    int it = 0;
-    bool ok = (maxit == 0);
-    for (; it < maxit; ++it) {
-        apply_operator_tree(c, nrhs, xt.p, rt.p);
-        k_axpy_sub<<<g, 256, 0, s>>>(NN, bt.p, rt.p);
-        check_launch("k_axpy_sub");
-        k_colnorm2<<<nrhs, 256, 0, s>>>(N, nrhs, rt.p, nrm.p);
-        check_launch("k_colnorm2");
-        nrm.download(hn.data(), hn.size(), s);
-        c.sync();
-        double worst = 0.0;
-        for (int r = 0; r < nrhs; ++r) worst = std::max(worst, std::sqrt(hn[r] / std::max(hn[nrhs + r], 1e-300)));
-        if (worst <= tol) { ok = true; break; }
-        correction(rt.p, rt.p);
-        k_add<<<g, 256, 0, s>>>(NN, rt.p, xt.p);
-        check_launch("k_add");
-    }
+    struct Ops {
+        Ctx& c;
+        int nrhs;
+        const zd* bt;
+        zd *xt, *rt;
+        double* nrm;
+        std::vector<double>& hn;
+        decltype(correction)& corr;
+        void ratios(std::vector<double>& q) {
+            const int64_t NN = c.n_unk * nrhs;
+            const unsigned g = ceil_div(NN, 256);
+            apply_operator_tree(c, nrhs, xt, rt);
+            k_axpy_sub<<<g, 256, 0, c.stream>>>(NN, bt, rt);
+            check_launch("k_axpy_sub");
+            k_colnorm2<<<nrhs, 256, 0, c.stream>>>(c.n_unk, nrhs, rt, nrm);
+            check_launch("k_colnorm2");
+            CBIE_HIP(hipMemcpyAsync(hn.data(), nrm, sizeof(double) * hn.size(), hipMemcpyDeviceToHost, c.stream));
+            c.sync();
+            q.resize(nrhs);
+            for (int r = 0; r < nrhs; ++r) q[r] = std::sqrt(hn[r] / std::max(hn[nrhs + r], 1e-300));
+        }
+        void correct() {
+            const int64_t NN = c.n_unk * nrhs;
+            corr(rt, rt);
+            k_add<<<ceil_div(NN, 256), 256, 0, c.stream>>>(NN, rt, xt);
+            check_launch("k_add");
+        }
+    } ops{c, nrhs, bt.p, xt.p, rt.p, nrm.p, hn, correction};
+    const RefineResult rr = refine(ops, tol, maxit);
+    const int it = rr.corrections;
     k_from_tree<double><<<g, 256, 0, s>>>(c.d_tree_node.p, c.upn, N, nrhs, xt.p, x, ld);
     check_launch("k_from_tree");
     c.sync();
@@ -1984,7 +2045,122 @@ void stage_solve(Ctx& c, int nrhs, const zd* b, zd* x, long ld, double tol, int 
     c.stats.ir_iterations = it;
     c.stats.solve_replays = c.hm->prec == CBIE_PREC_C128 ? c.hm->f64->replays : c.hm->f32->replays;
     c.stats.t_solve = now_s() - t0;
-    CBIE_REQUIRE(ok, CBIE_ENOCONV, "iterative refinement did not reach the tolerance");
+    CBIE_REQUIRE(!rr.nonfinite, CBIE_ENOCONV, "iterative refinement: non-finite residual (factorization overflow or NaN)");
+    CBIE_REQUIRE(rr.converged, CBIE_ENOCONV, "iterative refinement did not reach the tolerance");
+}
+
+// ------------------------------------------------------------ GMRES-IR
+// x^H y of two device vectors into out[0..1] (one work-group)
+__global__ __launch_bounds__(1024) void k_zdotc(int64_t n, const zd* __restrict__ x, const zd* __restrict__ y,
+                                                double* __restrict__ out) {
+    double sr = 0.0, si = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) {
+        const zd a = x[i], b = y[i];
+        sr += a.re * b.re + a.im * b.im;
+        si += a.re * b.im - a.im * b.re;
+    }
+    for (int off = 32; off > 0; off >>= 1) { sr += __shfl_xor(sr, off); si += __shfl_xor(si, off); }
+    __shared__ double sh[2][16];
+    if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = sr; sh[1][threadIdx.x >> 6] = si; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double a = 0.0, b = 0.0;
+        for (int w = 0; w < 16; ++w) { a += sh[0][w]; b += sh[1][w]; }
+        out[0] = a;
+        out[1] = b;
+    }
+}
+__global__ void k_zaxpy(int64_t n, double ar, double ai, const zd* __restrict__ x, zd* __restrict__ y) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e < n) y[e] = zd{y[e].re + ar * x[e].re - ai * x[e].im, y[e].im + ar * x[e].im + ai * x[e].re};
+}
+__global__ void k_zfill0(int64_t n, zd* __restrict__ x) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e < n) x[e] = zd{0.0, 0.0};
+}
+__global__ void k_zscal(int64_t n, double ar, double ai, zd* __restrict__ x) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e < n) x[e] = zd{ar * x[e].re - ai * x[e].im, ar * x[e].im + ai * x[e].re};
+}
+
+// Restarted GMRES in FP64 on A M y = b, x = M y (gmres.hpp), one
+// right-hand side at a time: A is the stored operator (FP64 H-matvec), M
+// the substitutions with the factorization (replayed graph, one column).
+// The starting iterate is x = M b.
+void stage_solve_gmres(Ctx& c, int nrhs, const zd* b, zd* x, long ld, double tol, int restart, int maxit,
+                       int* iters) {
+    const double t0 = now_s();
+    CBIE_REQUIRE(c.hm, CBIE_ESTATE, "no factorization");
+    const int64_t N = c.n_unk;
+    hipStream_t s = c.stream;
+    const unsigned g = ceil_div(N, 256);
+    DBuf<double> red;
+    red.alloc(2);
+    struct Ops {
+        Ctx& c;
+        int64_t N;
+        unsigned g;
+        double* red;
+        using Vec = DBuf<zd>;
+        Vec make() {
+            Vec v;
+            v.alloc(N);
+            k_zfill0<<<g, 256, 0, c.stream>>>(N, v.p);
+            check_launch("k_zfill0");
+            return v;
+        }
+        void apply(const Vec& v, Vec& y) { apply_operator_tree(c, 1, v.p, y.p); }
+        void precond(const Vec& r, Vec& z) {
+            if (c.hm->prec == CBIE_PREC_C128) lu_solve_replay(c, *c.hm->f64, 1, r.p, z.p);
+            else lu_solve_replay(c, *c.hm->f32, 1, r.p, z.p);
+        }
+        std::complex<double> dot(const Vec& u, const Vec& v) {
+            k_zdotc<<<1, 1024, 0, c.stream>>>(N, u.p, v.p, red);
+            check_launch("k_zdotc");
+            double h[2];
+            CBIE_HIP(hipMemcpyAsync(h, red, sizeof(h), hipMemcpyDeviceToHost, c.stream));
+            c.sync();
+            return {h[0], h[1]};
+        }
+        double nrm2(const Vec& u) { return std::sqrt(std::max(dot(u, u).real(), 0.0)); }
+        void axpy(std::complex<double> a, const Vec& u, Vec& y) {
+            k_zaxpy<<<g, 256, 0, c.stream>>>(N, a.real(), a.imag(), u.p, y.p);
+            check_launch("k_zaxpy");
+        }
+        void scal(std::complex<double> a, Vec& u) {
+            k_zscal<<<g, 256, 0, c.stream>>>(N, a.real(), a.imag(), u.p);
+            check_launch("k_zscal");
+        }
+        void copy(const Vec& u, Vec& y) {
+            CBIE_HIP(hipMemcpyAsync(y.p, u.p, sizeof(zd) * N, hipMemcpyDeviceToDevice, c.stream));
+        }
+    } ops{c, N, g, red.p};
+    DBuf<zd> bcol, xcol;
+    bcol.alloc(N);
+    xcol.alloc(N);
+    int total = 0;
+    bool ok = true, finite = true;
+    double worst = 0.0;
+    for (int r = 0; r < nrhs; ++r) {
+        k_to_tree<double><<<g, 256, 0, s>>>(c.d_tree_node.p, c.upn, N, 1, b + (int64_t)r * ld, ld, bcol.p);
+        check_launch("k_to_tree");
+        ops.precond(bcol, xcol);
+        const GmresResult res = gmres_ir(ops, bcol, xcol, tol, restart, maxit);
+        total += res.iterations;
+        if (!std::isfinite(res.rel_residual)) finite = false;
+        ok = ok && res.converged;
+        worst = std::max(worst, res.rel_residual);
+        k_from_tree<double><<<g, 256, 0, s>>>(c.d_tree_node.p, c.upn, N, 1, xcol.p, x + (int64_t)r * ld, ld);
+        check_launch("k_from_tree");
+    }
+    c.sync();
+    if (iters) *iters = total;
+    c.stats.ir_iterations = total;
+    c.stats.solve_replays = c.hm->prec == CBIE_PREC_C128 ? c.hm->f64->replays : c.hm->f32->replays;
+    c.stats.t_solve = now_s() - t0;
+    CBIE_REQUIRE(finite, CBIE_ENOCONV, "GMRES refinement: non-finite residual (factorization overflow or NaN)");
+    CBIE_REQUIRE(ok, CBIE_ENOCONV, "GMRES refinement did not reach the tolerance (worst relative residual " +
+                                       std::to_string(worst) + ")");
 }
 
 }  // namespace cbie

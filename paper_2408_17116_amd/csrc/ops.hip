@@ -2,6 +2,9 @@
 // plane-wave right-hand sides (eq. 22) and the far field of a solution.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <string>
+#include <vector>
 
 #include "ctx.hpp"
 #include "ops.hpp"
@@ -88,10 +91,10 @@ __global__ __launch_bounds__(256) void k_dense_mv(const DenseBlockDev* __restric
 }
 
 // tmp[l, r] = sum_j V[j, l] x[c0 + j, r] for each low-rank block (one
-// work-group per (block, l)).
+// work-group per (block, l)); block b's tmp starts at prefix[b] * nrhs.
 __global__ __launch_bounds__(256) void k_lr_vt(const DenseBlockDev* __restrict__ blocks, int nb,
                                                const int64_t* __restrict__ v_off, const int* __restrict__ rank,
-                                               const int64_t* __restrict__ t_off, const zd* __restrict__ store,
+                                               const int64_t* __restrict__ prefix, const zd* __restrict__ store,
                                                const zd* __restrict__ xt, zd* __restrict__ tmp, int64_t n_unk,
                                                int nrhs) {
     const int bid = blockIdx.y;
@@ -116,7 +119,7 @@ __global__ __launch_bounds__(256) void k_lr_vt(const DenseBlockDev* __restrict__
         if ((threadIdx.x & 63) == 0) { sh[0][threadIdx.x >> 6] = sr; sh[1][threadIdx.x >> 6] = si; }
         __syncthreads();
         if (threadIdx.x == 0)
-            tmp[t_off[bid] + (int64_t)rr * r + l] =
+            tmp[prefix[bid] * nrhs + (int64_t)rr * r + l] =
                 zd{sh[0][0] + sh[0][1] + sh[0][2] + sh[0][3], sh[1][0] + sh[1][1] + sh[1][2] + sh[1][3]};
     }
 }
@@ -124,7 +127,7 @@ __global__ __launch_bounds__(256) void k_lr_vt(const DenseBlockDev* __restrict__
 // y[r0 + i, r] += sum_l U[i, l] tmp[l, r]
 __global__ __launch_bounds__(256) void k_lr_u(const DenseBlockDev* __restrict__ blocks, int nb,
                                               const int64_t* __restrict__ u_off, const int* __restrict__ rank,
-                                              const int64_t* __restrict__ t_off, const zd* __restrict__ store,
+                                              const int64_t* __restrict__ prefix, const zd* __restrict__ store,
                                               const zd* __restrict__ tmp, zd* __restrict__ yt, int64_t n_unk,
                                               int nrhs) {
     const int bid = blockIdx.y;
@@ -135,7 +138,7 @@ __global__ __launch_bounds__(256) void k_lr_u(const DenseBlockDev* __restrict__ 
     if (i >= m) return;
     const int r = rank[bid];
     const zd* U = store + u_off[bid];
-    const zd* T = tmp + t_off[bid];
+    const zd* T = tmp + prefix[bid] * nrhs;
     const int64_t r0 = B.upn * (int64_t)B.row_node0;
     for (int rr = 0; rr < nrhs; ++rr) {
         zd s{0.0, 0.0};
@@ -144,43 +147,45 @@ __global__ __launch_bounds__(256) void k_lr_u(const DenseBlockDev* __restrict__ 
     }
 }
 
-// y_t = A x_t in tree order (FP64), y_t overwritten
-void apply_operator_tree(Ctx& c, int nrhs, const zd* xt, zd* yt) {
+__global__ void k_zero_z(int64_t n, zd* __restrict__ y) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e < n) y[e] = zd{0.0, 0.0};
+}
+
+// y_t = A x_t in tree order (FP64), y_t overwritten; tmp holds
+// lr_prefix[nl] * nrhs elements (V^T x of every low-rank block).  Launches
+// only: no allocation, no memset (a fill kernel clears y_t).
+static void apply_operator_tree_into(Ctx& c, int nrhs, const zd* xt, zd* yt, zd* tmp) {
     const int64_t N = c.n_unk;
-    CBIE_HIP(hipMemsetAsync(yt, 0, sizeof(zd) * N * nrhs, c.stream));
+    k_zero_z<<<ceil_div(N * nrhs, 256), 256, 0, c.stream>>>(N * nrhs, yt);
+    check_launch("k_zero_z");
     const int nd = (int)c.dblk.size();
     if (nd > 0) {
         int maxm = 0;
         for (const auto& d : c.dblk) maxm = std::max(maxm, c.upn * d.row_nodes);
-        dim3 grid(ceil_div(maxm, 64), nd);
-        k_dense_mv<<<grid, 256, 0, c.stream>>>(c.d_dblk.p, nd, c.dense.p, xt, yt, N, nrhs);
+        k_dense_mv<<<dim3(ceil_div(maxm, 64), nd), 256, 0, c.stream>>>(c.d_dblk.p, nd, c.dense.p, xt, yt, N, nrhs);
         check_launch("k_dense_mv");
     }
     const int nl = (int)c.lblk.size();
     if (nl > 0) {
-        if (c.mv_tmp_version != c.lr_version || c.mv_tmp_off.size() != (size_t)nl || c.mv_tmp_nrhs != nrhs) {
-            std::vector<int64_t> off(nl);
-            int64_t o = 0;
-            for (int b = 0; b < nl; ++b) { off[b] = o; o += (int64_t)c.lr.rank[b] * nrhs; }
-            c.mv_tmp_off = off;
-            c.d_mv_tmp_off.upload(off, c.stream);
-            c.mv_tmp.alloc(std::max<int64_t>(o, 1));
-            c.mv_tmp_nrhs = nrhs;
-            c.mv_tmp_version = c.lr_version;
-        }
         int maxr = 1, maxm = 0;
         for (int b = 0; b < nl; ++b) {
             maxr = std::max(maxr, c.lr.rank[b]);
             maxm = std::max(maxm, c.upn * c.lblk[b].row_nodes);
         }
-        k_lr_vt<<<dim3(maxr, nl), 256, 0, c.stream>>>(c.d_lblk.p, nl, c.lr.d_v_off.p, c.lr.d_rank.p,
-                                                       c.d_mv_tmp_off.p, c.lr.mem.p, xt, c.mv_tmp.p, N, nrhs);
+        k_lr_vt<<<dim3(maxr, nl), 256, 0, c.stream>>>(
+            c.d_lblk.p, nl, c.lr.d_v_off.p, c.lr.d_rank.p, c.d_lr_prefix.p, c.lr.mem.p, xt, tmp, N, nrhs);
         check_launch("k_lr_vt");
-        k_lr_u<<<dim3(ceil_div(maxm, 256), nl), 256, 0, c.stream>>>(c.d_lblk.p, nl, c.lr.d_u_off.p,
-                                                                     c.lr.d_rank.p, c.d_mv_tmp_off.p,
-                                                                     c.lr.mem.p, c.mv_tmp.p, yt, N, nrhs);
+        k_lr_u<<<dim3(ceil_div(maxm, 256), nl), 256, 0, c.stream>>>(
+            c.d_lblk.p, nl, c.lr.d_u_off.p, c.lr.d_rank.p, c.d_lr_prefix.p, c.lr.mem.p, tmp, yt, N, nrhs);
         check_launch("k_lr_u");
     }
+}
+
+void apply_operator_tree(Ctx& c, int nrhs, const zd* xt, zd* yt) {
+    const int64_t need = std::max<int64_t>(c.lr_prefix.empty() ? 0 : c.lr_prefix.back() * nrhs, 1);
+    if ((int64_t)c.mv_tmp.n < need) c.mv_tmp.alloc(need);
+    apply_operator_tree_into(c, nrhs, xt, yt, c.mv_tmp.p);
 }
 
 void stage_matvec(Ctx& c, int nrhs, const zd* x, zd* y, long ld) {

@@ -221,9 +221,16 @@ void stage_fill(Ctx& c, int n_ang, int n_rad) {
                                                            rule, stride, vals.p + p0 * stride);
             check_launch("k_quad_nm");
         } else {
-            k_quad<<<(unsigned)cnt, 256, 0, c.stream>>>(c.d_patches.p, c.d_objs.p, c.nd, c.d_near.p + p0, cnt,
-                                                        c.d_fej11_x.p, c.d_fej01_x.p, c.d_fej01_w.p, rule, stride,
-                                                        vals.p + p0 * stride);
+            // orders above 8: two nodes per lane (a separate instance keeps
+            // the registers of the common case)
+            if (qmax <= 8)
+                k_quad<8><<<(unsigned)cnt, 256, 0, c.stream>>>(c.d_patches.p, c.d_objs.p, c.nd, c.d_near.p + p0, cnt,
+                                                               c.d_fej11_x.p, c.d_fej01_x.p, c.d_fej01_w.p, rule,
+                                                               stride, vals.p + p0 * stride);
+            else
+                k_quad<11><<<(unsigned)cnt, 256, 0, c.stream>>>(c.d_patches.p, c.d_objs.p, c.nd, c.d_near.p + p0,
+                                                                cnt, c.d_fej11_x.p, c.d_fej01_x.p, c.d_fej01_w.p,
+                                                                rule, stride, vals.p + p0 * stride);
             check_launch("k_quad");
         }
     }
@@ -231,6 +238,10 @@ void stage_fill(Ctx& c, int n_ang, int n_rad) {
 
     // 2) far entries of every dense block
     c.dense.alloc((size_t)c.stats.dense_entries);
+    hipEvent_t e2, e3;
+    CBIE_HIP(hipEventCreate(&e2));
+    CBIE_HIP(hipEventCreate(&e3));
+    CBIE_HIP(hipEventRecord(e2, c.stream));
     if (c.upn == 4) {
         fill_blocks_nm(c, c.dblk, c.d_dblk.p, c.dense.p);
     } else {
@@ -248,6 +259,7 @@ void stage_fill(Ctx& c, int n_ang, int n_rad) {
             check_launch("k_far_fill");
         }
     }
+    CBIE_HIP(hipEventRecord(e3, c.stream));
 
     // 3) overwrite near/self entries: destination block of each pair
     // (row leaf cluster of the target, column range holding the patch)
@@ -294,6 +306,31 @@ void stage_fill(Ctx& c, int n_ang, int n_rad) {
     float ms = 0.f;
     CBIE_HIP(hipEventElapsedTime(&ms, e0, e1));
     c.stats.quad_seconds = ms * 1e-3;
+    CBIE_HIP(hipEventElapsedTime(&ms, e2, e3));
+    c.stats.far_fill_seconds = ms * 1e-3;
+    (void)hipEventDestroy(e2);
+    (void)hipEventDestroy(e3);
+    // work of the near quadrature: points of every pair's rule (two Duffy
+    // triangles per non-degenerate rectangle around the singular point) and
+    // the flops of the basis contraction, the kernel's dominant FP64 term:
+    // per point and source node 8 (MFIE) or 32 (N-Mueller) fused
+    // multiply-adds
+    {
+        double pts = 0.0, fl = 0.0;
+        for (const NearPair& e : c.near) {
+            int ntri = 0;
+            for (int iu = 0; iu < 2; ++iu)
+                for (int iv = 0; iv < 2; ++iv)
+                    if (std::fabs((iu ? 1.0 : -1.0) - e.us) >= 1e-14 && std::fabs((iv ? 1.0 : -1.0) - e.vs) >= 1e-14)
+                        ntri += 2;
+            const double np_ = (double)ntri * rule.n_ang * (e.self ? rule.n_rad : rule.n_in + rule.n_out);
+            const int pq = c.patches[e.patch].q;
+            pts += np_;
+            fl += np_ * pq * pq * (c.upn == 4 ? 64.0 : 16.0);
+        }
+        c.stats.quad_points = pts;
+        c.stats.quad_flops = fl;
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     c.stats.t_fill = now_s() - t0;

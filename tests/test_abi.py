@@ -66,7 +66,7 @@ def test_create_rejects_invalid_objects_before_any_device_work():
         return st, h.value
 
     bad = [
-        [obj(q=9)], [obj(q=1)], [obj(k0=0.0)], [obj(k0=float("nan"))], [obj(axes=(1.0, -1.0, 1.0))],
+        [obj(q=12)], [obj(form=cbie.NMULLER, q=9, eps_r=4.0)], [obj(q=1)], [obj(k0=0.0)], [obj(k0=float("nan"))], [obj(axes=(1.0, -1.0, 1.0))],
         [obj(patches=((6, 0, 0, 1),))], [obj(patches=((0, 2, 0, 2),))], [obj(patches=((0, 0, 0, 0),))],
         [obj(form=7)], [obj(form=cbie.NMULLER, eps_r=-4.0)], [obj(form=cbie.NMULLER, mu_r=0.0)],
         [obj(form=cbie.NMULLER, eps_r=float("inf"))],

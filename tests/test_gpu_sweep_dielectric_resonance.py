@@ -3,17 +3,22 @@ Fig. 7): diameter 4 exterior wavelengths (radius 2 m, wavelength 1 m,
 ka = 4 pi), plane wave along +z polarized along +x, permittivity swept
 through a sharp physical resonance near eps_d = 10.5082 (mu_d = 1).  The
 paper uses 96 patches of 10 x 10 points (38,400 unknowns); here q = 8 on
-150 patches gives the same count.  ACA 1e-6, complex64 H-LU, FP64
-refinement to 1e-10 in at most 30 sweeps.
+150 patches gives the same count (an N-Mueller patch of 10 x 10 points
+would not fit a 256-unknown leaf).  ACA 1e-6, complex64 H-LU.
 
-Away from the resonance the refined solution meets the tolerance and the
-currents follow the Mie series (measured: eps 10.3, 5 sweeps, J within
-1.0e-2; eps 10.5, 8 sweeps, J within 6.1e-2).  Close to it (eps 10.5074)
-the factorization, truncated at 1e-6, is too far from the inverse of the
-nearly singular operator and the refinement stops short of the tolerance
-(the library reports ENOCONV and returns the last iterate); the sweep
-records how far it got at every permittivity and checks the two measured
-points."""
+Two refinements of the same factorization at every permittivity:
+  - stationary FP64 refinement (cbie_solve, at most 30 sweeps), which
+    stops contracting close to the resonance (ENOCONV is recorded, not
+    failed);
+  - GMRES-based refinement (cbie_solve_gmres: FP64 GMRES on A M, the
+    factorization M as right preconditioner), which must reach a relative
+    residual of 1e-10 against the stored FP64 operator at every
+    permittivity, resonance included.
+The paper's claims checked here: the factorization time does not depend
+on the resonance (every factor time within 1.5x of the fastest), and the
+accuracy stays consistent near it (Table 2): the surface current's error
+against the Mie series at every permittivity within 3x of the error at
+the sweep's off-resonance ends, 10.3 and 10.7."""
 import numpy as np
 import pytest
 
@@ -23,7 +28,6 @@ from synth import workloads as W
 pytestmark = pytest.mark.gpu
 
 EPS = (10.3, 10.5, 10.5074, 10.5082, 10.6, 10.7)
-CONVERGED = {10.3: 0.012, 10.5: 0.075}   # measured points: bound on the J error
 
 
 def test_resonance_sweep_of_the_four_wavelength_sphere():
@@ -40,18 +44,25 @@ def test_resonance_sweep_of_the_four_wavelength_sphere():
         s.fill()
         s.compress(1e-6)
         s.factor(cbie.PREC_C64_IR)
+        t_factor = s.stats()["t_factor"]
         b = s.rhs_planewave(kh, pol)
-        x, it = s.solve(b, tol=1e-10, maxit=30, raise_on_noconv=False)
+        x0, it0 = s.solve(b, tol=1e-10, maxit=30, raise_on_noconv=False)
+        res0 = (torch.linalg.norm(s.matvec(x0) - b) / torch.linalg.norm(b)).item()
+        x, itg = s.solve_gmres(b, tol=1e-10, restart=40, maxit=400)
         res = (torch.linalg.norm(s.matvec(x) - b) / torch.linalg.norm(b)).item()
-        st = s.stats()
+        t_gmres = s.stats()["t_solve"]
         s.close()
         nd = G.build_nodes(spec)
         J, M = Mu.currents(nd, x.cpu().numpy()[:, 0])
         Jm, Mm = mie.dielectric_surface_currents(spec.k0, 2.0, eps, 1.0, nd.r)
         eJ, eM = post.weighted_rel_l2(nd, J, Jm), post.weighted_rel_l2(nd, M, Mm)
-        rows[eps] = (res, eJ)
-        print(f"eps {eps}: factor {st['t_factor']:.2f} s, solve {st['t_solve']:.2f} s ({it} sweeps), "
-              f"residual {res:.1e}, J vs Mie {eJ:.3e}, M vs Mie {eM:.3e}", flush=True)
-    for eps, bound in CONVERGED.items():
-        res, eJ = rows[eps]
-        assert res < 1e-8 and eJ < bound, eps
+        rows[eps] = (res, eJ, t_factor)
+        print(f"eps {eps}: factor {t_factor:.2f} s; stationary {it0} sweeps, residual {res0:.1e}; "
+              f"GMRES {itg} steps in {t_gmres:.2f} s, residual {res:.1e}; J vs Mie {eJ:.3e}, M vs Mie {eM:.3e}",
+              flush=True)
+    for eps, (res, eJ, tf) in rows.items():
+        assert res <= 1e-10 * 1.01, eps
+    tmin = min(r[2] for r in rows.values())
+    assert all(r[2] <= 1.5 * tmin for r in rows.values())
+    ends = max(rows[10.3][1], rows[10.7][1])
+    assert all(r[1] <= 3.0 * ends for r in rows.values()), {e: r[1] for e, r in rows.items()}
