@@ -186,3 +186,18 @@ def test_mfie_converges_spectrally_beyond_order_eight():
         Jm = mie.pec_surface_current(spec.k0, 1.0, nd.r)
         errs[q] = post.weighted_rel_l2(nd, post.surface_current(nd, x), Jm)
     assert errs[8] < 6e-3 and errs[10] < 4e-4 and errs[10] < errs[8] / 8
+
+
+@pytest.mark.parametrize("spec", [W.ObjectSpec(axes=(1.0, 0.8, 0.6), center=(0.1, 0.0, 0.0), s=1, q=4, k0=2.0),
+                                  W.tiny_sphere(s=2, q=3, k0=3.0)], ids=["ellipsoid_s1q4", "sphere_s2q3"])
+def test_rows_match_dense_assembly(spec):
+    """The row routine (the checker of every full-size sampled-row test) and
+    the dense assembly reach their entries by different loops (per row: a
+    projection onto every patch; dense: the near-pair list): both must give
+    the same matrix, first, last and interior rows of both components."""
+    nd = G.build_nodes(spec)
+    A = mfie.dense_matrix(nd, spec.k0, workers=4)
+    n2 = 2 * nd.size
+    rows = np.array([0, 1, 7, n2 // 2, n2 // 2 + 1, n2 - 2, n2 - 1])
+    R = mfie.matrix_rows(nd, spec.k0, rows)
+    assert np.abs(R - A[rows]).max() < 1e-13 * np.abs(A).max()
