@@ -49,18 +49,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 
-def run_pipeline(cbie, spec, kh, pol, prec, ir_tol, profile=True, model=None):
+def run_pipeline(cbie, spec, kh, pol, prec, ir_tol, profile=True, model=None, factor_tol=0.0, aca_tol=1e-6):
     """One step: tree, fill, compress (predicted widths when a rank model is
-    given), factor, right-hand sides and the refined solve."""
+    given), factor (truncation at factor_tol, 0: the ACA tolerance), right-hand
+    sides and the refined solve."""
     s = cbie.Solver([spec])
     s.set_profiling(profile)
+    s.set_factor_tolerance(factor_tol)
     s.build_tree(leaf_size=256, eta=1.0, near_delta=1.0)
     s.fill()
     if model is not None:
         s.set_rank_model(*model)
-        s.compress(1e-6, mode=cbie.RANK_PREDICTED)
+        s.compress(aca_tol, mode=cbie.RANK_PREDICTED)
     else:
-        s.compress(1e-6)
+        s.compress(aca_tol)
     s.factor(prec)
     b = s.rhs_planewave(kh, pol)
     x, it = s.solve(b, tol=ir_tol, maxit=20)
@@ -158,15 +160,17 @@ def dielectric(cbie, W, precs, names):
     spec = W.sphere_dielectric()
     kh, pol = np.array([[0.0, 0.0, 1.0]]), np.array([[1.0, 0.0, 0.0]])
     gold = golden("dielectric_24576_dense.npz")
+    # ACA 1e-7: at 1e-6 the compression error, amplified by the conditioning
+    # of the eps_r = 16 system, leaves 1.7e-5 against the dense solution
     out = {"workload": "dielectric sphere eps_r=16, ka=5, 96 patches q=8, 24576 unknowns, N-Mueller, "
-                       "leaf 256, eta 1, ACA 1e-6, 1 plane wave"}
+                       "leaf 256, eta 1, ACA 1e-7, 1 plane wave"}
     for name in names:
         prec = precs[name]
-        s, x, st = run_pipeline(cbie, spec, kh, pol, prec, 1e-10, profile=False)
+        s, x, st = run_pipeline(cbie, spec, kh, pol, prec, 1e-10, profile=False, aca_tol=1e-7)
         s.close()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        s, x, st = run_pipeline(cbie, spec, kh, pol, prec, 1e-10, profile=False)
+        s, x, st = run_pipeline(cbie, spec, kh, pol, prec, 1e-10, profile=False, aca_tol=1e-7)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         b = s.rhs_planewave(kh, pol)
@@ -329,6 +333,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--large-ellipsoid", action="store_true")
+    ap.add_argument("--factor-tol", type=float, default=0.0,
+                    help="truncation tolerance of the mixed leg's factorization (0: the ACA tolerance)")
     args = ap.parse_args()
     if args.copy_probe:
         import torch
@@ -363,15 +369,16 @@ def main():
     for name in names:
         prec = precs[name]
         mdl = model if name == "mixed" else None
+        ftol = args.factor_tol if name == "mixed" else 0.0
         for _ in range(args.warmup):
-            s, x, st = run_pipeline(cbie, spec, kh, pol, prec, 1e-9, model=mdl)
+            s, x, st = run_pipeline(cbie, spec, kh, pol, prec, 1e-9, model=mdl, factor_tol=ftol)
             s.close()
             print(f"[bench] warmup {name} done", file=sys.stderr, flush=True)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         stats = []
         for k in range(args.steps):
-            s, x, st = run_pipeline(cbie, spec, kh, pol, prec, 1e-9, model=mdl)
+            s, x, st = run_pipeline(cbie, spec, kh, pol, prec, 1e-9, model=mdl, factor_tol=ftol)
             stats.append(st)
             s.close()
             print(f"[bench] step {k} {name}: " + ", ".join(f"{p} {st['t_' + p]:.3f}s" for p in
@@ -399,6 +406,7 @@ def main():
     }
     for name, (d, s2, x) in results.items():
         rec = {"seconds": d, "unknowns_per_s": N / d, "ir_iterations": s2["ir_iterations"],
+               "factor_tolerance": (args.factor_tol if name == "mixed" else 0.0) or 1e-6,
                "phases_s": {p: s2["t_" + p] for p in ("tree", "fill", "compress", "factor", "solve")},
                "rank_widths": "predicted" if name == "mixed" else "adaptive"}
         if gold is not None:

@@ -117,7 +117,8 @@ cbie_status cbie_build_tree(cbie_ctx* ctx, int leaf_size, double eta, double nea
  * self/near entries by the change-of-variables quadrature, plus the identity
  * term (1/2 for the MFIE; (mu1 + mu2)/2 and -(eps1 + eps2)/2 for N-Mueller).
  * n_ang / n_rad: points of the singular rule per angular / radial direction
- * (0 = defaults 40 / 32).  Errors: ESTATE, ENOMEM, EHIP. */
+ * (0 = defaults: 40 / 32 up to q = 8, max(40, 6 q - 8) / max(32, 5 q - 8)
+ * for the largest order q of the context).  Errors: ESTATE, ENOMEM, EHIP. */
 cbie_status cbie_fill(cbie_ctx* ctx, int n_ang, int n_rad);
 
 /* Compress the admissible blocks by partial-pivot ACA (Sec. III-A) to the
@@ -133,11 +134,22 @@ cbie_status cbie_fill(cbie_ctx* ctx, int n_ang, int n_rad);
 cbie_status cbie_compress(cbie_ctx* ctx, double aca_tol, cbie_rank_mode mode);
 
 /* H-LU factorization (eqs. 23-28): partial pivoting inside diagonal leaves,
- * none across blocks; formatted updates truncated at the compress tolerance.
+ * none across blocks; formatted updates truncated at the compress tolerance
+ * (or the tolerance set by cbie_set_factor_tolerance) in the relative
+ * Frobenius norm of each block, with the range basis of every truncation
+ * built in FP64 in both precisions.
  * CBIE_PREC_C128: complex128 on FP64 MFMA.  CBIE_PREC_C64_IR: complex64 on
  * FP32 MFMA (FP32 accumulation); solve() then refines in FP64.
  * Errors: ESTATE, ENOMEM, EHIP, ESINGULAR. */
 cbie_status cbie_factor(cbie_ctx* ctx, cbie_precision prec);
+
+/* Truncation tolerance of the formatted sums of later factorizations
+ * (an addition to the paper, which truncates at the ACA tolerance): tol in
+ * (0, 1), or 0 for the compress tolerance (the default).  A looser factor
+ * is a cheaper preconditioner; the refinement of cbie_solve or
+ * cbie_solve_gmres still converges to the stored FP64 operator's solution
+ * while it contracts.  Errors: EINVAL. */
+cbie_status cbie_set_factor_tolerance(cbie_ctx* ctx, double tol);
 
 /* Solve A x = b for nrhs right-hand sides (per object).  b_dev, x_dev:
  * complex128 device arrays, n_unknowns x nrhs, leading dimension ld,

@@ -25,7 +25,8 @@ EXPORTED = ["cbie_create", "cbie_build_tree", "cbie_fill", "cbie_compress", "cbi
             "cbie_solve", "cbie_matvec", "cbie_rhs_planewave", "cbie_farfield", "cbie_get_stats",
             "cbie_set_profiling", "cbie_get_near_pairs", "cbie_export_dense", "cbie_last_error",
             "cbie_destroy", "cbie_get_block_features", "cbie_set_rank_model", "cbie_mlp_forward",
-            "cbie_mlp_grad", "cbie_mlp_train", "cbie_solve_gmres"]
+            "cbie_mlp_grad", "cbie_mlp_train", "cbie_solve_gmres",
+            "cbie_set_factor_tolerance"]
 
 MLP_NFEAT, MLP_NPARAMS = 8, 4801
 
@@ -84,6 +85,7 @@ def load(path: str = LIB_PATH):
         "cbie_solve": ([vp, i32, vp, vp, C.c_long, dbl, i32, C.POINTER(i32)], i32),
         "cbie_matvec": ([vp, i32, vp, vp, C.c_long], i32),
         "cbie_solve_gmres": ([vp, i32, vp, vp, C.c_long, dbl, i32, i32, C.POINTER(i32)], i32),
+        "cbie_set_factor_tolerance": ([vp, dbl], i32),
         "cbie_rhs_planewave": ([vp, i32, vp, vp, vp, C.c_long], i32),
         "cbie_farfield": ([vp, i32, vp, C.c_long, i32, vp, vp], i32),
         "cbie_get_stats": ([vp, vp, C.c_size_t], i32),
@@ -175,6 +177,10 @@ class Solver:
 
     def factor(self, prec=PREC_C128):
         self._check(self.lib.cbie_factor(self.h, prec))
+
+    def set_factor_tolerance(self, tol):
+        """Truncation tolerance of later factorizations (0: the compress tolerance)."""
+        self._check(self.lib.cbie_set_factor_tolerance(self.h, tol))
 
     def _cols(self, v):
         """(n,) or (n, m) complex128 cuda tensor -> contiguous (m, n) tensor."""

@@ -182,6 +182,13 @@ cbie_status cbie_factor(cbie_ctx* ctx, cbie_precision prec) {
     });
 }
 
+cbie_status cbie_set_factor_tolerance(cbie_ctx* ctx, double tol) {
+    return guarded(ctx, [&](Ctx& c) {
+        CBIE_REQUIRE(tol >= 0 && tol < 1, CBIE_EINVAL, "factor tolerance outside [0, 1)");
+        c.factor_tol = tol;
+    });
+}
+
 cbie_status cbie_solve(cbie_ctx* ctx, int nrhs, const void* b_dev, void* x_dev, long ld, double ir_tol,
                        int ir_maxit, int* ir_iters_out) {
     return guarded(ctx, [&](Ctx& c) {

@@ -73,6 +73,7 @@ struct Ctx {
     std::vector<DenseBlockDev> lblk;        // geometry of low-rank blocks (same layout)
     DBuf<DenseBlockDev> d_lblk;
     double aca_tol = 1e-6;
+    double factor_tol = 0.0;                // truncation of formatted sums (0: aca_tol)
 
     // exclusive prefix sums of the low-rank ranks (nl + 1 entries, set by
     // compress): block b's V^T x occupies rows prefix[b] * nrhs .. of the

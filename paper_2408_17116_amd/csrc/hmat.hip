@@ -876,6 +876,87 @@ template <typename T> struct HF {
             ++launches;
         }
     }
+    // FP64 products of the recompression's range basis (complex64
+    // factorization), 64 x 64 tiles.  The Gram products have a deep k (the
+    // block's rows) and few output tiles: k is split into 256-deep ranges
+    // whose partial products go to a workspace in the recompression's
+    // scratch, summed in order by one reduction launch (no atomics).
+    void run_gemms_f64(const std::vector<GemmDesc<double>>& g) {
+        if (g.empty()) return;
+        std::vector<GemmDesc<double>> e;
+        std::vector<GemmTile> t;
+        std::vector<ReduceDesc<double>> rd;
+        std::vector<CopyTile> rt;
+        double fl = 0.0;
+        int64_t ws_left = int64_t(1) << 25;   // partial-product entries of this call (512 MiB)
+        for (const GemmDesc<double>& d : g) {
+            fl += 8.0 * d.m * d.n * d.k;
+            const int64_t tiles = (int64_t)((d.m + 63) / 64) * ((d.n + 63) / 64);
+            int S = (d.k >= 512 && tiles < 64) ? (int)std::min<int64_t>((d.k + 255) / 256, 32) : 1;
+            if ((int64_t)S * d.m * d.n > ws_left) S = 1;
+            if (S > 1) ws_left -= (int64_t)S * d.m * d.n;
+            if (S <= 1) {
+                for (int m0 = 0; m0 < d.m; m0 += 64)
+                    for (int n0 = 0; n0 < d.n; n0 += 64) t.push_back(GemmTile{(int)e.size(), m0, n0, 0});
+                e.push_back(d);
+                continue;
+            }
+            const int64_t mn = (int64_t)d.m * d.n;
+            cplx<double>* W = reinterpret_cast<cplx<double>*>(rscratch.alloc(2 * (size_t)(mn * S)));
+            const int kc = (d.k + S - 1) / S;
+            for (int q = 0; q < S; ++q) {
+                const int k0 = q * kc, k1 = std::min(d.k, k0 + kc);
+                if (k1 <= k0) continue;
+                GemmDesc<double> x = d;
+                x.k = k1 - k0;
+                x.A = d.ta == 0 ? d.A + (int64_t)k0 * d.lda : d.A + k0;
+                x.B = d.tb == 0 ? d.B + k0 : d.B + (int64_t)k0 * d.ldb;
+                x.alpha = cplx<double>{1.0, 0.0};
+                x.beta = cplx<double>{0.0, 0.0};
+                x.C = W + q * mn;
+                x.ldc = d.m;
+                for (int m0 = 0; m0 < d.m; m0 += 64)
+                    for (int n0 = 0; n0 < d.n; n0 += 64) t.push_back(GemmTile{(int)e.size(), m0, n0, 0});
+                e.push_back(x);
+            }
+            const int nsplit = (d.k + kc - 1) / kc;
+            const int ri = (int)rd.size();
+            rd.push_back(ReduceDesc<double>{d.m, d.n, nsplit, d.ldc, d.alpha, d.beta, W, d.C});
+            for (int64_t e0 = 0; e0 < mn; e0 += kCopyChunk) rt.push_back(CopyTile{ri, (int)e0});
+        }
+        flops += fl;
+        alg_flops += fl;
+        const GemmDesc<double>* dg = stage_upload(e);
+        const GemmTile* dt = stage_upload(t);
+        const int nt = (int)t.size();
+        launch([=] { gemm_batched<double>(s, dg, dt, nt, kTile64x64); });
+        ++launches;
+        if (!rt.empty()) {
+            const ReduceDesc<double>* dr = stage_upload(rd);
+            const CopyTile* drt = stage_upload(rt);
+            const int nr = (int)rt.size();
+            launch([=] { reduce_batched<double>(s, dr, drt, nr); });
+            ++launches;
+        }
+    }
+    template <typename P> void run_pchol(const std::vector<PcholDesc<P>>& v) {
+        if (v.empty()) return;
+        const PcholDesc<P>* d = stage_upload(v);
+        const int n = (int)v.size();
+        launch([=] { pchol_batched<P>(s, d, n); });
+        ++launches;
+    }
+    template <typename A, typename B> void run_convert(const std::vector<ConvDesc<A, B>>& v) {
+        std::vector<ConvTile> t;
+        for (size_t i = 0; i < v.size(); ++i)
+            for (int64_t e0 = 0; e0 < v[i].n; e0 += 4096) t.push_back(ConvTile{(int)i, 0, e0});
+        if (t.empty()) return;
+        const ConvDesc<A, B>* d = stage_upload(v);
+        const ConvTile* dt = stage_upload(t);
+        const int nt = (int)t.size();
+        launch([=] { convert_batched_dev<A, B>(s, d, dt, nt); });
+        ++launches;
+    }
     void run_copies(const std::vector<CopyDesc<T>>& c2) {
         if (c2.empty()) return;
         std::vector<CopyTile> tiles;
@@ -909,8 +990,16 @@ template <typename T> struct HF {
             pq[q] = std::min({L.m, L.n, L.r + 32 + (L.dirty ? 32 : 0), 512});
         }
         // Gram eigenvalue ratio kept by the pivoted Cholesky: CholeskyQR2 is
-        // stable while cond(Y) < u^{-1/2}, i.e. ratio > ~u (FP64 1e-16, FP32 1e-7)
-        const double gram_thr = sizeof(T) == 8 ? 1e-16 : 1e-7;
+        // stable while cond(Y) < u^{-1/2}, i.e. ratio > ~u.  The range basis is
+        // always built in FP64: in complex64 the sample Y is converted
+        // exactly, its Gram matrix, pivoted Cholesky and both CholeskyQR
+        // passes run in double, and only Q is rounded to complex64.  An FP32
+        // Gram matrix would drop every direction below u32^{1/2} ~ 3e-4 of the
+        // largest, far looser than the truncation tolerance.  The ratio kept
+        // is 1e-16 in complex128 and 1e-14 in complex64 (directions down to
+        // 1e-7, the resolution of the FP32 sample).
+        const double gram_thr = sizeof(T) == 8 ? 1e-16 : 1e-14;
+        constexpr bool f64_basis = sizeof(T) == 4;
         std::vector<int> rest_b, rest_p;
         while (!todo.empty()) {
             // blocks whose temporaries fit the scratch budget go in this round
@@ -919,7 +1008,8 @@ template <typename T> struct HF {
                 for (; take < todo.size(); ++take) {
                     const LR& L = lr[todo[take]];
                     const size_t pp = (size_t)pq[take], K1 = (size_t)std::max(L.K, 1);
-                    const size_t need = pp * (3 * (size_t)L.n + 4 * (size_t)L.m + 2 * K1 + 6 * pp);
+                    size_t need = pp * (3 * (size_t)L.n + 4 * (size_t)L.m + 2 * K1 + 6 * pp);
+                    if (f64_basis) need += pp * (6 * (size_t)L.m + 8 * pp);   // FP64 basis temporaries
                     if (take > 0 && mem + need > kRecompScratch) break;
                     mem += need;
                 }
@@ -931,10 +1021,11 @@ template <typename T> struct HF {
             const size_t nb = todo.size();
             size_t bytes = 0;
             for (size_t q = 0; q < nb; ++q)
-                bytes += 64 * 1024 + (size_t)((lr[todo[q]].m + lr[todo[q]].n) / 64 + 4) * ((pq[q] + 63) / 64 + 2) * 64;
+                bytes += 128 * 1024 + (size_t)((lr[todo[q]].m + lr[todo[q]].n) / 64 + 4) * ((pq[q] + 63) / 64 + 2) * 64;
             imm_begin(std::max<size_t>(bytes * 4, (size_t)1 << 22));
             struct Tmp {
                 cplx<T> *Om, *W, *Y, *G, *S, *Q1, *G2, *S2, *Q, *Z, *B, *Ub, *Vb, *Uo;
+                cplx<double> *Yd, *Gd, *Sd, *Q1d, *G2d, *S2d, *Qd;   // FP64 basis (complex64 factorization)
                 int cap;
             };
             std::vector<Tmp> tm(nb);
@@ -943,6 +1034,10 @@ template <typename T> struct HF {
             std::vector<RandDesc<T>> rd;
             std::vector<GemmDesc<T>> g1, g2, g3, g4, g5, g6, h1, h2, h4, q1, q2;
             std::vector<PcholDesc<T>> pc, pc2;
+            std::vector<GemmDesc<double>> d4, d5, dq1, dq2;
+            std::vector<PcholDesc<double>> pcd, pcd2;
+            std::vector<ConvDesc<T, double>> cvin;
+            std::vector<ConvDesc<double, T>> cvout;
             int* ks2 = reinterpret_cast<int*>(rscratch.alloc(nb));
             std::vector<AcaProdJob<T>> aj;
             const cplx<T> o = one(), z = zero();
@@ -972,13 +1067,33 @@ template <typename T> struct HF {
                     g2.push_back(GemmDesc<T>{m, pp, K, 0, 0, o, z, L.U, t.W, t.Y, m, K, m, 0});
                 }
                 if (L.dirty) g3.push_back(GemmDesc<T>{m, pp, n, 0, 0, o, K > 0 ? o : z, L.D, t.Om, t.Y, m, n, m, 0});
-                g4.push_back(GemmDesc<T>{pp, pp, m, 2, 0, o, z, t.Y, t.Y, t.G, m, m, pp, 0});
-                pc.push_back(PcholDesc<T>{t.G, t.S, pp, gram_thr, ks + q});
-                g5.push_back(GemmDesc<T>{m, pp, pp, 0, 0, o, z, t.Y, t.S, t.Q1, m, pp, m, 0});
-                // second CholeskyQR pass restores orthogonality
-                q1.push_back(GemmDesc<T>{pp, pp, m, 2, 0, o, z, t.Q1, t.Q1, t.G2, m, m, pp, 0});
-                pc2.push_back(PcholDesc<T>{t.G2, t.S2, pp, 1e-4, ks2 + q});
-                q2.push_back(GemmDesc<T>{m, pp, pp, 0, 0, o, z, t.Q1, t.S2, t.Q, m, pp, m, 0});
+                if constexpr (f64_basis) {
+                    const cplx<double> od{1.0, 0.0}, zd0{0.0, 0.0};
+                    auto dalloc = [&](size_t e) { return reinterpret_cast<cplx<double>*>(rscratch.alloc(2 * e)); };
+                    t.Yd = dalloc((size_t)m * pp);
+                    t.Gd = dalloc((size_t)pp * pp);
+                    t.Sd = dalloc((size_t)pp * pp);
+                    t.Q1d = dalloc((size_t)m * pp);
+                    t.G2d = dalloc((size_t)pp * pp);
+                    t.S2d = dalloc((size_t)pp * pp);
+                    t.Qd = dalloc((size_t)m * pp);
+                    cvin.push_back(ConvDesc<T, double>{t.Y, t.Yd, (int64_t)m * pp});
+                    d4.push_back(GemmDesc<double>{pp, pp, m, 2, 0, od, zd0, t.Yd, t.Yd, t.Gd, m, m, pp, 0});
+                    pcd.push_back(PcholDesc<double>{t.Gd, t.Sd, pp, gram_thr, ks + q});
+                    d5.push_back(GemmDesc<double>{m, pp, pp, 0, 0, od, zd0, t.Yd, t.Sd, t.Q1d, m, pp, m, 0});
+                    dq1.push_back(GemmDesc<double>{pp, pp, m, 2, 0, od, zd0, t.Q1d, t.Q1d, t.G2d, m, m, pp, 0});
+                    pcd2.push_back(PcholDesc<double>{t.G2d, t.S2d, pp, 1e-4, ks2 + q});
+                    dq2.push_back(GemmDesc<double>{m, pp, pp, 0, 0, od, zd0, t.Q1d, t.S2d, t.Qd, m, pp, m, 0});
+                    cvout.push_back(ConvDesc<double, T>{t.Qd, t.Q, (int64_t)m * pp});
+                } else {
+                    g4.push_back(GemmDesc<T>{pp, pp, m, 2, 0, o, z, t.Y, t.Y, t.G, m, m, pp, 0});
+                    pc.push_back(PcholDesc<T>{t.G, t.S, pp, gram_thr, ks + q});
+                    g5.push_back(GemmDesc<T>{m, pp, pp, 0, 0, o, z, t.Y, t.S, t.Q1, m, pp, m, 0});
+                    // second CholeskyQR pass restores orthogonality
+                    q1.push_back(GemmDesc<T>{pp, pp, m, 2, 0, o, z, t.Q1, t.Q1, t.G2, m, m, pp, 0});
+                    pc2.push_back(PcholDesc<T>{t.G2, t.S2, pp, 1e-4, ks2 + q});
+                    q2.push_back(GemmDesc<T>{m, pp, pp, 0, 0, o, z, t.Q1, t.S2, t.Q, m, pp, m, 0});
+                }
                 if (K > 0) g6.push_back(GemmDesc<T>{pp, K, m, 2, 0, o, z, t.Q, L.U, t.Z, m, m, pp, 0});
                 if (K > 0) h1.push_back(GemmDesc<T>{pp, n, K, 0, 1, o, z, t.Z, L.V, t.B, pp, n, pp, 0});
                 if (L.dirty) h2.push_back(GemmDesc<T>{pp, n, m, 2, 0, o, K > 0 ? o : z, t.Q, L.D, t.B, m, m, pp, 0});
@@ -1001,22 +1116,23 @@ template <typename T> struct HF {
             run_gemms(g1);
             run_gemms(g2);
             run_gemms(g3);
-            run_gemms(g4);
-            {
-                const PcholDesc<T>* d = stage_upload(pc);
-                const int n = (int)pc.size();
-                launch([=] { pchol_batched<T>(s, d, n); });
+            if constexpr (f64_basis) {
+                run_convert(cvin);
+                run_gemms_f64(d4);
+                run_pchol(pcd);
+                run_gemms_f64(d5);
+                run_gemms_f64(dq1);
+                run_pchol(pcd2);
+                run_gemms_f64(dq2);
+                run_convert(cvout);
+            } else {
+                run_gemms(g4);
+                run_pchol(pc);
+                run_gemms(g5);
+                run_gemms(q1);
+                run_pchol(pc2);
+                run_gemms(q2);
             }
-            ++launches;
-            run_gemms(g5);
-            run_gemms(q1);
-            {
-                const PcholDesc<T>* d = stage_upload(pc2);
-                const int n = (int)pc2.size();
-                launch([=] { pchol_batched<T>(s, d, n); });
-            }
-            ++launches;
-            run_gemms(q2);
             run_gemms(g6);
             run_gemms(h1);
             run_gemms(h2);
@@ -1758,7 +1874,7 @@ Ctx::Ctx() {}
 Ctx::~Ctx() {}
 
 template <typename T> static std::shared_ptr<HF<T>> make_factor(Ctx& c) {
-    auto f = std::make_shared<HF<T>>(c, c.aca_tol);
+    auto f = std::make_shared<HF<T>>(c, c.factor_tol > 0.0 ? c.factor_tol : c.aca_tol);
     hipStream_t s = c.stream;
     const Tree& T_ = c.tree;
     f->dense.alloc(std::max<int64_t>(c.stats.dense_entries, 1));

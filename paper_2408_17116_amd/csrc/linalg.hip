@@ -300,10 +300,6 @@ __global__ void k_convert(int64_t n, const cplx<Tin>* __restrict__ a, cplx<Tout>
 
 // many conversions in one launch: work-group t converts elements
 // [e0, e0 + 4096) of array desc
-struct ConvTile {
-    int desc, pad;
-    int64_t e0;
-};
 template <typename Tin, typename Tout>
 __global__ void k_convert_b(const ConvDesc<Tin, Tout>* __restrict__ d, const ConvTile* __restrict__ t, int nt) {
     if ((int)blockIdx.x >= nt) return;
@@ -325,6 +321,14 @@ void convert_batched(hipStream_t s, const std::vector<ConvDesc<Tin, Tout>>& v) {
     k_convert_b<Tin, Tout><<<(unsigned)t.size(), 256, 0, s>>>(dd.p, dt.p, (int)t.size());
     check_launch("k_convert_b");
     CBIE_HIP(hipStreamSynchronize(s));   // the descriptor buffers are released on return
+}
+
+// the same launch over descriptors and tiles already on the device
+template <typename Tin, typename Tout>
+void convert_batched_dev(hipStream_t s, const ConvDesc<Tin, Tout>* d, const ConvTile* t, int nt) {
+    if (nt <= 0) return;
+    k_convert_b<Tin, Tout><<<(unsigned)nt, 256, 0, s>>>(d, t, nt);
+    check_launch("k_convert_b");
 }
 
 template <typename Tin, typename Tout>
@@ -535,6 +539,8 @@ CBIE_LINALG_INST(double)
 CBIE_LINALG_INST(float)
 template void convert_batched<double, float>(hipStream_t, const std::vector<ConvDesc<double, float>>&);
 template void convert_batched<double, double>(hipStream_t, const std::vector<ConvDesc<double, double>>&);
+template void convert_batched_dev<float, double>(hipStream_t, const ConvDesc<float, double>*, const ConvTile*, int);
+template void convert_batched_dev<double, float>(hipStream_t, const ConvDesc<double, float>*, const ConvTile*, int);
 template void convert<double, float>(hipStream_t, int64_t, const zd*, zf*);
 template void convert<float, double>(hipStream_t, int64_t, const zf*, zd*);
 template void convert<double, double>(hipStream_t, int64_t, const zd*, zd*);

@@ -44,6 +44,15 @@ template <typename Tin, typename Tout> struct ConvDesc {
 };
 template <typename Tin, typename Tout>
 void convert_batched(hipStream_t s, const std::vector<ConvDesc<Tin, Tout>>& v);
+// work-group t converts elements [e0, e0 + 4096) of array desc
+struct ConvTile {
+    int desc, pad;
+    int64_t e0;
+};
+// convert_batched over descriptors and tiles already on the device (no
+// allocation, no synchronization)
+template <typename Tin, typename Tout>
+void convert_batched_dev(hipStream_t s, const ConvDesc<Tin, Tout>* d, const ConvTile* t, int nt);
 
 // ACA of an implicit product M = Uc Vc^T (m x n, inner K <= 2048): writes
 // U (m x cap) and V (n x cap), cap <= 1024, with M ~ U V^T to relative

@@ -189,9 +189,13 @@ void stage_fill(Ctx& c, int n_ang, int n_rad) {
     const double t0 = now_s();
     const Tree& T = c.tree;
     // singular rule of the change of variables
+    // default sizes grow with the order above 8: the integrand carries the
+    // interpolation basis, a polynomial of degree q - 1 in each direction
+    int qmax_rule = 0;
+    for (const auto& p : c.patches) qmax_rule = std::max(qmax_rule, p.q);
     QuadRule rule{};
-    rule.n_ang = n_ang > 0 ? n_ang : 40;
-    rule.n_rad = n_rad > 0 ? n_rad : 32;
+    rule.n_ang = n_ang > 0 ? n_ang : std::max(40, 6 * qmax_rule - 8);
+    rule.n_rad = n_rad > 0 ? n_rad : std::max(32, 5 * qmax_rule - 8);
     rule.n_in = std::max(4, (rule.n_rad * 5) / 8);
     rule.n_out = rule.n_rad;
     CBIE_REQUIRE(rule.n_ang <= kMaxRule && rule.n_rad <= kMaxRule, CBIE_EINVAL, "rule size above 96");

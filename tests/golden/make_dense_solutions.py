@@ -13,9 +13,10 @@ oracle's row routine (matrix_rows) and the residual of the stored solution
 on those rows is recorded: it checks the row routine against the dense
 assembly at full size and the solution against the matrix it solves.
 
-    python tests/golden/make_dense_solutions.py sphere_ka20     # 49152 unknowns, ~1.5 h on 8 cores, 40 GB
+    python tests/golden/make_dense_solutions.py sphere_ka20     # 49152 unknowns, ~32 min on 8 cores, 40 GB
     python tests/golden/make_dense_solutions.py dielectric      # 24576 unknowns
     python tests/golden/make_dense_solutions.py batch_subset    # 4 seeded objects of the 64-ellipsoid batch
+    python tests/golden/make_dense_solutions.py resonance       # 38400 unknowns, eps_d 10.5074 (Sec. IV-B)
 """
 from __future__ import annotations
 
@@ -135,6 +136,12 @@ def main():
             out[f"x{o}"] = x
             out[f"check_residual{o}"] = rec["check_residual"]
         np.savez(os.path.join(HERE, "ellipsoid_batch_subset_dense.npz"), **out)
+    elif which == "resonance":
+        spec = W.ObjectSpec(axes=(2.0, 2.0, 2.0), center=(0.0, 0.0, 0.0), s=5, q=8, k0=2.0 * np.pi,
+                            form=W.FORM_NMULLER, eps_r=10.5074, mu_r=1.0)
+        kh, pol = W.axial_wave()
+        x, rec = dense_solve(spec, kh, pol)
+        np.savez(os.path.join(HERE, "resonance_38400_dense.npz"), x=x, khat=kh, pol=pol, **rec)
     else:
         raise SystemExit(f"unknown workload {which}")
 

@@ -115,3 +115,41 @@ def test_predicted_width_fallback_meets_tolerance():
     assert err <= 10 * tol
     torch.cuda.synchronize()
     s.close()
+
+
+def test_complex64_recompression_keeps_the_tolerance():
+    """Recompression of formatted sums in a complex64 factorization builds
+    its range basis in FP64 (an FP32 Gram matrix would drop every direction
+    below ~3e-4 of the largest).  Forced to recompress after every 64
+    appended columns (CBIE_KMAX), the complex64 factorization's plain
+    substitution must leave a residual against the stored FP64 operator
+    within a small factor of the complex128 one's: both are truncated at the
+    same tolerance, and complex64 rounding adds ~1e-7 relative per entry."""
+    import os
+    import torch
+    from paper_2408_17116_amd import cbie
+    spec = W.tiny_sphere(s=4, q=4, k0=6.0)      # 3072 unknowns
+    old = os.environ.get("CBIE_KMAX")
+    os.environ["CBIE_KMAX"] = "64"
+    try:
+        s = cbie.Solver([spec])
+        s.build_tree(leaf_size=64, eta=1.0, near_delta=1.0)
+        s.fill()
+        s.compress(1e-8)
+        kh, pol = W.plane_waves(2, seed=8)
+        b = s.rhs_planewave(kh, pol)
+        res = {}
+        for prec in (cbie.PREC_C128, cbie.PREC_C64_IR):
+            s.factor(prec)
+            x0, _ = s.solve(b, tol=1e-10, maxit=0)
+            res[prec] = (torch.linalg.norm(s.matvec(x0) - b) / torch.linalg.norm(b)).item()
+            x, it = s.solve(b, tol=1e-10, maxit=30)
+            print(f"prec {prec}: substitution residual {res[prec]:.2e}, {it} sweeps to 1e-10")
+        s.close()
+    finally:
+        if old is None:
+            del os.environ["CBIE_KMAX"]
+        else:
+            os.environ["CBIE_KMAX"] = old
+    assert res[cbie.PREC_C128] < 1e-6
+    assert res[cbie.PREC_C64_IR] < 1e-4

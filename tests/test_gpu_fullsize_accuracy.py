@@ -7,7 +7,7 @@ tests/golden/make_dense_solutions.py, which calls only the oracle.  The
 target is the relative L2 error 1e-5 of the unknowns against that dense
 solution, for both pipelines:
   - the 49,152-unknown PEC sphere at ka = 20 with its 16 seeded waves;
-  - the 24,576-unknown dielectric sphere (N-Mueller);
+  - the 24,576-unknown dielectric sphere (N-Mueller; ACA 1e-7);
   - four seeded objects of the 64-ellipsoid batch, solved inside the
     64-object context with 32 waves each (the first four compared).
 The 196,608-unknown ellipsoid has no dense oracle (618 GB): 256 seeded
@@ -64,8 +64,11 @@ def test_sphere_ka20_against_dense_oracle(prec):
 
 @pytest.mark.parametrize("prec", [1, 0], ids=["c64_ir", "c128_ir"])
 def test_dielectric_against_dense_oracle(prec):
+    # ACA 1e-7: at 1e-6 the compression error, amplified by the conditioning
+    # of the eps_r = 16 N-Mueller system, leaves 1.7e-5 against the dense
+    # solution (measured), above the 1e-5 target
     g = _gold("dielectric_24576_dense.npz")
-    s, x, it = _pipeline([W.sphere_dielectric()], prec, g["khat"], g["pol"])
+    s, x, it = _pipeline([W.sphere_dielectric()], prec, g["khat"], g["pol"], tol=1e-7)
     s.close()
     err = _rel(x, g["x"])
     print(f"prec {prec}: {it} sweeps, rel L2 vs dense oracle {err:.2e}")
@@ -85,6 +88,29 @@ def test_batch_subset_against_dense_oracle():
         err = _rel(x[off[o]:off[o + 1], :xr.shape[1]], xr)
         print(f"object {o} ({objs[o].n_unknowns} unknowns, q {objs[o].q}): rel L2 vs dense oracle {err:.2e}")
         assert err < TARGET
+
+
+def test_resonance_against_dense_oracle():
+    """The 38,400-unknown dielectric sphere at eps_d 10.5074, next to the
+    resonance of Sec. IV-B (Fig. 7).  Compressed at 1e-8 so the H-matrix
+    error stays small against the conditioning there, factored in complex64
+    and refined to 1e-10: the solution must match the dense oracle, and its
+    error against the Mie series must be the oracle's own (the
+    discretization's)."""
+    from oracle import mie, post
+    g = _gold("resonance_38400_dense.npz")
+    spec = W.ObjectSpec(axes=(2.0, 2.0, 2.0), center=(0.0, 0.0, 0.0), s=5, q=8, k0=2.0 * np.pi,
+                        form=W.FORM_NMULLER, eps_r=10.5074, mu_r=1.0)
+    s, x, it = _pipeline([spec], 1, g["khat"], g["pol"], tol=1e-8)
+    s.close()
+    err = _rel(x, g["x"])
+    nd = G.build_nodes(spec)
+    Jm, _ = mie.dielectric_surface_currents(spec.k0, 2.0, 10.5074, 1.0, nd.r)
+    eg = post.weighted_rel_l2(nd, Mu.currents(nd, x[:, 0])[0], Jm)
+    eo = post.weighted_rel_l2(nd, Mu.currents(nd, g["x"][:, 0])[0], Jm)
+    print(f"{it} sweeps; rel L2 vs dense oracle {err:.2e}; J vs Mie: solver {eg:.3e}, dense oracle {eo:.3e}")
+    assert err < 1e-4
+    assert abs(eg - eo) <= 0.05 * eo
 
 
 def _rows_worker(args):

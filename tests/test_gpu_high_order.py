@@ -35,7 +35,12 @@ def test_fill_rows_match_oracle(q):
     ref = mfie.matrix_rows(nd, spec.k0, rows)
     got = A[rows].cpu().numpy()
     err = np.abs(got - ref).max() / np.abs(ref).max()
-    print(f"q {q}: rows err {err:.2e}")
+    # the same rows with a finer rule (90 x 72 points): what is left of the
+    # difference is the oracle's side
+    s.fill(n_ang=90, n_rad=72)
+    fine = s.export_dense()[rows].cpu().numpy()
+    err_f = np.abs(fine - ref).max() / np.abs(ref).max()
+    print(f"q {q}: rows err {err:.2e} (finer rule {err_f:.2e})")
     assert err < 1e-9
     s.close()
 
