@@ -33,6 +33,9 @@ python bench.py --large-ellipsoid   (the PEC ellipsoid of semi-axes (8, 4, 2) m,
                                 ellipsoids; adaptive vs predicted-width
                                 compression; complex64 H-LU + refinement and
                                 a one-wave solve; one JSON line, about 2 min)
+python bench.py --sphere-scaling 2,4,8,16,26   (the 3-wavelength-radius PEC sphere
+                                at q = 10 from 4,800 to 811,200 unknowns: phase
+                                times and storage per size, one JSON line each)
 python bench.py --copy-probe   (a plain 1 GiB read + 1 GiB write elementwise
                                 kernel, three launches: the reference for
                                 scaling HBM traffic counters)
@@ -266,6 +269,41 @@ def large_ellipsoid(cbie, W):
     return out
 
 
+def sphere_scaling(cbie, W, splits):
+    """The paper's scaling study (Sec. IV-A, Fig. 4): PEC sphere of radius
+    3 wavelengths (ka = 6 pi), 10 x 10 points per patch, cube-sphere faces
+    split s x s (6 s^2 patches, 1200 s^2 unknowns: 4,800 at s = 2 up to
+    811,200 at s = 26), ACA 1e-4, axial wave, mixed pipeline.  Times of each
+    phase, compression rate, storage and the residual against the stored
+    operator, one size at a time (one JSON line each)."""
+    import numpy as np
+    import torch
+    kh, pol = W.axial_wave()
+    for s_ in splits:
+        spec = W.ObjectSpec(axes=(3.0, 3.0, 3.0), center=(0.0, 0.0, 0.0), s=s_, q=10, k0=2.0 * np.pi)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sv = cbie.Solver([spec])
+        sv.build_tree(leaf_size=256, eta=1.0, near_delta=1.0)
+        sv.fill()
+        sv.compress(1e-4)
+        sv.factor(cbie.PREC_C64_IR)
+        b = sv.rhs_planewave(kh, pol)
+        x, it = sv.solve(b, tol=1e-10, maxit=30)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = sv.stats()
+        res = (torch.linalg.norm(sv.matvec(x) - b) / torch.linalg.norm(b)).item()
+        sv.close()
+        rec = {"sphere_scaling": {"radius_wavelengths": 3, "q": 10, "patches": 6 * s_ * s_,
+                                  "unknowns": spec.n_unknowns, "seconds": dt,
+                                  "phases_s": {p: st["t_" + p] for p in ("tree", "fill", "compress", "factor", "solve")},
+                                  "compression_rate": st["compression_rate"], "max_rank": st["max_rank"],
+                                  "lr_entries": st["lr_entries"], "dense_entries": st["dense_entries"],
+                                  "factor_flops": st["factor_flops"], "ir_iterations": it, "residual": res}}
+        print(json.dumps(rec), flush=True)
+
+
 def gemm_traffic(pipeline):
     """HBM bytes per k_zgemm launch from the committed counter runs
     (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known size), or
@@ -333,6 +371,8 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
     ap.add_argument("--large-ellipsoid", action="store_true")
+    ap.add_argument("--sphere-scaling", default="",
+                    help="comma-separated face splits s of the 3-wavelength sphere at q = 10 (e.g. 2,4,8,16,26)")
     ap.add_argument("--factor-tol", type=float, default=0.0,
                     help="truncation tolerance of the mixed leg's factorization (0: the ACA tolerance)")
     args = ap.parse_args()
@@ -358,6 +398,9 @@ def main():
 
     if args.large_ellipsoid:
         print(json.dumps({"large_ellipsoid": large_ellipsoid(cbie, W)}))
+        return
+    if args.sphere_scaling:
+        sphere_scaling(cbie, W, [int(v) for v in args.sphere_scaling.split(",")])
         return
     spec = W.sphere_pec_ka20()
     kh, pol = W.plane_waves(16, seed=0)
@@ -442,6 +485,7 @@ def gemm_roofline(st, pipeline):
             "launches": st["gemm_launches"], "avg_launch_us": 1e6 * sec / max(st["gemm_launches"], 1),
             "flops_per_launch": st["gemm_flops_alg"] / max(st["gemm_launches"], 1),
             "executed_flops_per_launch": st["gemm_flops"] / max(st["gemm_launches"], 1),
+            "algorithmic_bytes_per_launch": st["gemm_bytes_alg"] / max(st["gemm_launches"], 1),
             "executed_tflops": st["gemm_flops"] / sec / 1e12 if sec > 0 else None,
             "kernel_seconds": sec}
 

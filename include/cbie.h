@@ -137,7 +137,8 @@ cbie_status cbie_compress(cbie_ctx* ctx, double aca_tol, cbie_rank_mode mode);
  * none across blocks; formatted updates truncated at the compress tolerance
  * (or the tolerance set by cbie_set_factor_tolerance) in the relative
  * Frobenius norm of each block, with the range basis of every truncation
- * built in FP64 in both precisions.
+ * built in FP64 in both precisions; a complex64 factor is truncated at no
+ * less than 1e-6 (below, its rounding noise would be kept as rank).
  * CBIE_PREC_C128: complex128 on FP64 MFMA.  CBIE_PREC_C64_IR: complex64 on
  * FP32 MFMA (FP32 accumulation); solve() then refines in FP64.
  * Errors: ESTATE, ENOMEM, EHIP, ESINGULAR. */
@@ -270,6 +271,10 @@ typedef struct {
     /* fill: kernel time of the far (Fejer-rule) entries of the dense blocks,
      * dense_entries complex128 values written */
     double far_fill_seconds;
+    /* algorithmic bytes of the batched GEMM launches since create: per
+     * product A (m k), B (k n), C read when beta != 0 and C written (m n),
+     * in the factor precision */
+    double gemm_bytes_alg;
 } cbie_stats;
 cbie_status cbie_get_stats(cbie_ctx* ctx, void* stats_out, size_t bytes);
 

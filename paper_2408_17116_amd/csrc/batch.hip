@@ -684,11 +684,11 @@ __global__ __launch_bounds__(256) void k_pchol_b(const PcholDesc<T>* __restrict_
     if ((int)blockIdx.x >= nd) return;
     const PcholDesc<T> D = descs[blockIdx.x];
     const int p = D.p;
-    cplx<T>* G = D.G;
+    constexpr int PL = PcholLds<T>::PL;
+    static_assert(PL * PL >= 4 * 512, "back-substitution vectors");
     __shared__ int perm[512];
+    __shared__ cplx<T> Gl[PL * PL];   // the matrix when p <= PL, else the vectors of the back substitution
     {
-        constexpr int PL = PcholLds<T>::PL;
-        __shared__ cplx<T> Gl[PL * PL];
         __shared__ cplx<T> xs[4 * PL];
         __shared__ unsigned wmax[4];
         __shared__ double red[4];
@@ -697,11 +697,13 @@ __global__ __launch_bounds__(256) void k_pchol_b(const PcholDesc<T>* __restrict_
             return;
         }
     }
+    // larger matrices in global memory, rows and columns swapped in place
+    const gptr<T> G = as_global(D.G);
     __shared__ double dv[4];
     __shared__ int di[4];
     __shared__ double dmax0;
     __shared__ int kk;
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     for (int i = tid; i < p; i += 256) perm[i] = i;
     if (tid == 0) {
         double m0 = 0.0;
@@ -736,46 +738,59 @@ __global__ __launch_bounds__(256) void k_pchol_b(const PcholDesc<T>* __restrict_
         // symmetric swap of rows/columns j and bi
         if (bi != j) {
             for (int t = tid; t < p; t += 256) {
-                const cplx<T> a = G[j + (int64_t)t * p];
-                G[j + (int64_t)t * p] = G[bi + (int64_t)t * p];
-                G[bi + (int64_t)t * p] = a;
+                const cplx<T> a = gld<T>(G + j + (int64_t)t * p);
+                gst<T>(G + j + (int64_t)t * p, gld<T>(G + bi + (int64_t)t * p));
+                gst<T>(G + bi + (int64_t)t * p, a);
             }
             __syncthreads();
             for (int t = tid; t < p; t += 256) {
-                const cplx<T> a = G[t + (int64_t)j * p];
-                G[t + (int64_t)j * p] = G[t + (int64_t)bi * p];
-                G[t + (int64_t)bi * p] = a;
+                const cplx<T> a = gld<T>(G + t + (int64_t)j * p);
+                gst<T>(G + t + (int64_t)j * p, gld<T>(G + t + (int64_t)bi * p));
+                gst<T>(G + t + (int64_t)bi * p, a);
             }
             if (tid == 0) { const int x = perm[j]; perm[j] = perm[bi]; perm[bi] = x; }
             __syncthreads();
         }
         // row j of R: R[j, j] = sqrt(G[j, j]), R[j, t] = G[j, t] / R[j, j]
         const T rjj = sqrt((T)bv);
-        for (int t = j + 1 + tid; t < p; t += 256) G[j + (int64_t)t * p] = (T(1) / rjj) * G[j + (int64_t)t * p];
+        for (int t = j + 1 + tid; t < p; t += 256)
+            gst<T>(G + j + (int64_t)t * p, (T(1) / rjj) * gld<T>(G + j + (int64_t)t * p));
         __syncthreads();
-        if (tid == 0) G[j + (int64_t)j * p] = cplx<T>{rjj, (T)0};
+        if (tid == 0) gst<T>(G + j + (int64_t)j * p, cplx<T>{rjj, (T)0});
         // trailing downdate G[t, u] -= conj(R[j, t]) R[j, u], t, u > j
         const int R = p - j - 1;
         for (int64_t e = tid; e < (int64_t)R * R; e += 256) {
             const int t = j + 1 + (int)(e % R), u = j + 1 + (int)(e / R);
-            cplx<T> v = G[t + (int64_t)u * p];
-            cfma(v, -conj(G[j + (int64_t)t * p]), G[j + (int64_t)u * p]);
-            G[t + (int64_t)u * p] = v;
+            cplx<T> v = gld<T>(G + t + (int64_t)u * p);
+            cfma(v, -conj(gld<T>(G + j + (int64_t)t * p)), gld<T>(G + j + (int64_t)u * p));
+            gst<T>(G + t + (int64_t)u * p, v);
         }
         __syncthreads();
     }
     __syncthreads();
     const int k = kk;
-    // S = Pi R_kk^{-1}: column j solves R x = e_j by back substitution
-    for (int64_t e = tid; e < (int64_t)p * p; e += 256) D.S[e] = bz<T>();
+    // S = Pi R_kk^{-1}: column j solves R x = e_j by back substitution, one
+    // wave per column with its lanes over the inner sums, x in LDS
+    const gptr<T> Sg = as_global(D.S);
+    for (int64_t e = tid; e < (int64_t)p * p; e += 256) gst<T>(Sg + e, bz<T>());
     __syncthreads();
-    for (int j = tid; j < k; j += 256) {
-        // x[t] for t <= j, kept in S (row perm[t], column j)
+    cplx<T>* x = Gl + wave * 512;
+    for (int j = wave; j < k; j += 4) {
         for (int t = j; t >= 0; --t) {
-            cplx<T> v = cplx<T>{(T)(t == j ? 1 : 0), (T)0};
-            for (int u = t + 1; u <= j; ++u) cfma(v, -G[t + (int64_t)u * p], D.S[perm[u] + (int64_t)j * p]);
-            D.S[perm[t] + (int64_t)j * p] = cdiv(v, G[t + (int64_t)t * p]);
+            cplx<T> acc = bz<T>();
+            for (int u = t + 1 + lane; u <= j; u += 64) cfma(acc, gld<T>(G + t + (int64_t)u * p), x[u]);
+            for (int off = 32; off > 0; off >>= 1) {
+                acc.re += __shfl_xor(acc.re, off);
+                acc.im += __shfl_xor(acc.im, off);
+            }
+            const cplx<T> num = cplx<T>{(T)(t == j ? 1 : 0), (T)0} - acc;
+            const cplx<T> xt = cdiv(num, gld<T>(G + t + (int64_t)t * p));
+            if (lane == 0) x[t] = xt;
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         }
+        for (int t = lane; t <= j; t += 64) gst<T>(Sg + perm[t] + (int64_t)j * p, x[t]);
+        __builtin_amdgcn_wave_barrier();
     }
     if (tid == 0) D.k_out[0] = k;
 }

@@ -294,6 +294,8 @@ template <typename T> struct HF {
     int max_level = -1;
     void* pinned = nullptr;
     size_t pinned_bytes = 0;
+    hipEvent_t staged_ev = nullptr;   // recorded after the last program's descriptor copy
+    int64_t staged_gen = -1;          // that program's launch number (-1: none)
 
     HF(Ctx& cc, double t) : c(cc), s(cc.stream), T_(cc.tree), tol(t) {}
     ~HF() {
@@ -302,6 +304,7 @@ template <typename T> struct HF {
         if (rank_pinned) (void)hipHostFree(rank_pinned);
         if (pinned) (void)hipHostFree(pinned);
         if (imm_pinned) (void)hipHostFree(imm_pinned);
+        if (staged_ev) (void)hipEventDestroy(staged_ev);
     }
 
     // host time spent waiting for the stream (debug statistics)
@@ -457,6 +460,7 @@ template <typename T> struct HF {
         std::vector<GemmDesc<T>> g[kNumTileShapes];
         std::vector<GemmTile> t[kNumTileShapes];
         double fl[kNumTileShapes] = {}, alg[kNumTileShapes] = {};
+        double by[kNumTileShapes] = {};   // algorithmic bytes: A, B, C read if beta != 0, C written
         std::vector<ReduceDesc<T>> rd;
         std::vector<CopyTile> rt;
         int64_t ws_left = int64_t(1) << 26;   // partial-product entries one launch may use
@@ -470,6 +474,8 @@ template <typename T> struct HF {
     void add_gemm(Batch& b, const GemmDesc<T>& d, int sh, bool forced, int64_t launch_tiles, Arena<T>& ws,
                   double alg = -1.0) {
         const double a = alg >= 0.0 ? alg : 8.0 * d.m * d.n * d.k;
+        const bool b0 = d.beta.re == (T)0 && d.beta.im == (T)0;
+        const double bytes = ((double)d.m * d.k + (double)d.k * d.n + (b0 ? 1.0 : 2.0) * d.m * d.n) * sizeof(cplx<T>);
         if (debug) {
             hist_fl[Tuner<T>::mb(d.m)][Tuner<T>::mb(d.n)][Tuner<T>::kb(d.k)] += 8.0 * d.m * d.n * d.k;
             ++hist_n[Tuner<T>::mb(d.m)][Tuner<T>::mb(d.n)][Tuner<T>::kb(d.k)];
@@ -480,6 +486,7 @@ template <typename T> struct HF {
         if (S <= 1) {
             b.fl[sh] += 8.0 * d.m * d.n * d.k;
             b.alg[sh] += a;
+            b.by[sh] += bytes;
             add_tiles(b.t[sh], (int)b.g[sh].size(), d, sh);
             b.g[sh].push_back(d);
             return;
@@ -487,6 +494,7 @@ template <typename T> struct HF {
         if (forced) sh = pick_shape(d.m, d.n, d.k);
         b.fl[sh] += 8.0 * d.m * d.n * d.k;
         b.alg[sh] += a;
+        b.by[sh] += bytes;
         const int64_t mn = (int64_t)d.m * d.n;
         b.ws_left -= mn * S;
         cplx<T>* W = ws.alloc((size_t)(mn * S));
@@ -567,7 +575,8 @@ template <typename T> struct HF {
 
     // one batched GEMM launch of fl flops (8 m n k per product) standing for
     // alg algorithmic flops, timed when profiling
-    void launch_gemm(const GemmDesc<T>* d, const GemmTile* t, int ntiles, int sh, double fl, double alg) {
+    void launch_gemm(const GemmDesc<T>* d, const GemmTile* t, int ntiles, int sh, double fl, double alg,
+                     double bytes) {
         Ctx::KernelTimer& tm = c.gemm_timer;
         if (tm.on) tm.begin(s);
         gemm_batched<T>(s, d, t, ntiles, sh);
@@ -576,6 +585,7 @@ template <typename T> struct HF {
         ++c.stats.gemm_launches;
         c.stats.gemm_flops += fl;
         c.stats.gemm_flops_alg += alg;
+        c.stats.gemm_bytes_alg += bytes;
     }
 
     // Dependency audit (CBIE_CHECK_DEPS).  From the memory each recorded
@@ -673,7 +683,7 @@ template <typename T> struct HF {
             size_t g[kNumTileShapes], gt[kNumTileShapes], r, rt, c, ct, l;
             double lfl;   // algorithmic flops of the level's leaf LUs (8/3 b^3 each)
             int ng[kNumTileShapes], ngt[kNumTileShapes], nr, nrt, nc, nct, nl;
-            double fl[kNumTileShapes], alg[kNumTileShapes];
+            double fl[kNumTileShapes], alg[kNumTileShapes], by[kNumTileShapes];
         };
         // the program that last used this workspace finished before the
         // previous program was staged
@@ -705,6 +715,7 @@ template <typename T> struct HF {
                 sg.ngt[sh] = (int)bt.t[sh].size();
                 sg.fl[sh] = bt.fl[sh];
                 sg.alg[sh] = bt.alg[sh];
+                sg.by[sh] = bt.by[sh];
             }
             sg.r = put(bt.rd.data(), bt.rd.size() * sizeof(ReduceDesc<T>));
             sg.rt = put(bt.rt.data(), bt.rt.size() * sizeof(CopyTile));
@@ -731,17 +742,34 @@ template <typename T> struct HF {
             sg.nl = (int)lf.size();
         }
         if (audit) audit_program();
-        if (host.size() > pinned_bytes) {
-            if (pinned) CBIE_HIP(hipHostFree(pinned));
-            pinned_bytes = std::max(host.size(), pinned_bytes * 2);
-            CBIE_HIP(hipHostMalloc(&pinned, pinned_bytes));
-        }
-        // the previous use of the staging buffers must be complete
-        wait_stream();
-        std::memcpy(pinned, host.data(), host.size());
         DBuf<char>& dev = rec_into ? rec_into->desc : descbuf;
-        if (dev.n < host.size()) dev.alloc(std::max(host.size(), (size_t)1 << 20));
+        if (host.size() > pinned_bytes || dev.n < host.size()) {
+            wait_stream();   // nothing in flight reads the buffers being replaced
+            if (host.size() > pinned_bytes) {
+                if (pinned) CBIE_HIP(hipHostFree(pinned));
+                pinned_bytes = std::max(host.size(), pinned_bytes * 2);
+                CBIE_HIP(hipHostMalloc(&pinned, pinned_bytes));
+            }
+            if (dev.n < host.size()) dev.alloc(std::max(host.size(), (size_t)1 << 20));
+        }
+        // The previous program's descriptors must have left the pinned
+        // buffer: wait for the event recorded after their copy.  That
+        // program's kernels may still run (they read the device copy, which
+        // this program's copy follows in stream order), so the host stages
+        // and launches this program while the GPU works; every program
+        // before the previous one has completed, which releases the factor
+        // storage they held.
+        if (staged_gen >= 0) {
+            const double t0 = now_s();
+            CBIE_HIP(hipEventSynchronize(staged_ev));
+            t_wait += now_s() - t0;
+            store.completed_through(staged_gen - 1);
+        }
+        std::memcpy(pinned, host.data(), host.size());
         CBIE_HIP(hipMemcpyAsync(dev.p, pinned, host.size(), hipMemcpyHostToDevice, s));
+        if (!staged_ev) CBIE_HIP(hipEventCreateWithFlags(&staged_ev, hipEventDisableTiming));
+        CBIE_HIP(hipEventRecord(staged_ev, s));
+        staged_gen = store.launches;   // the launch number this program gets
         auto keep = [&](std::function<void(hipStream_t)> f) {
             if (rec_into) rec_into->seq.push_back(std::move(f));
         };
@@ -764,7 +792,7 @@ template <typename T> struct HF {
                     const GemmDesc<T>* dg = (const GemmDesc<T>*)(dev.p + sg.g[sh]);
                     const GemmTile* dt = (const GemmTile*)(dev.p + sg.gt[sh]);
                     const int nt = sg.ngt[sh];
-                    launch_gemm(dg, dt, nt, sh, sg.fl[sh], sg.alg[sh]);
+                    launch_gemm(dg, dt, nt, sh, sg.fl[sh], sg.alg[sh], sg.by[sh]);
                     keep([=](hipStream_t st) { gemm_batched<T>(st, dg, dt, nt, sh); });
                 }
             if (sg.nrt) {
@@ -865,8 +893,8 @@ template <typename T> struct HF {
             const GemmDesc<T>* dg = stage_upload(bt.g[sh]);
             const GemmTile* dt = stage_upload(bt.t[sh]);
             const int nt = (int)bt.t[sh].size();
-            const double fl = bt.fl[sh], al = bt.alg[sh];
-            launch([=] { launch_gemm(dg, dt, nt, sh, fl, al); });
+            const double fl = bt.fl[sh], al = bt.alg[sh], by = bt.by[sh];
+            launch([=] { launch_gemm(dg, dt, nt, sh, fl, al, by); });
         }
         if (!bt.rt.empty()) {
             const ReduceDesc<T>* dr = stage_upload(bt.rd);
@@ -1874,7 +1902,14 @@ Ctx::Ctx() {}
 Ctx::~Ctx() {}
 
 template <typename T> static std::shared_ptr<HF<T>> make_factor(Ctx& c) {
-    auto f = std::make_shared<HF<T>>(c, c.factor_tol > 0.0 ? c.factor_tol : c.aca_tol);
+    // A complex64 factor is not truncated below 1e-6: its entries carry
+    // relative rounding ~6e-8 (more after the updates), so at tighter
+    // tolerances the rounding noise, which has full rank, would be kept.  The
+    // refinement against the stored FP64 operator recovers the compression
+    // tolerance.
+    double tol = c.factor_tol > 0.0 ? c.factor_tol : c.aca_tol;
+    if (sizeof(T) == 4) tol = std::max(tol, 1e-6);
+    auto f = std::make_shared<HF<T>>(c, tol);
     hipStream_t s = c.stream;
     const Tree& T_ = c.tree;
     f->dense.alloc(std::max<int64_t>(c.stats.dense_entries, 1));

@@ -19,7 +19,9 @@ namespace cbie {
 // released buffer may still be read or written by tasks recorded before its
 // release, so it is reused only after the stream has completed them:
 // released while a program is being recorded -> waiting for that program's
-// launch -> free once the stream has been synchronized after the launch.
+// launch (tagged with its launch number) -> free once the stream has
+// completed that program (completed_through) or has been synchronized
+// (completed).
 template <typename E, typename Chunk> struct FactorPool {
     using P = E*;
     struct Range {
@@ -30,7 +32,14 @@ template <typename E, typename Chunk> struct FactorPool {
     std::map<P, int> chunk_at;                    // chunk base -> index
     std::map<P, Range> free_at;                   // free ranges by address
     std::set<std::pair<size_t, P>> free_by_size;  // the same, by size
-    std::vector<std::pair<P, size_t>> rec, run;
+    struct Pending {
+        P p;
+        size_t n;
+        int64_t gen;   // launch number of the program it waits for
+    };
+    std::vector<std::pair<P, size_t>> rec;
+    std::vector<Pending> run;
+    int64_t launches = 0;   // programs launched so far (the next one gets this number)
     size_t chunk_elems = size_t(1) << 26;
     size_t live = 0, peak = 0;
     static size_t rounded(size_t n) { return std::max<size_t>(32, (n + 31) & ~size_t(31)); }
@@ -88,16 +97,24 @@ template <typename E, typename Chunk> struct FactorPool {
         live -= n;
     }
     void launched() {
-        run.insert(run.end(), rec.begin(), rec.end());
+        for (const auto& x : rec) run.push_back(Pending{x.first, x.second, launches});
         rec.clear();
+        ++launches;
     }
-    void completed() {
-        for (auto& x : run) {
-            auto c = std::prev(chunk_at.upper_bound(x.first));
-            add_free(x.first, x.second, c->second);
+    // every program with launch number <= g has completed on the stream
+    void completed_through(int64_t g) {
+        size_t keep = 0;
+        for (size_t i = 0; i < run.size(); ++i) {
+            if (run[i].gen <= g) {
+                auto c = std::prev(chunk_at.upper_bound(run[i].p));
+                add_free(run[i].p, run[i].n, c->second);
+            } else {
+                run[keep++] = run[i];
+            }
         }
-        run.clear();
+        run.resize(keep);
     }
+    void completed() { completed_through(launches - 1); }
     double capacity() const {
         double c = 0;
         for (const auto& b : chunks) c += (double)b.n;

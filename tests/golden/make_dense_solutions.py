@@ -17,6 +17,8 @@ assembly at full size and the solution against the matrix it solves.
     python tests/golden/make_dense_solutions.py dielectric      # 24576 unknowns
     python tests/golden/make_dense_solutions.py batch_subset    # 4 seeded objects of the 64-ellipsoid batch
     python tests/golden/make_dense_solutions.py resonance       # 38400 unknowns, eps_d 10.5074 (Sec. IV-B)
+    python tests/golden/make_dense_solutions.py stretched       # 12288 unknowns: the 196,608-unknown ellipsoid's
+                                                                # shape and patch size, scaled down 4x
 """
 from __future__ import annotations
 
@@ -142,6 +144,11 @@ def main():
         kh, pol = W.axial_wave()
         x, rec = dense_solve(spec, kh, pol)
         np.savez(os.path.join(HERE, "resonance_38400_dense.npz"), x=x, khat=kh, pol=pol, **rec)
+    elif which == "stretched":
+        spec = W.ObjectSpec(axes=(2.0, 1.0, 0.5), center=(0.0, 0.0, 0.0), s=4, q=8, k0=5.0)
+        kh, pol = W.plane_waves(1, seed=0)
+        x, rec = dense_solve(spec, kh, pol)
+        np.savez(os.path.join(HERE, "stretched_ellipsoid_12288_dense.npz"), x=x, khat=kh, pol=pol, **rec)
     else:
         raise SystemExit(f"unknown workload {which}")
 

@@ -50,7 +50,11 @@ int check(const Pool& P, const std::vector<Live>& live, std::vector<std::pair<do
         if (nx != P.free_at.end() && nx->second.chunk == f.second.chunk) return 3;
     }
     for (const auto& x : P.rec) { iv.push_back(x); pend += x.second; }
-    for (const auto& x : P.run) { iv.push_back(x); pend += x.second; }
+    for (const auto& x : P.run) {
+        iv.push_back({x.p, x.n});
+        pend += x.n;
+        if (x.gen < 0 || x.gen >= P.launches) return 8;   // waits for a program that was launched
+    }
     std::sort(iv.begin(), iv.end());
     for (size_t k = 1; k < iv.size(); ++k)
         if (iv[k].first < iv[k - 1].first + iv[k - 1].second) return 4;   // overlap
@@ -83,8 +87,16 @@ extern "C" int pool_random(unsigned seed, int steps, size_t chunk_elems, size_t 
             P.release(live[i].p, live[i].n);
             live.erase(live.begin() + i);
         } else {
+            // a launch; then the stream has passed every program, or all but
+            // the last one (an event after the previous program), or none
             P.launched();
-            if (g() % 2) P.completed();
+            const int r = (int)(g() % 3);
+            if (r == 1) P.completed();
+            if (r == 2) {
+                P.completed_through(P.launches - 2);
+                for (const auto& x : P.run)
+                    if (x.gen != P.launches - 1) return 9;   // only the last program's releases remain
+            }
         }
         if (const int e = check(P, live, iv)) return 100 * e + 0 * it;
     }

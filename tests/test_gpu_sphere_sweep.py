@@ -1,24 +1,18 @@
 """The 20-wavelength-diameter PEC sphere of the paper's accuracy study
-(Sec. IV, Table 1): radius 10 m at wavelength 1 m (ka = 20 pi), ACA
-tolerance 1e-4, plane wave along +z polarized along +x.  The H-LU solution
-(complex64 with FP64 refinement) is compared with the Mie series: relative
-L2 error of the surface current, quadrature-weighted over the nodes.
+(Sec. IV-A, Table 1): radius 10 m at wavelength 1 m (ka = 20 pi), ACA
+tolerance 1e-4, plane wave along +z polarized along +x, 10 x 10 points per
+patch.  The cube-sphere faces split s x s give exactly the table's four
+unknown counts at q = 10: s = 6, 8, 10, 12 -> 216, 384, 600, 864 patches ->
+43,200, 76,800, 120,000, 172,800 unknowns.  The H-LU solution (complex64
+with FP64 refinement) is compared with the Mie series: relative L2 error of
+the surface current, quadrature-weighted over the nodes.
 
-The paper uses 10 x 10 points per patch; the library takes q <= 8, and
-q = 8 with more patches (cube-sphere faces split s x s) gives the same
-numbers of unknowns for two of the table's four columns: 76,800 (s = 10,
-patches 1.57 wavelengths across) and 172,800 (s = 15).  The errors are
-above the paper's (6.1e-2 at 76,800 against its 1.41e-2).  Both sample
-about 5.1 points per wavelength; at a fixed patch size the error grows with
-the electrical size (the oracle's own dense solution with the same
-1.57-wavelength patches: 2.7e-3 at ka = 4 pi, 7.3e-3 at ka = 8 pi), and the
-higher order explains part of the gap, not all of it (the paper states
-neither its patching nor its error norm).  The bound, 0.07, is a
-regression bound above the measured 6.5e-2 (49,152) and 6.1e-2 (76,800),
-not the paper's figure, which is printed beside the result.  The 172,800
-case takes a few minutes and runs only with CBIE_LARGE_TESTS=1."""
-import os
-
+The table's errors of the proposed solver (1.91e-1, 1.41e-2, 6.69e-3,
+2.13e-3) fall by about 2.2x from each column to the next, the spectral
+convergence of the discretization.  The test asserts the same convergence
+(each error below half the previous one) and every error within 3x of the
+table's: the paper states neither its patching nor the norm of its error,
+so an exact match is not expected."""
 import numpy as np
 import pytest
 
@@ -27,35 +21,38 @@ from synth import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-KA = 20.0 * np.pi
-PAPER = {76800: 1.41e-2, 172800: 2.13e-3}   # Table 1, proposed solver
+TABLE1 = {43200: 1.91e-1, 76800: 1.41e-2, 120000: 6.69e-3, 172800: 2.13e-3}   # proposed solver
 
 
-@pytest.mark.parametrize("s", [8, 10, 15], ids=["N49152", "N76800", "N172800"])
-def test_twenty_wavelength_sphere_against_mie(s):
+def test_twenty_wavelength_sphere_at_order_ten_against_mie():
     import torch
     from paper_2408_17116_amd import cbie
-    if s == 15 and os.environ.get("CBIE_LARGE_TESTS") != "1":
-        pytest.skip("172,800 unknowns: set CBIE_LARGE_TESTS=1")
-    spec = W.ObjectSpec(axes=(10.0, 10.0, 10.0), center=(0.0, 0.0, 0.0), s=s, q=8, k0=2.0 * np.pi)
-    N = spec.n_unknowns
-    s_ = cbie.Solver([spec])
-    s_.build_tree(leaf_size=256, eta=1.0, near_delta=1.0)
-    s_.fill()
-    s_.compress(1e-4)
-    s_.factor(cbie.PREC_C64_IR)
-    kh, pol = W.axial_wave()
-    b = s_.rhs_planewave(kh, pol)
-    x, it = s_.solve(b, tol=1e-10, maxit=30)
-    res = (torch.linalg.norm(s_.matvec(x) - b) / torch.linalg.norm(b)).item()
-    st = s_.stats()
-    s_.close()
-    nd = G.build_nodes(spec)
-    J = post.surface_current(nd, x.cpu().numpy()[:, 0])
-    Jm = mie.pec_surface_current(spec.k0, 10.0, nd.r)
-    err = post.weighted_rel_l2(nd, J, Jm)
-    print(f"N {N}: max rank {st['max_rank']}, CR {st['compression_rate']:.3f}, fill {st['t_fill']:.2f} s, "
-          f"compress {st['t_compress']:.2f} s, factor {st['t_factor']:.2f} s, solve {st['t_solve']:.2f} s "
-          f"({it} sweeps), residual {res:.1e}; J vs Mie {err:.3e} (paper {PAPER.get(N)})", flush=True)
-    assert res < 1e-8
-    assert err < 0.07
+    errs = {}
+    for s in (6, 8, 10, 12):
+        spec = W.ObjectSpec(axes=(10.0, 10.0, 10.0), center=(0.0, 0.0, 0.0), s=s, q=10, k0=2.0 * np.pi)
+        N = spec.n_unknowns
+        sv = cbie.Solver([spec])
+        sv.build_tree(leaf_size=256, eta=1.0, near_delta=1.0)
+        sv.fill()
+        sv.compress(1e-4)
+        sv.factor(cbie.PREC_C64_IR)
+        kh, pol = W.axial_wave()
+        b = sv.rhs_planewave(kh, pol)
+        x, it = sv.solve(b, tol=1e-10, maxit=30)
+        res = (torch.linalg.norm(sv.matvec(x) - b) / torch.linalg.norm(b)).item()
+        st = sv.stats()
+        sv.close()
+        nd = G.build_nodes(spec)
+        J = post.surface_current(nd, x.cpu().numpy()[:, 0])
+        Jm = mie.pec_surface_current(spec.k0, 10.0, nd.r)
+        errs[N] = post.weighted_rel_l2(nd, J, Jm)
+        print(f"N {N} ({6 * s * s} patches, q 10): max rank {st['max_rank']}, CR {st['compression_rate']:.3f}, "
+              f"fill {st['t_fill']:.2f} s, compress {st['t_compress']:.2f} s, factor {st['t_factor']:.2f} s, "
+              f"solve {st['t_solve']:.2f} s ({it} sweeps), residual {res:.1e}; J vs Mie {errs[N]:.3e} "
+              f"(Table 1: {TABLE1[N]:.2e})", flush=True)
+        assert res < 1e-8
+    ns = sorted(errs)
+    for a, b in zip(ns, ns[1:]):
+        assert errs[b] < 0.5 * errs[a], (a, b)
+    for n in ns:
+        assert errs[n] < 3.0 * TABLE1[n], n
