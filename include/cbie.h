@@ -189,6 +189,18 @@ cbie_status cbie_solve_gmres(cbie_ctx* ctx, int nrhs, const void* b_dev, void* x
  * nrhs columns, original order, leading dimension ld.  Errors: ESTATE, EINVAL, EHIP. */
 cbie_status cbie_matvec(cbie_ctx* ctx, int nrhs, const void* x_dev, void* y_dev, long ld);
 
+/* The same product as cbie_matvec, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): the call allocates nothing and works in a scratch array
+ * that the library holds on each GPU for the life of the process, 2^23
+ * complex128 elements (128 MiB).  One call needs (2 n_unknowns + sum of the
+ * low-rank ranks) * nrhs elements (the ranks from compress: cbie_stats
+ * sum_rank); larger calls return EINVAL and do nothing.  Every context on a
+ * GPU shares that GPU's array, which keeps the last call's contents: calls
+ * that overlap on one GPU (other threads, other streams) race and must be
+ * serialized by the caller.  Errors: ESTATE, EINVAL, EHIP. */
+cbie_status cbie_matvec_noalloc(cbie_ctx* ctx, int nrhs, const void* x_dev, void* y_dev, long ld);
+
 /* Right-hand sides of eq. (22) for nw plane waves E = pol e^{-j k khat.r},
  * H = khat x E: b_u = -a_v . H, b_v = a_u . H per node; N-Mueller objects
  * (eq. 19, exterior vacuum) add the electric rows -a_v . E, a_u . E after

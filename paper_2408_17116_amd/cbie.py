@@ -25,7 +25,7 @@ EXPORTED = ["cbie_create", "cbie_build_tree", "cbie_fill", "cbie_compress", "cbi
             "cbie_solve", "cbie_matvec", "cbie_rhs_planewave", "cbie_farfield", "cbie_get_stats",
             "cbie_set_profiling", "cbie_get_near_pairs", "cbie_export_dense", "cbie_last_error",
             "cbie_destroy", "cbie_get_block_features", "cbie_set_rank_model", "cbie_mlp_forward",
-            "cbie_mlp_grad", "cbie_mlp_train", "cbie_solve_gmres",
+            "cbie_mlp_grad", "cbie_mlp_train", "cbie_matvec_noalloc", "cbie_solve_gmres",
             "cbie_set_factor_tolerance"]
 
 MLP_NFEAT, MLP_NPARAMS = 8, 4801
@@ -84,6 +84,7 @@ def load(path: str = LIB_PATH):
         "cbie_factor": ([vp, i32], i32),
         "cbie_solve": ([vp, i32, vp, vp, C.c_long, dbl, i32, C.POINTER(i32)], i32),
         "cbie_matvec": ([vp, i32, vp, vp, C.c_long], i32),
+        "cbie_matvec_noalloc": ([vp, i32, vp, vp, C.c_long], i32),
         "cbie_solve_gmres": ([vp, i32, vp, vp, C.c_long, dbl, i32, i32, C.POINTER(i32)], i32),
         "cbie_set_factor_tolerance": ([vp, dbl], i32),
         "cbie_rhs_planewave": ([vp, i32, vp, vp, vp, C.c_long], i32),
@@ -217,6 +218,15 @@ class Solver:
         xc = self._cols(x)
         y = self.torch.empty_like(xc)
         self._check(self.lib.cbie_matvec(self.h, xc.shape[0], _ptr(xc), _ptr(y), self.n))
+        return y.t()
+
+    def matvec_noalloc(self, x, y=None):
+        """y = A_H x through the allocation-free entry point; y (same shape
+        as the (m, n) column block of x) may be passed in."""
+        xc = self._cols(x)
+        if y is None:
+            y = self.torch.empty_like(xc)
+        self._check(self.lib.cbie_matvec_noalloc(self.h, xc.shape[0], _ptr(xc), _ptr(y), self.n))
         return y.t()
 
     def rhs_planewave(self, khat, pol):

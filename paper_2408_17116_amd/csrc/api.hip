@@ -4,6 +4,7 @@
 
 #include "ctx.hpp"
 #include "mlp.hpp"
+#include "ops.hpp"
 
 struct cbie_ctx {
     cbie::Ctx c;
@@ -125,6 +126,7 @@ cbie_status cbie_create(const cbie_object* objs, int n_objs, void* hip_stream, c
         c.d_obj_patch0.upload(c.obj_patch0, c.stream);
         c.d_obj_npatch.upload(c.obj_npatch, c.stream);
         make_fejer_tables(c);
+        resolve_scratch(c.device);
         c.sync();
         c.state = ST_CREATED;
     });
@@ -216,6 +218,15 @@ cbie_status cbie_matvec(cbie_ctx* ctx, int nrhs, const void* x_dev, void* y_dev,
         CBIE_REQUIRE(nrhs > 0 && x_dev && y_dev && ld >= c.n_unk && x_dev != y_dev, CBIE_EINVAL,
                      "matvec arguments");
         stage_matvec(c, nrhs, (const zd*)x_dev, (zd*)y_dev, ld);
+    });
+}
+
+cbie_status cbie_matvec_noalloc(cbie_ctx* ctx, int nrhs, const void* x_dev, void* y_dev, long ld) {
+    return guarded(ctx, [&](Ctx& c) {
+        CBIE_REQUIRE(c.state >= ST_COMPRESSED, CBIE_ESTATE, "matvec before compress");
+        CBIE_REQUIRE(nrhs > 0 && x_dev && y_dev && ld >= c.n_unk && x_dev != y_dev, CBIE_EINVAL,
+                     "matvec arguments");
+        stage_matvec_noalloc(c, nrhs, (const zd*)x_dev, (zd*)y_dev, ld);
     });
 }
 

@@ -202,6 +202,54 @@ void stage_matvec(Ctx& c, int nrhs, const zd* x, zd* y, long ld) {
     c.sync();
 }
 
+// ------------------------------------------------ allocation-free matvec
+// One scratch array per GPU for callers that cannot allocate.  Host code
+// never passes the array's name to a kernel (on the host it is only a
+// stand-in): its device address is resolved once per device by
+// resolve_scratch() and kept in g_scratch.
+static __device__ __align__(256) zd scratch[kScratchElems];
+
+static std::mutex g_scratch_mu;
+static std::vector<zd*> g_scratch;   // device -> address of that device's scratch
+
+void resolve_scratch(int device) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if ((int)g_scratch.size() <= device) g_scratch.resize(device + 1, nullptr);
+    if (g_scratch[device]) return;
+    void* p = nullptr;
+    CBIE_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    CBIE_REQUIRE(p != nullptr, CBIE_EHIP, "scratch symbol has no device address");
+    g_scratch[device] = (zd*)p;
+}
+
+int64_t matvec_scratch_elems(const Ctx& c, int nrhs) {
+    return (2 * c.n_unk + (c.lr_prefix.empty() ? 0 : c.lr_prefix.back())) * (int64_t)nrhs;
+}
+
+void stage_matvec_noalloc(Ctx& c, int nrhs, const zd* x, zd* y, long ld) {
+    const int64_t N = c.n_unk;
+    const int64_t need = matvec_scratch_elems(c, nrhs);
+    CBIE_REQUIRE(need <= kScratchElems, CBIE_EINVAL,
+                 "matvec_noalloc: needs " + std::to_string(need) + " complex128 scratch elements, the limit is " +
+                     std::to_string(kScratchElems) + " (fewer right-hand sides per call, or cbie_matvec)");
+    zd* base = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_scratch_mu);
+        if (c.device < (int)g_scratch.size()) base = g_scratch[c.device];
+    }
+    CBIE_REQUIRE(base != nullptr, CBIE_EHIP, "scratch address not resolved for this device");
+    zd* xt = base;
+    zd* yt = base + N * nrhs;
+    zd* tmp = yt + N * nrhs;
+    const unsigned g = ceil_div(N * nrhs, 256);
+    k_to_tree<double><<<g, 256, 0, c.stream>>>(c.d_tree_node.p, c.upn, N, nrhs, x, ld, xt);
+    check_launch("k_to_tree");
+    apply_operator_tree_into(c, nrhs, xt, yt, tmp);
+    k_from_tree<double><<<g, 256, 0, c.stream>>>(c.d_tree_node.p, c.upn, N, nrhs, yt, y, ld);
+    check_launch("k_from_tree");
+    c.sync();
+}
+
 // ------------------------------------------------------ RHS (eqs. 19, 22)
 // MFIE: b_u = -a_v . H_inc, b_v = a_u . H_inc.  N-Mueller (rows H_u, H_v,
 // E_u, E_v of a node): -a_v . H_inc, a_u . H_inc, -a_v . E_inc, a_u . E_inc.
