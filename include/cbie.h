@@ -138,7 +138,8 @@ cbie_status cbie_compress(cbie_ctx* ctx, double aca_tol, cbie_rank_mode mode);
  * (or the tolerance set by cbie_set_factor_tolerance) in the relative
  * Frobenius norm of each block, with the range basis of every truncation
  * built in FP64 in both precisions; a complex64 factor is truncated at no
- * less than 1e-6 (below, its rounding noise would be kept as rank).
+ * less than 1e-5 (closer to its rounding noise, the noise would be kept as
+ * rank).
  * CBIE_PREC_C128: complex128 on FP64 MFMA.  CBIE_PREC_C64_IR: complex64 on
  * FP32 MFMA (FP32 accumulation); solve() then refines in FP64.
  * Errors: ESTATE, ENOMEM, EHIP, ESINGULAR. */
@@ -287,6 +288,12 @@ typedef struct {
      * product A (m k), B (k n), C read when beta != 0 and C written (m n),
      * in the factor precision */
     double gemm_bytes_alg;
+    /* matrix-core flops of the batched GEMM launches since create: 8 m n k
+     * per product, 6 m n k for complex64 products on 64 x 64 tiles, which
+     * form the complex product from three real ones (P1 = Ar Br,
+     * P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi); Cr = P1 - P2, Ci = P3 - P1 - P2;
+     * CBIE_GEMM_3M=0 selects the four-product form) */
+    double gemm_flops_mfma;
 } cbie_stats;
 cbie_status cbie_get_stats(cbie_ctx* ctx, void* stats_out, size_t bytes);
 

@@ -61,7 +61,8 @@ class Stats(C.Structure):
         ("aca_unconverged", C.c_int64), ("gemm_flops_alg", C.c_double), ("factor_flops_executed", C.c_int64),
         ("leaf_lu_launches", C.c_int64), ("leaf_lu_flops", C.c_double), ("leaf_lu_seconds", C.c_double),
         ("quad_points", C.c_double), ("quad_flops", C.c_double),
-        ("solve_factor_bytes", C.c_double), ("far_fill_seconds", C.c_double), ("gemm_bytes_alg", C.c_double)]
+        ("solve_factor_bytes", C.c_double), ("far_fill_seconds", C.c_double), ("gemm_bytes_alg", C.c_double),
+        ("gemm_flops_mfma", C.c_double)]
 
 
 _lib = None

@@ -63,6 +63,17 @@ __device__ inline void far_pair(const NodeArrays& nd, double k, int gi, int gj, 
         for (int a = 0; a < 2; ++a) K[b][a] = zd{w * K[b][a].re, w * K[b][a].im};
 }
 
+// N-Mueller far entries of one (target node, source node) pair: the twelve
+// kernel values times the source weight, and the weighted divergence
+// weights w phi[b] (eqs. 7-9, 19; rows H_u, H_v, E_u, E_v).
+__device__ inline void nm_far_pair(const NmMat& M, const NodeArrays& nd, int gi, int gj, NmVals& K, double& w) {
+    nm_kernel(M, v3(nd.rx[gi] - nd.rx[gj], nd.ry[gi] - nd.ry[gj], nd.rz[gi] - nd.rz[gj]),
+              v3(nd.aux[gi], nd.auy[gi], nd.auz[gi]), v3(nd.avx[gi], nd.avy[gi], nd.avz[gi]),
+              v3(nd.aux[gj], nd.auy[gj], nd.auz[gj]), v3(nd.avx[gj], nd.avy[gj], nd.avz[gj]), K);
+    w = nd.w[gj];
+}
+__device__ inline int nm_dmat_offset(int q) { return (q - 1) * q * (2 * q - 1) / 6; }
+
 // One work-group of 256 threads per admissible block M (m x n, m = 2 row
 // nodes, n = 2 column nodes), M ~ sum_k u_k v_k^T:
 //   row i_k -> residual row r (written into V[:, k]); pivot j_k = argmax |r|
@@ -70,20 +81,31 @@ __device__ inline void far_pair(const NodeArrays& nd, double k, int gi, int gj, 
 //   v_k = r / r[j_k]; u_k = residual column j_k (written into U[:, k]);
 //   |S_k|^2 += 2 Re sum_{l<k} (u_l^H u_k)(v_l^H v_k) + |u_k|^2 |v_k|^2;
 //   stop when |u_k| |v_k| <= tol |S_k|, else i_{k+1} = argmax |u_k| over
-//   unused rows.  MFIE entries are generated on the fly from the far rule
-//   (an admissible block holds no near pair); with `dense` set, the block
-//   is read from its explicit copy (column-major m x n at J.a_off).
+//   unused rows.  Entries are generated on the fly from the far rule (an
+//   admissible block holds no near pair), or, for an N-Mueller block with
+//   J.a_off >= 0, read from its explicit copy (column-major m x n in
+//   `dense`).  N-Mueller entries on the fly: the surface divergence of the
+//   source couples an entry of column (j = (k, l), a) to the divergence
+//   weights of the nodes on the source patch's line through j, through the
+//   differentiation matrix D (u: sum_m D[m][l] w phi(k, m); v: sum_m D[m][k]
+//   w phi(m, l)).  A row takes one kernel evaluation per column node (the
+//   weights of the row's component staged in the job's phi scratch); a
+//   column takes q per row node.
 __global__ __launch_bounds__(256) void k_aca(const AcaJob* __restrict__ jobs, int n_jobs,
                                              const int* __restrict__ tree_node, NodeArrays nd,
                                              const ObjDev* __restrict__ objs, double tol,
                                              zd* __restrict__ ws, unsigned char* __restrict__ used_ws,
                                              int* __restrict__ rank_out, int* __restrict__ flag_out,
-                                             const zd* __restrict__ dense) {
+                                             const zd* __restrict__ dense, const PatchDev* __restrict__ patches,
+                                             const int* __restrict__ node_patch, const double* __restrict__ dmat) {
     const int jb = blockIdx.x;
     if (jb >= n_jobs) return;
     const AcaJob J = jobs[jb];
     const int m = J.upn * J.row_nodes, n = J.upn * J.col_nodes;
-    const zd* A = dense ? dense + J.a_off : nullptr;
+    const zd* A = (dense && J.a_off >= 0) ? dense + J.a_off : nullptr;
+    const bool nm = J.upn == 4;
+    const NmMat M = nm_mat(objs[J.obj]);
+    zd* phi = ws + J.phi_off;   // N-Mueller row step: w phi of the row's component per column node
     zd* U = ws + J.u_off;   // m x cap
     zd* V = ws + J.v_off;   // n x cap
     unsigned char* used = used_ws + J.used_off;
@@ -114,6 +136,45 @@ __global__ __launch_bounds__(256) void k_aca(const AcaJob* __restrict__ jobs, in
                 for (int l = 0; l < rank; ++l) r = r - s_coef[l] * V[(int64_t)l * n + j];
                 vk[j] = r;
                 am = better(am, ArgMax{abs2(r), j});
+            }
+        } else if (nm) {
+            const int gi = tree_node[J.row_node0 + irow / 4];
+            const int cr = irow & 3, b = cr & 1;
+            const bool isE = cr >= 2;
+            // pass 1: the entries without the divergence term, and w phi[b]
+            for (int jn = tid; jn < J.col_nodes; jn += 256) {
+                const int gj = tree_node[J.col_node0 + jn];
+                NmVals K;
+                double w;
+                nm_far_pair(M, nd, gi, gj, K, w);
+                phi[jn] = w * K.phi[b];
+                for (int a = 0; a < 2; ++a) {
+                    vk[4 * jn + a] = w * (isE ? K.X0[b][a] : K.CH[b][a]);
+                    vk[4 * jn + 2 + a] = w * (isE ? K.CE[b][a] : K.X0[b][a]);
+                }
+            }
+            __syncthreads();
+            // pass 2: divergence terms on the X entries, residual, pivot
+            for (int jn = tid; jn < J.col_nodes; jn += 256) {
+                const int gj = tree_node[J.col_node0 + jn];
+                const PatchDev P = patches[node_patch[gj]];
+                const int q = P.q, loc = gj - P.node0, kk = loc / q, ll = loc % q, base = jn - loc;
+                const double* Dq = dmat + nm_dmat_offset(q);
+                zd su{0.0, 0.0}, sv{0.0, 0.0};
+                for (int mm = 0; mm < q; ++mm) {
+                    cfma(su, zd{Dq[mm * q + ll], 0.0}, phi[base + kk * q + mm]);
+                    cfma(sv, zd{Dq[mm * q + kk], 0.0}, phi[base + mm * q + ll]);
+                }
+                const int xs = isE ? 0 : 2;   // slots of the X entries (a = 0, 1)
+                vk[4 * jn + xs] = vk[4 * jn + xs] + su;
+                vk[4 * jn + xs + 1] = vk[4 * jn + xs + 1] + sv;
+                for (int a = 0; a < 4; ++a) {
+                    const int j = 4 * jn + a;
+                    zd r = vk[j];
+                    for (int l = 0; l < rank; ++l) r = r - s_coef[l] * V[(int64_t)l * n + j];
+                    vk[j] = r;
+                    am = better(am, ArgMax{abs2(r), j});
+                }
             }
         } else {
             const int gi = tree_node[J.row_node0 + irow / 2];
@@ -161,6 +222,52 @@ __global__ __launch_bounds__(256) void k_aca(const AcaJob* __restrict__ jobs, in
                 uk[i] = c;
                 nu2 += abs2(c);
                 if (!used[i]) nx = better(nx, ArgMax{abs2(c), i});
+            }
+        } else if (nm) {
+            const int gj = tree_node[J.col_node0 + jp / 4];
+            const int a = jp & 3, ap = a & 1;
+            const bool isM = a >= 2;
+            const PatchDev P = patches[node_patch[gj]];
+            const int q = P.q, loc = gj - P.node0, kk = loc / q, ll = loc % q;
+            const double* Dq = dmat + nm_dmat_offset(q);
+            for (int in = tid; in < J.row_nodes; in += 256) {
+                const int gi2 = tree_node[J.row_node0 + in];
+                NmVals K;
+                double w;
+                nm_far_pair(M, nd, gi2, gj, K, w);
+                // divergence terms of both row components b: the weights on
+                // the source patch's line through j (direction ap)
+                zd d0{0.0, 0.0}, d1{0.0, 0.0};
+                for (int mm = 0; mm < q; ++mm) {
+                    const int lm = ap == 0 ? kk * q + mm : mm * q + ll;
+                    const double dc = Dq[mm * q + (ap == 0 ? ll : kk)];
+                    zd p0, p1;
+                    if (lm == loc) {
+                        p0 = w * K.phi[0];
+                        p1 = w * K.phi[1];
+                    } else {
+                        NmVals Km;
+                        double wm;
+                        nm_far_pair(M, nd, gi2, P.node0 + lm, Km, wm);
+                        p0 = wm * Km.phi[0];
+                        p1 = wm * Km.phi[1];
+                    }
+                    cfma(d0, zd{dc, 0.0}, p0);
+                    cfma(d1, zd{dc, 0.0}, p1);
+                }
+                const int ac = isM ? a - 2 : a;
+                for (int cr = 0; cr < 4; ++cr) {
+                    const int b = cr & 1;
+                    const bool isE = cr >= 2;
+                    zd c;
+                    if (!isM) c = isE ? w * K.X0[b][ac] + (b ? d1 : d0) : w * K.CH[b][ac];
+                    else c = isE ? w * K.CE[b][ac] : w * K.X0[b][ac] + (b ? d1 : d0);
+                    const int i = 4 * in + cr;
+                    for (int l = 0; l < rank; ++l) c = c - s_coef[l] * U[(int64_t)l * m + i];
+                    uk[i] = c;
+                    nu2 += abs2(c);
+                    if (!used[i]) nx = better(nx, ArgMax{abs2(c), i});
+                }
             }
         } else {
             const int gj = tree_node[J.col_node0 + jp / 2];
@@ -264,9 +371,12 @@ __global__ void k_export_lr(const DenseBlockDev* __restrict__ blocks, int n_bloc
 // (U: m x width and V: n x width per block) stays within a budget
 // (CBIE_ACA_BUDGET elements, default 2^30); each round's factors are packed
 // (U then V, rank columns each) into a buffer of their own before the
-// workspace is reused.  N-Mueller blocks are filled explicitly per round
-// (the surface divergence couples whole source patches), at most kAcaDense
-// entries, and compressed from their copies.
+// workspace is reused.  N-Mueller blocks whose shorter side is below
+// CBIE_NM_OTF_MIN unknowns (default 2048) are filled explicitly per round, at
+// most kAcaDense entries, and compressed from their copies; larger ones get
+// their entries on the fly (a column costs q kernel evaluations per row: the
+// surface divergence couples the source patch's line, so the explicit copy
+// is cheaper for small blocks).
 struct AcaPass {
     std::vector<int> rank, flag;
     std::vector<int> round;        // per block: the buffer holding its factors
@@ -279,6 +389,8 @@ static void aca_pass(Ctx& c, double tol, const std::vector<int>& blocks, const s
     const int nb = (int)blocks.size();
     const char* eb = getenv("CBIE_ACA_BUDGET");
     const int64_t budget = eb ? std::max<int64_t>(1, atoll(eb)) : int64_t(1) << 30;
+    const char* eo = getenv("CBIE_NM_OTF_MIN");
+    const int64_t otf_min = eo ? std::max<int64_t>(0, atoll(eo)) : 2048;
     P.rank.assign(nb, 0);
     P.flag.assign(nb, 0);
     P.round.assign(nb, -1);
@@ -297,8 +409,10 @@ static void aca_pass(Ctx& c, double tol, const std::vector<int>& blocks, const s
         while (q1 < nb) {
             const DenseBlockDev& d = c.lblk[blocks[q1]];
             const int m = d.upn * d.row_nodes, n = d.upn * d.col_nodes;
-            const int64_t w = (int64_t)(m + n) * width[q1];
-            const int64_t e = c.upn == 4 ? (int64_t)m * n : 0;
+            const bool explicit_nm = c.upn == 4 && std::min(m, n) < otf_min;
+            const bool otf_nm = c.upn == 4 && !explicit_nm;
+            const int64_t w = (int64_t)(m + n) * width[q1] + (otf_nm ? d.col_nodes : 0);
+            const int64_t e = explicit_nm ? (int64_t)m * n : 0;
             if (q1 > q0 && (off + w > budget || doff + e > kAcaDense)) break;
             AcaJob J{};
             J.row_node0 = d.row_node0;
@@ -312,9 +426,15 @@ static void aca_pass(Ctx& c, double tol, const std::vector<int>& blocks, const s
             off += (int64_t)m * J.cap;
             J.v_off = off;
             off += (int64_t)n * J.cap;
+            J.phi_off = 0;
+            if (otf_nm) {
+                J.phi_off = off;
+                off += d.col_nodes;
+            }
             J.used_off = uoff;
             uoff += m;
-            if (c.upn == 4) {
+            J.a_off = -1;
+            if (explicit_nm) {
                 DenseBlockDev x = d;
                 x.offset = doff;
                 x.ld = m;
@@ -336,14 +456,14 @@ static void aca_pass(Ctx& c, double tol, const std::vector<int>& blocks, const s
         d_flag.alloc(nq);
         const zd* src = nullptr;
         DBuf<DenseBlockDev> d_blk;
-        if (c.upn == 4) {
+        if (!blk.empty()) {
             if ((int64_t)dense.n < doff) dense.alloc(doff);
             d_blk.upload(blk, c.stream);
             fill_blocks_nm(c, blk, d_blk.p, dense.p);
             src = dense.p;
         }
         k_aca<<<nq, 256, 0, c.stream>>>(d_jobs.p, nq, c.d_tree_node.p, c.nd, c.d_objs.p, tol, ws.p, used.p, d_rank.p,
-                                        d_flag.p, src);
+                                        d_flag.p, src, c.d_patches.p, c.d_node_patch.p, c.d_dmat.p);
         check_launch("k_aca");
         d_rank.download(P.rank.data() + q0, nq, c.stream);
         d_flag.download(P.flag.data() + q0, nq, c.stream);

@@ -46,8 +46,15 @@ template <> struct Mfma<double> {
 // only the rows of op(A) and columns of op(B) of its own tile and stores
 // after its last read, so a tile that spans all rows (or all columns) of
 // C may overwrite its own operand: X := M X and X := X M in place.
-template <typename T, int BM, int BN, int WGM, int BK>
-__global__ __launch_bounds__(256) void k_zgemm(const GemmDesc<T>* __restrict__ descs,
+// K3: the complex product by three real MFMAs (Karatsuba / "3M"):
+//   P1 += Ar Br,  P2 += Ai Bi,  P3 += (Ar + Ai)(Br + Bi);
+//   Cr = P1 - P2,  Ci = P3 - P1 - P2
+// a quarter fewer matrix-core operations for one more accumulator set; the
+// imaginary part is formed as a difference, so its rounding error grows with
+// |Ar Br| + |Ai Bi| instead of |Ar Bi| + |Ai Br| (a small factor for
+// operands of unrelated phases).
+template <typename T, int BM, int BN, int WGM, int BK, bool K3 = false>
+__global__ __launch_bounds__(256, K3 ? 4 : 1) void k_zgemm(const GemmDesc<T>* __restrict__ descs,
                                                const GemmTile* __restrict__ tiles, int ntiles) {
     constexpr int WGN = 4 / WGM, WM = BM / WGM, WN = BN / WGN, FM = WM / 16, FN = WN / 16;
     // one-element row padding: rows written lane by lane (transposing
@@ -73,10 +80,14 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc<T>* __restrict__ d
     const int wm = wave % WGM, wn = wave / WGM;
     const int r = lane & 15, kq = lane >> 4;
 
-    v4 cr[FM][FN], ci[FM][FN];
+    v4 cr[FM][FN], ci[FM][FN], c3[K3 ? FM : 1][K3 ? FN : 1];
     for (int i = 0; i < FM; ++i)
         for (int j = 0; j < FN; ++j)
             for (int v = 0; v < 4; ++v) { cr[i][j][v] = (T)0; ci[i][j][v] = (T)0; }
+    if (K3)
+        for (int i = 0; i < FM; ++i)
+            for (int j = 0; j < FN; ++j)
+                for (int v = 0; v < 4; ++v) c3[K3 ? i : 0][K3 ? j : 0][v] = (T)0;
 
     // The next slice is fetched into registers while the current one is
     // multiplied: every load is issued unconditionally (out-of-range
@@ -151,20 +162,49 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc<T>* __restrict__ d
             for (int i = 0; i < FM; ++i) a[i] = As[cur][kk + kq][wm * WM + 16 * i + r];
 #pragma unroll
             for (int j = 0; j < FN; ++j) b[j] = Bs[cur][kk + kq][wn * WN + 16 * j + r];
+            if constexpr (K3) {
+                // P1 in cr, P2 in ci, P3 in c3
+                T sa[FM], sb[FN];
 #pragma unroll
-            for (int i = 0; i < FM; ++i) {
-                const T nai = -a[i].im;
+                for (int i = 0; i < FM; ++i) sa[i] = a[i].re + a[i].im;
 #pragma unroll
-                for (int j = 0; j < FN; ++j) {
-                    cr[i][j] = Mfma<T>::op(a[i].re, b[j].re, cr[i][j]);
-                    cr[i][j] = Mfma<T>::op(nai, b[j].im, cr[i][j]);
-                    ci[i][j] = Mfma<T>::op(a[i].re, b[j].im, ci[i][j]);
-                    ci[i][j] = Mfma<T>::op(a[i].im, b[j].re, ci[i][j]);
+                for (int j = 0; j < FN; ++j) sb[j] = b[j].re + b[j].im;
+#pragma unroll
+                for (int i = 0; i < FM; ++i)
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) {
+                        cr[i][j] = Mfma<T>::op(a[i].re, b[j].re, cr[i][j]);
+                        ci[i][j] = Mfma<T>::op(a[i].im, b[j].im, ci[i][j]);
+                        c3[K3 ? i : 0][K3 ? j : 0] = Mfma<T>::op(sa[i], sb[j], c3[K3 ? i : 0][K3 ? j : 0]);
+                    }
+            } else {
+#pragma unroll
+                for (int i = 0; i < FM; ++i) {
+                    const T nai = -a[i].im;
+#pragma unroll
+                    for (int j = 0; j < FN; ++j) {
+                        cr[i][j] = Mfma<T>::op(a[i].re, b[j].re, cr[i][j]);
+                        cr[i][j] = Mfma<T>::op(nai, b[j].im, cr[i][j]);
+                        ci[i][j] = Mfma<T>::op(a[i].re, b[j].im, ci[i][j]);
+                        ci[i][j] = Mfma<T>::op(a[i].im, b[j].re, ci[i][j]);
+                    }
                 }
             }
         }
         if (more) stash(cur ^ 1);
         __syncthreads();
+    }
+    if constexpr (K3) {
+#pragma unroll
+        for (int i = 0; i < FM; ++i)
+#pragma unroll
+            for (int j = 0; j < FN; ++j)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const T p1 = cr[i][j][v], p2 = ci[i][j][v];
+                    cr[i][j][v] = p1 - p2;
+                    ci[i][j][v] = c3[K3 ? i : 0][K3 ? j : 0][v] - p1 - p2;
+                }
     }
     // Epilogue, one column group j at a time: every C value of the group is
     // loaded before any is stored (C is read and written through the same
@@ -198,14 +238,31 @@ __global__ __launch_bounds__(256) void k_zgemm(const GemmDesc<T>* __restrict__ d
     }
 }
 
+bool gemm_three_mult() {
+    static const bool on = [] {
+        const char* e = getenv("CBIE_GEMM_3M");
+        return !e || atoi(e) != 0;
+    }();
+    return on;
+}
+
 template <typename T>
 void gemm_batched(hipStream_t s, const GemmDesc<T>* d_desc, const GemmTile* d_tiles, int ntiles, int shape) {
     if (ntiles <= 0) return;
     const int grid = (ntiles + 7) / 8 * 8;
     constexpr int BKW = sizeof(T) == 4 ? 16 : 8;   // deep slices of the wide tiles fit LDS
     constexpr int BK64 = 16;
+    const bool k3 = sizeof(T) == 4 && gemm_three_mult();
     switch (shape) {
-        case kTile64x64: k_zgemm<T, 64, 64, 2, BK64><<<grid, 256, 0, s>>>(d_desc, d_tiles, ntiles); break;
+        case kTile64x64:
+            if constexpr (sizeof(T) == 4) {
+                if (k3) {
+                    k_zgemm<T, 64, 64, 2, BK64, true><<<grid, 256, 0, s>>>(d_desc, d_tiles, ntiles);
+                    break;
+                }
+            }
+            k_zgemm<T, 64, 64, 2, BK64><<<grid, 256, 0, s>>>(d_desc, d_tiles, ntiles);
+            break;
         case kTile256x32: k_zgemm<T, 256, 32, 4, BKW><<<grid, 256, 0, s>>>(d_desc, d_tiles, ntiles); break;
         case kTile32x256: k_zgemm<T, 32, 256, 1, BKW><<<grid, 256, 0, s>>>(d_desc, d_tiles, ntiles); break;
         default: throw Error{-7, "gemm_batched: unknown tile shape"};

@@ -102,6 +102,9 @@ void rand_batched(hipStream_t s, const RandDesc<T>* d_desc, int n);
 template <typename T>
 void eig_batched(hipStream_t s, const EigDesc<T>* d_desc, int n);
 
+// complex64 products on 64 x 64 tiles by three real products instead of
+// four (on unless CBIE_GEMM_3M=0)
+bool gemm_three_mult();
 template <typename T>
 void gemm_batched(hipStream_t s, const GemmDesc<T>* d_desc, const GemmTile* d_tiles, int ntiles, int shape);
 template <typename T>

@@ -18,7 +18,8 @@ struct AcaJob {
     int cap;                     // workspace columns
     int64_t u_off, v_off;        // workspace offsets (elements)
     int64_t used_off;            // row-flag offset (bytes)
-    int64_t a_off;               // explicit copy of the block (N-Mueller), elements
+    int64_t a_off;               // explicit copy of the block (N-Mueller), elements; -1: entries on the fly
+    int64_t phi_off;             // N-Mueller on the fly: column-node scratch in the workspace (elements)
 };
 
 }  // namespace cbie

@@ -9,7 +9,8 @@ solution, for both pipelines:
   - the 49,152-unknown PEC sphere at ka = 20 with its 16 seeded waves;
   - the 24,576-unknown dielectric sphere (N-Mueller; ACA 1e-7);
   - four seeded objects of the 64-ellipsoid batch, solved inside the
-    64-object context with 32 waves each (the first four compared).
+    64-object context with 32 waves each (the first four compared);
+  - the large ellipsoid's shape scaled down to 12,288 unknowns.
 The 196,608-unknown ellipsoid has no dense oracle (618 GB): 256 seeded
 rows are computed exactly by the oracle and the relative residual of the
 solution on them must be below 1e-5; compressing with the trained rank
@@ -111,6 +112,21 @@ def test_resonance_against_dense_oracle():
     print(f"{it} sweeps; rel L2 vs dense oracle {err:.2e}; J vs Mie: solver {eg:.3e}, dense oracle {eo:.3e}")
     assert err < 1e-4
     assert abs(eg - eo) <= 0.05 * eo
+
+
+def test_stretched_ellipsoid_against_dense_oracle():
+    """The 196,608-unknown ellipsoid's shape (semi-axes 2 : 1 : 0.5) and patch
+    size scaled down to 12,288 unknowns, where the dense oracle fits: the
+    same stretched patches and near-pair classification at a size the
+    oracle solves densely."""
+    g = _gold("stretched_ellipsoid_12288_dense.npz")
+    spec = W.ObjectSpec(axes=(2.0, 1.0, 0.5), center=(0.0, 0.0, 0.0), s=4, q=8, k0=5.0)
+    for prec in (1, 0):
+        s, x, it = _pipeline([spec], prec, g["khat"], g["pol"])
+        s.close()
+        err = _rel(x, g["x"])
+        print(f"prec {prec}: {it} sweeps, rel L2 vs dense oracle {err:.2e}")
+        assert err < TARGET
 
 
 def _rows_worker(args):

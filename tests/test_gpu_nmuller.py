@@ -73,6 +73,41 @@ def test_aca_of_explicit_blocks_within_tolerance():
     s.close()
 
 
+def test_aca_entries_on_the_fly_equal_explicit_copies():
+    """The same admissible blocks compressed from explicit copies and from
+    entries generated on the fly (divergence through the source patch's
+    lines): both within the tolerance of the uncompressed fill, with the same
+    ranks, and the two compressed operators equal to well below it."""
+    import os
+    import torch
+    spec = _spec(3, 4, 3.0, 4.0)
+    s = _solver(spec)
+    s.fill()
+    A = s.export_dense()
+    old = os.environ.get("CBIE_NM_OTF_MIN")
+    out = {}
+    try:
+        for name, lim in (("explicit", "1000000000"), ("on_the_fly", "0")):
+            os.environ["CBIE_NM_OTF_MIN"] = lim
+            s.compress(1e-7)
+            out[name] = (s.export_dense(), s.block_features(1e-7)[1], s.stats())
+    finally:
+        if old is None:
+            del os.environ["CBIE_NM_OTF_MIN"]
+        else:
+            os.environ["CBIE_NM_OTF_MIN"] = old
+    (Ae, re, ste), (Ao, ro, sto) = out["explicit"], out["on_the_fly"]
+    ee = (torch.linalg.norm(Ae - A) / torch.linalg.norm(A)).item()
+    eo = (torch.linalg.norm(Ao - A) / torch.linalg.norm(A)).item()
+    d = (torch.linalg.norm(Ao - Ae) / torch.linalg.norm(A)).item()
+    print(f"{ste['n_lr_blocks']} blocks: explicit {ee:.2e}, on the fly {eo:.2e}, between them {d:.2e}; "
+          f"ranks equal {np.array_equal(re, ro)} (max {re.max()} / {ro.max()}); "
+          f"compress {ste['t_compress']:.3f} s / {sto['t_compress']:.3f} s")
+    assert ee < 1e-6 and eo < 1e-6
+    assert np.array_equal(re, ro) or d < 1e-8
+    s.close()
+
+
 @pytest.mark.parametrize("prec", [0, 1], ids=["c128", "c64_ir"])
 def test_hlu_solution_matches_dense_oracle(prec):
     from paper_2408_17116_amd import cbie
