@@ -27,7 +27,7 @@ pipeline, one step.
 
 python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu] [--no-dielectric] [--no-batch]
 python bench.py --large-ellipsoid   (the PEC ellipsoid of semi-axes (8, 4, 2) m,
-                                ka = 40, 196608 unknowns, ACA 1e-6: the rank
+                                ka = 40, 196608 unknowns, ACA 1e-8: the rank
                                 network trained on the GPU from the adaptive
                                 ranks of the small sphere and 24 seeded
                                 ellipsoids; adaptive vs predicted-width
@@ -264,7 +264,10 @@ def ellipsoid_batch(cbie, W):
 def large_ellipsoid(cbie, W):
     """Rank network trained on the GPU, then the 196608-unknown ellipsoid
     compressed adaptively and with predicted widths (same ranks), factored
-    in complex64 and solved with FP64 refinement."""
+    in complex64 and solved with FP64 refinement.  ACA 1e-8: the operator's
+    smallest singular value is near 1.5e-3 (an interior resonance of the
+    MFIE at this size), which amplifies the compression error about
+    800-fold; at 1e-6 the solution would miss 1e-5."""
     import numpy as np
     import torch
     model, info = train_rank_model(cbie, W)
@@ -273,17 +276,17 @@ def large_ellipsoid(cbie, W):
     s.build_tree(leaf_size=256, eta=1.0, near_delta=1.0)
     s.fill()
     out = {"workload": "PEC ellipsoid semi-axes (8, 4, 2) m, ka = 40, 1536 patches q = 8, 196608 unknowns, "
-                       "leaf 256, eta 1, ACA 1e-6, 1 plane wave, mixed pipeline",
+                       "leaf 256, eta 1, ACA 1e-8, 1 plane wave, mixed pipeline",
            "training": info, "fill_s": s.stats()["t_fill"]}
     ranks = {}
     s.set_rank_model(*model)
     for name, mode in (("adaptive", cbie.RANK_ADAPTIVE), ("predicted", cbie.RANK_PREDICTED)):
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        s.compress(1e-6, mode=mode)
+        s.compress(1e-8, mode=mode)
         torch.cuda.synchronize()
         st = s.stats()
-        ranks[name] = s.block_features(1e-6)[1]
+        ranks[name] = s.block_features(1e-8)[1]
         out[name] = {"seconds": time.perf_counter() - t1, "aca_workspace_GiB": st["aca_workspace_bytes"] / 2 ** 30,
                      "fallbacks": st["aca_fallbacks"], "unconverged": st["aca_unconverged"],
                      "lr_blocks": st["n_lr_blocks"], "max_rank": st["max_rank"]}

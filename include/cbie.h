@@ -294,6 +294,10 @@ typedef struct {
      * P2 = Ai Bi, P3 = (Ar + Ai)(Br + Bi); Cr = P1 - P2, Ci = P3 - P1 - P2;
      * CBIE_GEMM_3M=0 selects the four-product form) */
     double gemm_flops_mfma;
+    /* last factor: recompressions of every pending block forced by storage
+     * pressure (the factors grew by more than half the device memory free
+     * when the factorization started, or by CBIE_FACTOR_MEM bytes) */
+    int64_t factor_mem_flushes;
 } cbie_stats;
 cbie_status cbie_get_stats(cbie_ctx* ctx, void* stats_out, size_t bytes);
 

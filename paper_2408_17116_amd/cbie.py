@@ -62,7 +62,7 @@ class Stats(C.Structure):
         ("leaf_lu_launches", C.c_int64), ("leaf_lu_flops", C.c_double), ("leaf_lu_seconds", C.c_double),
         ("quad_points", C.c_double), ("quad_flops", C.c_double),
         ("solve_factor_bytes", C.c_double), ("far_fill_seconds", C.c_double), ("gemm_bytes_alg", C.c_double),
-        ("gemm_flops_mfma", C.c_double)]
+        ("gemm_flops_mfma", C.c_double), ("factor_mem_flushes", C.c_int64)]
 
 
 _lib = None

@@ -1269,7 +1269,25 @@ template <typename T> struct HF {
         else if (b.type == BLK_HIER)
             for (int k = 0; k < 4; ++k) collect_lr(b.child[k], out);
     }
-    int64_t flushes = 0, flush_overflow = 0;
+    int64_t flushes = 0, flush_overflow = 0, flush_mem = 0;
+    // Storage pressure: the factors grow by appended update columns (up to
+    // kmax per block) and dense accumulators until a recompression folds
+    // them.  When the live storage passes mem_next elements every pending
+    // block is recompressed; the next check is at the storage left after it
+    // plus a quarter of the growth allowed.  The budget is the factors'
+    // initial storage plus half the device memory free when the
+    // factorization starts (CBIE_FACTOR_MEM: another growth in bytes).
+    size_t mem_budget = SIZE_MAX, mem_next = SIZE_MAX, mem_grow = 0;
+    void set_mem_budget(size_t bytes) {
+        mem_budget = mem_next = std::max<size_t>(bytes / sizeof(cplx<T>), 1);
+        mem_grow = mem_budget > store.live ? mem_budget - store.live : 0;
+    }
+    void relieve_storage() {
+        if (store.live <= mem_next) return;
+        ++flush_mem;
+        flush_all();
+        mem_next = std::max(mem_budget, store.live + std::max<size_t>(mem_grow / 4, 1));
+    }
     double width_lr_a = 0, width_lr_b = 0, width_dd = 0, flush_k = 0;
     // the dense accumulator of a block, allocated and cleared on first use
     cplx<T>* dacc(int leaf) {
@@ -1440,6 +1458,7 @@ template <typename T> struct HF {
             rec_gemm(0, 1, C.m, C.n, k, al, Xp, ldx, Yp, ldy, one(), Cp, ldc, cat({res(X), res(Y)}), res(C));
             return;
         }
+        relieve_storage();
         if (to_dacc(C, k)) {
             const int lc = leaf_of(C);
             cplx<T>* D = dacc(lc);
@@ -1526,6 +1545,7 @@ template <typename T> struct HF {
         // Room in a low-rank C is made before anything is recorded, so no
         // recompression can fold an operand's parts mid-way.
         if (kind(C) == LRK) {
+            relieve_storage();
             int need = 0;
             const bool da = kind(A) == LRK && lrb(A).dirty, db = kind(B) == LRK && lrb(B).dirty;
             const int wa = kind(A) == LRK ? lrb(A).K : -1, wb = kind(B) == LRK ? lrb(B).K : -1;
@@ -1955,27 +1975,15 @@ template <typename T> static std::shared_ptr<HF<T>> make_factor(Ctx& c) {
 
 template <typename T> static void run_factor(Ctx& c, HF<T>& f) {
     Tuner<T>::tune(c.stream, f.debug);
+    {
+        const char* em = getenv("CBIE_FACTOR_MEM");
+        size_t fr = 0, tot = 0;
+        size_t grow = 0;
+        if (em) grow = (size_t)std::max<long long>(0, atoll(em));
+        else if (hipMemGetInfo(&fr, &tot) == hipSuccess) grow = fr / 2;
+        if (em || grow > 0) f.set_mem_budget(f.store.live * sizeof(cplx<T>) + grow);
+    }
     try {
-        // Initial truncation of the compressed blocks (CBIE_TRUNC0): 0 (the
-        // default) factors the ACA ranks as they are; 1 first recompresses
-        // every low-rank block at the factor tolerance when that is looser
-        // than the ACA tolerance; 2 always does (ACA's ranks exceed the
-        // truncated ones at the same tolerance)
-        const char* e0 = getenv("CBIE_TRUNC0");
-        const int mode0 = e0 ? atoi(e0) : 0;
-        if (mode0 == 2 || (mode0 == 1 && f.tol > 1.5 * c.aca_tol)) {
-            std::vector<int> all;
-            double r0 = 0.0, r1 = 0.0;
-            for (size_t b = 0; b < f.lr.size(); ++b)
-                if (f.lr[b].r > 0) {
-                    all.push_back((int)b);
-                    r0 += f.lr[b].r;
-                }
-            f.recompress(all);
-            for (const auto& L : f.lr) r1 += L.r;
-            if (f.debug)
-                fprintf(stderr, "[cbie] initial truncation to %.1e: summed rank %.0f -> %.0f\n", f.tol, r0, r1);
-        }
         for (int root : c.tree.block_roots) f.hlu(root);
         f.flush_all();
     } catch (const Error&) {
@@ -2018,6 +2026,7 @@ template <typename T> static void run_factor(Ctx& c, HF<T>& f) {
                  "dependency audit: " + std::to_string(f.audit_conflicts) + " conflicting task pairs in one level");
     c.stats.factor_flops = (int64_t)f.alg_flops;
     c.stats.factor_flops_executed = (int64_t)f.flops;
+    c.stats.factor_mem_flushes = f.flush_mem;
     c.stats.n_kernel_launches = f.launches;
     c.gemm_timer.harvest();
     c.stats.gemm_seconds = c.gemm_timer.seconds;

@@ -14,7 +14,11 @@ solution, for both pipelines:
 The 196,608-unknown ellipsoid has no dense oracle (618 GB): 256 seeded
 rows are computed exactly by the oracle and the relative residual of the
 solution on them must be below 1e-5; compressing with the trained rank
-network must give the adaptive ranks."""
+network must give the adaptive ranks.  At ka = 40 this MFIE operator has a
+singular value near 1.5e-3 (inverse iteration: ||A^-1|| >= 653, an interior
+resonance), which amplifies the compression error about 800-fold: ACA 1e-6
+leaves 7.8e-4 on the exact rows, ACA 1e-8 leaves 8.4e-9.  The workload is
+compressed at 1e-8."""
 import multiprocessing as mp
 import os
 
@@ -176,12 +180,12 @@ def test_large_ellipsoid_sampled_rows_and_rank_network():
     s.build_tree(leaf_size=256, eta=1.0, near_delta=1.0)
     s.fill()
     s.set_rank_model(p.cpu().numpy(), mean, sdev, 0.25)
-    s.compress(1e-6)
+    s.compress(1e-8)
     st_a = s.stats()
-    ranks_a = s.block_features(1e-6)[1]
-    s.compress(1e-6, mode=cbie.RANK_PREDICTED)
+    ranks_a = s.block_features(1e-8)[1]
+    s.compress(1e-8, mode=cbie.RANK_PREDICTED)
     st_p = s.stats()
-    ranks_p = s.block_features(1e-6)[1]
+    ranks_p = s.block_features(1e-8)[1]
     assert np.array_equal(ranks_a, ranks_p)
     assert st_p["aca_workspace_bytes"] < st_a["aca_workspace_bytes"]
     assert st_a["aca_unconverged"] == 0 and st_p["aca_unconverged"] == 0

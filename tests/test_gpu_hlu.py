@@ -134,3 +134,44 @@ def test_dependency_audit_clean():
             s.close()
     finally:
         del os.environ["CBIE_CHECK_DEPS"]
+
+
+@pytest.mark.parametrize("prec", [0, 1], ids=["c128", "c64_ir"])
+def test_storage_pressure_recompressions_keep_the_solution(prec):
+    """A factorization whose storage may grow by only 32 MB past its initial
+    size (CBIE_FACTOR_MEM) recompresses every pending block whenever it
+    passes that, instead of at the width limit only: it must still factor,
+    and the refined solution must equal the unconstrained one (both refined
+    against the same FP64 operator)."""
+    import torch
+    from paper_2408_17116_amd import cbie
+    spec = W.tiny_sphere(s=4, q=8, k0=8.0)        # 12,288 unknowns
+    kh, pol = W.plane_waves(2, seed=6)
+    s = _solver(spec, leaf=256, tol=1e-6)
+    b = s.rhs_planewave(kh, pol)
+    out = {}
+    old = os.environ.get("CBIE_FACTOR_MEM")
+    try:
+        for name, lim in (("free", None), ("tight", str(32 << 20))):
+            if lim is None:
+                os.environ.pop("CBIE_FACTOR_MEM", None)
+            else:
+                os.environ["CBIE_FACTOR_MEM"] = lim
+            s.factor(prec)
+            st = s.stats()
+            x, it = s.solve(b, tol=1e-10, maxit=30)
+            res = (torch.linalg.norm(s.matvec(x) - b) / torch.linalg.norm(b)).item()
+            out[name] = (x.cpu().numpy(), st["factor_mem_flushes"], it, res, st["t_factor"])
+    finally:
+        if old is None:
+            os.environ.pop("CBIE_FACTOR_MEM", None)
+        else:
+            os.environ["CBIE_FACTOR_MEM"] = old
+    s.close()
+    (xf, nf, itf, rf, tf), (xt, nt, itt, rt, tt) = out["free"], out["tight"]
+    d = np.linalg.norm(xt - xf) / np.linalg.norm(xf)
+    print(f"prec {prec}: storage flushes {nf} / {nt}, sweeps {itf} / {itt}, residual {rf:.1e} / {rt:.1e}, "
+          f"factor {tf:.2f} s / {tt:.2f} s, solutions differ by {d:.1e}")
+    assert nf == 0 and nt > 0
+    assert rf <= 1e-10 and rt <= 1e-10
+    assert d < 1e-8
