@@ -1880,8 +1880,17 @@ template <typename T> struct HF {
         collect_lr(D.child[2], ops);
         flush_set(ops);
         update(full(D.child[3]), full(D.child[2]), full(D.child[1]), neg());
+        // The recompression above synchronized the stream, so the GPU idles
+        // while the host records.  A large Schur update goes out now and runs
+        // while the host records the next diagonal block's factorization;
+        // that work then cannot share levels with the update's tail.
+        if (exec_after_update > 0 && (int64_t)gd.size() >= exec_after_update) execute();
         hlu(D.child[3]);
     }
+    // recorded products that make a Schur update run at once (CBIE_EXEC_UPDATE;
+    // 0: never)
+    const int64_t exec_after_update =
+        getenv("CBIE_EXEC_UPDATE") ? atoll(getenv("CBIE_EXEC_UPDATE")) : 1000;
 };
 
 // ------------------------------------------------------------ kernel timer
