@@ -33,6 +33,9 @@ python bench.py --large-ellipsoid   (the PEC ellipsoid of semi-axes (8, 4, 2) m,
                                 ellipsoids; adaptive vs predicted-width
                                 compression; complex64 H-LU + refinement and
                                 a one-wave solve; one JSON line, about 2 min)
+python bench.py --high-contrast 50,100,200,300   (the 1-wavelength dielectric
+                                sphere of the high-contrast study on 98,304
+                                unknowns, ACA 1e-8: one JSON line per eps)
 python bench.py --sphere-scaling 2,4,8,16,26   (the 3-wavelength-radius PEC sphere
                                 at q = 10 from 4,800 to 811,200 unknowns: phase
                                 times and storage per size, one JSON line each)
@@ -341,6 +344,42 @@ def sphere_scaling(cbie, W, splits):
         print(json.dumps(rec), flush=True)
 
 
+def high_contrast(cbie, W, eps_list):
+    """The paper's high-contrast study (Sec. IV-B, Fig. 8): dielectric sphere
+    one exterior wavelength across (radius 0.5 m, k0 = 2 pi, mu_d = 1) on one
+    fixed mesh (faces split 8 x 8, q = 8: 98,304 unknowns, which resolves the
+    interior wavelength up to eps_d = 300), ACA 1e-8, complex64 H-LU refined
+    to 1e-10, axial wave.  Time of each phase, ranks, sweeps and the residual
+    against the stored operator per permittivity (one JSON line each); the
+    currents' error against the Mie series is checked by
+    tests/test_gpu_high_contrast.py."""
+    import numpy as np
+    import torch
+    kh, pol = W.axial_wave()
+    for eps in eps_list:
+        spec = W.ObjectSpec(axes=(0.5, 0.5, 0.5), center=(0.0, 0.0, 0.0), s=8, q=8, k0=2.0 * np.pi,
+                            form=W.FORM_NMULLER, eps_r=eps, mu_r=1.0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sv = cbie.Solver([spec])
+        sv.build_tree(leaf_size=256, eta=1.0, near_delta=1.0)
+        sv.fill()
+        sv.compress(1e-8)
+        sv.factor(cbie.PREC_C64_IR)
+        b = sv.rhs_planewave(kh, pol)
+        x, it = sv.solve(b, tol=1e-10, maxit=30)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        st = sv.stats()
+        res = (torch.linalg.norm(sv.matvec(x) - b) / torch.linalg.norm(b)).item()
+        sv.close()
+        rec = {"high_contrast": {"eps_r": eps, "unknowns": spec.n_unknowns, "seconds": dt,
+                                 "phases_s": {p: st["t_" + p] for p in ("tree", "fill", "compress", "factor", "solve")},
+                                 "compression_rate": st["compression_rate"], "max_rank": st["max_rank"],
+                                 "ir_iterations": it, "residual": res}}
+        print(json.dumps(rec), flush=True)
+
+
 def gemm_traffic(pipeline):
     """HBM bytes per k_zgemm launch from the committed counter runs
     (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known size), or
@@ -410,6 +449,8 @@ def main():
     ap.add_argument("--large-ellipsoid", action="store_true")
     ap.add_argument("--sphere-scaling", default="",
                     help="comma-separated face splits s of the 3-wavelength sphere at q = 10 (e.g. 2,4,8,16,26)")
+    ap.add_argument("--high-contrast", default="",
+                    help="comma-separated permittivities of the 1-wavelength dielectric sphere (e.g. 50,100,200,300)")
     ap.add_argument("--factor-tol", type=float, default=0.0,
                     help="truncation tolerance of the mixed leg's factorization (0: the ACA tolerance)")
     args = ap.parse_args()
@@ -438,6 +479,9 @@ def main():
         return
     if args.sphere_scaling:
         sphere_scaling(cbie, W, [int(v) for v in args.sphere_scaling.split(",")])
+        return
+    if args.high_contrast:
+        high_contrast(cbie, W, [float(v) for v in args.high_contrast.split(",")])
         return
     spec = W.sphere_pec_ka20()
     kh, pol = W.plane_waves(16, seed=0)

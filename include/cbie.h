@@ -127,9 +127,12 @@ cbie_status cbie_fill(cbie_ctx* ctx, int n_ang, int n_rad);
  * mode CBIE_RANK_ADAPTIVE sizes each block's workspace at full width,
  * CBIE_RANK_PREDICTED at the width the rank model predicts (see
  * cbie_set_rank_model); both give the same factors.  Blocks are processed in
- * rounds whose ACA workspace fits 2^30 complex elements (environment
- * variable CBIE_ACA_BUDGET: another element count), so the workspace stays
- * bounded at any problem size.  Errors: ESTATE, EINVAL (aca_tol outside (0, 1),
+ * rounds whose ACA workspace fits a quarter of the device memory free when
+ * the call starts, at most 2^32 complex elements (environment variable
+ * CBIE_ACA_BUDGET: another element count), so the workspace stays bounded at
+ * any problem size; N-Mueller blocks compressed from explicit copies keep
+ * those within an eighth of the free memory, at most 2^31 entries
+ * (CBIE_ACA_DENSE).  Errors: ESTATE, EINVAL (aca_tol outside (0, 1),
  * CBIE_RANK_PREDICTED without a model), ENOMEM, EHIP. */
 cbie_status cbie_compress(cbie_ctx* ctx, double aca_tol, cbie_rank_mode mode);
 

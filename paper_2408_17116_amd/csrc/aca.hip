@@ -369,14 +369,18 @@ __global__ void k_export_lr(const DenseBlockDev* __restrict__ blocks, int n_bloc
 
 // ACA of the given blocks with the given widths, in rounds whose workspace
 // (U: m x width and V: n x width per block) stays within a budget
-// (CBIE_ACA_BUDGET elements, default 2^30); each round's factors are packed
-// (U then V, rank columns each) into a buffer of their own before the
-// workspace is reused.  N-Mueller blocks whose shorter side is below
-// CBIE_NM_OTF_MIN unknowns (default 2048) are filled explicitly per round, at
-// most kAcaDense entries, and compressed from their copies; larger ones get
-// their entries on the fly (a column costs q kernel evaluations per row: the
-// surface divergence couples the source patch's line, so the explicit copy
-// is cheaper for small blocks).
+// (CBIE_ACA_BUDGET elements; default a quarter of the device memory free at
+// the start, at most 2^32 elements); each round's factors are packed (U then
+// V, rank columns each) into a buffer of their own before the workspace is
+// reused.  N-Mueller blocks whose shorter side is below CBIE_NM_OTF_MIN
+// unknowns (default 2048) are filled explicitly per round, within a budget
+// of their own (CBIE_ACA_DENSE entries; default an eighth of the free
+// memory, at most kAcaDense), and compressed from their copies; larger ones
+// get their entries on the fly (a column costs q kernel evaluations per
+// row: the surface divergence couples the source patch's line, so the
+// explicit copy is cheaper for small blocks).  A round lasts as long as its
+// slowest block (one work-group each), so fewer, larger rounds finish
+// sooner.
 struct AcaPass {
     std::vector<int> rank, flag;
     std::vector<int> round;        // per block: the buffer holding its factors
@@ -387,8 +391,15 @@ struct AcaPass {
 };
 static void aca_pass(Ctx& c, double tol, const std::vector<int>& blocks, const std::vector<int>& width, AcaPass& P) {
     const int nb = (int)blocks.size();
+    size_t mfree = 0, mtot = 0;
+    if (hipMemGetInfo(&mfree, &mtot) != hipSuccess) mfree = size_t(64) << 30;
+    const int64_t free_elems = (int64_t)(mfree / sizeof(zd));
     const char* eb = getenv("CBIE_ACA_BUDGET");
-    const int64_t budget = eb ? std::max<int64_t>(1, atoll(eb)) : int64_t(1) << 30;
+    const int64_t budget = eb ? std::max<int64_t>(1, atoll(eb))
+                              : std::max<int64_t>(int64_t(1) << 26, std::min<int64_t>(int64_t(1) << 32, free_elems / 4));
+    const char* ed = getenv("CBIE_ACA_DENSE");
+    const int64_t dense_budget = ed ? std::max<int64_t>(1, atoll(ed))
+                                    : std::max<int64_t>(int64_t(1) << 24, std::min<int64_t>(kAcaDense, free_elems / 8));
     const char* eo = getenv("CBIE_NM_OTF_MIN");
     const int64_t otf_min = eo ? std::max<int64_t>(0, atoll(eo)) : 2048;
     P.rank.assign(nb, 0);
@@ -413,7 +424,7 @@ static void aca_pass(Ctx& c, double tol, const std::vector<int>& blocks, const s
             const bool otf_nm = c.upn == 4 && !explicit_nm;
             const int64_t w = (int64_t)(m + n) * width[q1] + (otf_nm ? d.col_nodes : 0);
             const int64_t e = explicit_nm ? (int64_t)m * n : 0;
-            if (q1 > q0 && (off + w > budget || doff + e > kAcaDense)) break;
+            if (q1 > q0 && (off + w > budget || doff + e > dense_budget)) break;
             AcaJob J{};
             J.row_node0 = d.row_node0;
             J.row_nodes = d.row_nodes;

@@ -75,7 +75,8 @@ __global__ __launch_bounds__(256, K3 ? 4 : 1) void k_zgemm(const GemmDesc<T>* __
     const GemmTile tl = tiles[t];
     const GemmDesc<T> D = descs[tl.desc];
     const int m = D.m, n = D.n, k = D.k;
-    const int m0 = tl.m0, n0 = tl.n0;
+    const int tn = (n + BN - 1) / BN;
+    const int m0 = (tl.lt / tn) * BM, n0 = (tl.lt % tn) * BN;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int wm = wave % WGM, wn = wave / WGM;
     const int r = lane & 15, kq = lane >> 4;

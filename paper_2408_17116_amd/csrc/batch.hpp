@@ -15,8 +15,11 @@ template <typename T> struct GemmDesc {
     int lda, ldb, ldc;
     int pad;
 };
+// one output tile of a product: the descriptor and the tile's index in it,
+// row-major over the product's tile grid (m0 = (lt / tiles per row) * rows,
+// n0 = (lt % tiles per row) * columns of the launch's tile shape)
 struct GemmTile {
-    int desc, m0, n0, pad;
+    int desc, lt;
 };
 // output tile shapes of the batched GEMM (rows x columns of C)
 enum { kTile64x64 = 0, kTile256x32 = 1, kTile32x256 = 2, kNumTileShapes = 3 };

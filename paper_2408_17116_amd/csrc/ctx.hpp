@@ -96,8 +96,10 @@ struct Ctx {
     // statistics
     cbie_stats stats{};
 
-    // Event pairs around timed launches; times are harvested when the pool
-    // fills and at the end of each stage.
+    // Event pairs around timed launches.  When the pool is full, the pairs
+    // that have completed are read without waiting (they complete in stream
+    // order) and their events reused; the pool grows only while none has.
+    // harvest() waits for all of them, at the end of a stage.
     struct KernelTimer {
         bool on = false;
         std::vector<hipEvent_t> ev;
@@ -106,6 +108,7 @@ struct Ctx {
         void begin(hipStream_t s);
         void end(hipStream_t s);
         void harvest();
+        void harvest_ready();
         ~KernelTimer();
     } gemm_timer, leaf_timer;
 

@@ -155,6 +155,11 @@ template <typename T> struct Tuner {
         DBuf<cplx<T>> buf;
         buf.alloc(need);
         CBIE_HIP(hipMemsetAsync(buf.p, 0, need * sizeof(cplx<T>), s));
+        DBuf<RandDesc<T>> rdd;
+        if (getenv("CBIE_TUNE_RANDOM") && atoi(getenv("CBIE_TUNE_RANDOM")) == 1) {
+            rdd.upload(std::vector<RandDesc<T>>{RandDesc<T>{buf.p, (int)need, 1, (int)need, 12345u}}, s);
+            rand_batched<T>(s, rdd.p, 1);
+        }
         DBuf<GemmDesc<T>> dd;
         DBuf<GemmTile> dt;
         hipEvent_t e0, e1;
@@ -181,9 +186,9 @@ template <typename T> struct Tuner {
                     int best_sh = kTile64x64;
                     for (int sh = 0; sh < kNumTileShapes; ++sh) {
                         std::vector<GemmTile> t;
+                        const int nt = ((m + tile_rows(sh) - 1) / tile_rows(sh)) * ((n + tile_cols(sh) - 1) / tile_cols(sh));
                         for (int b = 0; b < B; ++b)
-                            for (int m0 = 0; m0 < m; m0 += tile_rows(sh))
-                                for (int n0 = 0; n0 < n; n0 += tile_cols(sh)) t.push_back(GemmTile{b, m0, n0, 0});
+                            for (int q = 0; q < nt; ++q) t.push_back(GemmTile{b, q});
                         dt.upload(t, s);
                         gemm_batched<T>(s, dd.p, dt.p, (int)t.size(), sh);
                         CBIE_HIP(hipEventRecord(e0, s));
@@ -292,8 +297,12 @@ template <typename T> struct HF {
     std::unordered_map<int64_t, std::vector<Ent>> st;
     int next_temp = 0;
     int max_level = -1;
-    void* pinned = nullptr;
-    size_t pinned_bytes = 0;
+    // two pinned staging buffers, alternating between programs: the one a
+    // program fills was last read by the copy of the program before the
+    // previous one, which completed before the previous program was staged
+    char* pin_buf[2] = {nullptr, nullptr};
+    size_t pin_cap[2] = {0, 0};
+    int pin_cur = 0;
     hipEvent_t staged_ev = nullptr;   // recorded after the last program's descriptor copy
     int64_t staged_gen = -1;          // that program's launch number (-1: none)
 
@@ -302,7 +311,8 @@ template <typename T> struct HF {
         for (auto e : dev_ev)
             if (e) (void)hipEventDestroy(e);
         if (rank_pinned) (void)hipHostFree(rank_pinned);
-        if (pinned) (void)hipHostFree(pinned);
+        for (char* p : pin_buf)
+            if (p) (void)hipHostFree(p);
         if (imm_pinned) (void)hipHostFree(imm_pinned);
         if (staged_ev) (void)hipEventDestroy(staged_ev);
     }
@@ -326,6 +336,8 @@ template <typename T> struct HF {
     // into one rectangle are ordered like writes: the results do not depend
     // on the schedule.)
     double t_level = 0.0, t_exec = 0.0, t_recomp = 0.0;
+    double t_ex_build = 0.0, t_ex_stage = 0.0, t_ex_launch = 0.0;   // parts of execute (debug)
+    int64_t n_tiles_staged = 0;
     int64_t n_level_calls = 0, n_scanned = 0;
     int level_of(const std::vector<Res>& rd, const std::vector<Res>& wr) {
         const double t0 = debug ? now_s() : 0.0;
@@ -432,8 +444,11 @@ template <typename T> struct HF {
         return best;
     }
     static void add_tiles(std::vector<GemmTile>& t, int di, const GemmDesc<T>& d, int sh) {
-        for (int m0 = 0; m0 < d.m; m0 += tile_rows(sh))
-            for (int n0 = 0; n0 < d.n; n0 += tile_cols(sh)) t.push_back(GemmTile{di, m0, n0, 0});
+        const int nt = (int)ntiles(d, sh);
+        const size_t o = t.size();
+        t.resize(o + nt);
+        GemmTile* p = t.data() + o;
+        for (int q = 0; q < nt; ++q) p[q] = GemmTile{di, q};
     }
     // Long inner dimension and few output tiles: the k range is split over
     // several work-groups that write partial products to a workspace, and a
@@ -674,13 +689,18 @@ template <typename T> struct HF {
             if (pin == 0) scratch.reset();
             return;
         }
+        // a replayed program is captured whole: a second program recorded into
+        // the same replay would overwrite the descriptors the first one's
+        // launches point to
+        CBIE_REQUIRE(!rec_into || rec_into->seq.empty(), -7, "a substitution recorded for replay must run as one program");
         const int L = max_level + 1;
         std::vector<std::vector<int>> gl(L), cl(L), ll(L);
         for (size_t i = 0; i < gd.size(); ++i) gl[glev[i]].push_back((int)i);
         for (size_t i = 0; i < cd.size(); ++i) cl[clev[i]].push_back((int)i);
         for (size_t i = 0; i < ld.size(); ++i) ll[llev[i]].push_back((int)i);
-        // one pinned staging buffer: per level and tile shape [gemm descs][gemm
-        // tiles], then [copy descs][copy tiles][leaf descs]
+        // the program's descriptors, staged in one pinned buffer: per level and
+        // tile shape [gemm descs][gemm tiles], then [copy descs][copy
+        // tiles][leaf descs]
         struct Seg {
             size_t g[kNumTileShapes], gt[kNumTileShapes], r, rt, c, ct, l;
             double lfl;   // algorithmic flops of the level's leaf LUs (8/3 b^3 each)
@@ -692,13 +712,26 @@ template <typename T> struct HF {
         wsp_cur ^= 1;
         Arena<T>& ws = rec_into ? rec_into->ws : wsp[wsp_cur];
         std::vector<Seg> seg(L);
-        std::vector<char> host;
+        pin_cur ^= 1;
+        char*& P = pin_buf[pin_cur];
+        size_t& cap = pin_cap[pin_cur];
+        size_t used = 0;
         auto put = [&](const void* src, size_t bytes) {
-            size_t off = (host.size() + 255) & ~size_t(255);
-            host.resize(off + bytes);
-            if (bytes) std::memcpy(host.data() + off, src, bytes);
+            const size_t off = (used + 255) & ~size_t(255);
+            if (off + bytes > cap) {
+                const size_t nc = std::max({off + bytes, 2 * cap, (size_t)1 << 20});
+                void* np = nullptr;
+                CBIE_HIP(hipHostMalloc(&np, nc));
+                if (used) std::memcpy(np, P, used);
+                if (P) CBIE_HIP(hipHostFree(P));
+                P = static_cast<char*>(np);
+                cap = nc;
+            }
+            if (bytes) std::memcpy(P + off, src, bytes);
+            used = off + bytes;
             return off;
         };
+        const double tb0 = now_s();
         for (int lv = 0; lv < L; ++lv) {
             Seg& sg = seg[lv];
             Batch bt;
@@ -744,34 +777,34 @@ template <typename T> struct HF {
             sg.nl = (int)lf.size();
         }
         if (audit) audit_program();
+        const double tb1 = now_s();
+        t_ex_build += tb1 - tb0;
+        for (int lv = 0; lv < L; ++lv)
+            for (int sh = 0; sh < kNumTileShapes; ++sh) n_tiles_staged += seg[lv].ngt[sh];
         DBuf<char>& dev = rec_into ? rec_into->desc : descbuf;
-        if (host.size() > pinned_bytes || dev.n < host.size()) {
-            wait_stream();   // nothing in flight reads the buffers being replaced
-            if (host.size() > pinned_bytes) {
-                if (pinned) CBIE_HIP(hipHostFree(pinned));
-                pinned_bytes = std::max(host.size(), pinned_bytes * 2);
-                CBIE_HIP(hipHostMalloc(&pinned, pinned_bytes));
-            }
-            if (dev.n < host.size()) dev.alloc(std::max(host.size(), (size_t)1 << 20));
+        if (dev.n < used) {
+            wait_stream();   // nothing in flight reads the buffer being replaced
+            dev.alloc(std::max(used, (size_t)1 << 20));
         }
-        // The previous program's descriptors must have left the pinned
-        // buffer: wait for the event recorded after their copy.  That
-        // program's kernels may still run (they read the device copy, which
-        // this program's copy follows in stream order), so the host stages
-        // and launches this program while the GPU works; every program
-        // before the previous one has completed, which releases the factor
-        // storage they held.
+        // The previous program's descriptors must have left their pinned
+        // buffer before the next program fills it: wait for the event
+        // recorded after their copy.  That program's kernels may still run
+        // (they read the device copy, which this program's copy follows in
+        // stream order), so the host stages and launches this program while
+        // the GPU works; every program before the previous one has
+        // completed, which releases the factor storage they held.
         if (staged_gen >= 0) {
             const double t0 = now_s();
             CBIE_HIP(hipEventSynchronize(staged_ev));
             t_wait += now_s() - t0;
             store.completed_through(staged_gen - 1);
         }
-        std::memcpy(pinned, host.data(), host.size());
-        CBIE_HIP(hipMemcpyAsync(dev.p, pinned, host.size(), hipMemcpyHostToDevice, s));
+        CBIE_HIP(hipMemcpyAsync(dev.p, P, used, hipMemcpyHostToDevice, s));
         if (!staged_ev) CBIE_HIP(hipEventCreateWithFlags(&staged_ev, hipEventDisableTiming));
         CBIE_HIP(hipEventRecord(staged_ev, s));
         staged_gen = store.launches;   // the launch number this program gets
+        const double tb2 = now_s();
+        t_ex_stage += tb2 - tb1;
         auto keep = [&](std::function<void(hipStream_t)> f) {
             if (rec_into) rec_into->seq.push_back(std::move(f));
         };
@@ -815,6 +848,7 @@ template <typename T> struct HF {
             }
         }
         levels_run += L;
+        t_ex_launch += now_s() - tb2;
         store.launched();
         gd.clear(); glev.clear(); gshape.clear(); gseq.clear(); galg.clear();
         cd.clear(); clev.clear(); ld.clear(); llev.clear(); cseq.clear(); lseq.clear();
@@ -926,8 +960,7 @@ template <typename T> struct HF {
             if ((int64_t)S * d.m * d.n > ws_left) S = 1;
             if (S > 1) ws_left -= (int64_t)S * d.m * d.n;
             if (S <= 1) {
-                for (int m0 = 0; m0 < d.m; m0 += 64)
-                    for (int n0 = 0; n0 < d.n; n0 += 64) t.push_back(GemmTile{(int)e.size(), m0, n0, 0});
+                for (int q = 0; q < (int)tiles; ++q) t.push_back(GemmTile{(int)e.size(), q});
                 e.push_back(d);
                 continue;
             }
@@ -945,8 +978,7 @@ template <typename T> struct HF {
                 x.beta = cplx<double>{0.0, 0.0};
                 x.C = W + q * mn;
                 x.ldc = d.m;
-                for (int m0 = 0; m0 < d.m; m0 += 64)
-                    for (int n0 = 0; n0 < d.n; n0 += 64) t.push_back(GemmTile{(int)e.size(), m0, n0, 0});
+                for (int q = 0; q < (int)tiles; ++q) t.push_back(GemmTile{(int)e.size(), q});
                 e.push_back(x);
             }
             const int nsplit = (d.k + kc - 1) / kc;
@@ -1283,7 +1315,7 @@ template <typename T> struct HF {
         mem_grow = mem_budget > store.live ? mem_budget - store.live : 0;
     }
     void relieve_storage() {
-        if (store.live <= mem_next) return;
+        if (store.live <= mem_next || rec_into) return;
         ++flush_mem;
         flush_all();
         mem_next = std::max(mem_budget, store.live + std::max<size_t>(mem_grow / 4, 1));
@@ -1501,8 +1533,10 @@ template <typename T> struct HF {
     };
     void update(const View& C, const View& A, const View& B, cplx<T> al) {
         // no scratch view is live outside the pinned shortcuts: when the
-        // program's temporaries grow large, run it and recycle them
-        if (pin == 0 && scratch.live > kScratchBudget) execute();
+        // program's temporaries grow large, run it and recycle them.  A
+        // substitution recorded for replay is one program (its launches keep
+        // pointers into its one descriptor buffer): it never goes out early.
+        if (pin == 0 && !rec_into && scratch.live > kScratchBudget) execute();
         const bool hc = kind(C) == HIER, ha = kind(A) == HIER, hb = kind(B) == HIER;
         const Busy busy_a(lr_busy, kind(A) == LRK ? leaf_of(A) : -1), busy_b(lr_busy, kind(B) == LRK ? leaf_of(B) : -1);
         // low-rank times hierarchical: the product has the operand's rank;
@@ -1891,12 +1925,13 @@ template <typename T> struct HF {
     // 0: never)
     const int64_t exec_after_update =
         getenv("CBIE_EXEC_UPDATE") ? atoll(getenv("CBIE_EXEC_UPDATE")) : 1000;
+
 };
 
 // ------------------------------------------------------------ kernel timer
 void Ctx::KernelTimer::begin(hipStream_t s) {
     if (used + 2 > ev.size()) {
-        if (ev.size() >= 4096) harvest();
+        harvest_ready();
         while (used + 2 > ev.size()) {
             hipEvent_t e;
             CBIE_HIP(hipEventCreate(&e));
@@ -1918,6 +1953,21 @@ void Ctx::KernelTimer::harvest() {
         seconds += 1e-3 * ms;
     }
     used = 0;
+}
+void Ctx::KernelTimer::harvest_ready() {
+    size_t done = 0;
+    while (done < used) {
+        const hipError_t q = hipEventQuery(ev[done + 1]);
+        if (q == hipErrorNotReady) break;
+        CBIE_HIP(q);
+        float ms = 0.f;
+        CBIE_HIP(hipEventElapsedTime(&ms, ev[done], ev[done + 1]));
+        seconds += 1e-3 * ms;
+        done += 2;
+    }
+    if (done == 0) return;
+    std::rotate(ev.begin(), ev.begin() + done, ev.begin() + used);
+    used -= done;
 }
 Ctx::KernelTimer::~KernelTimer() {
     for (hipEvent_t e : ev) (void)hipEventDestroy(e);
@@ -2041,6 +2091,9 @@ template <typename T> static void run_factor(Ctx& c, HF<T>& f) {
     c.stats.gemm_seconds = c.gemm_timer.seconds;
     c.leaf_timer.harvest();
     c.stats.leaf_lu_seconds = c.leaf_timer.seconds;
+    if (getenv("CBIE_DEBUG"))
+        fprintf(stderr, "[cbie] execute: build %.3f s, stage %.3f s, launch %.3f s; %lld GEMM tiles staged\n", f.t_ex_build,
+                f.t_ex_stage, f.t_ex_launch, (long long)f.n_tiles_staged);
     if (getenv("CBIE_DEBUG"))
         fprintf(stderr,
                 "[cbie] levels %lld flushes %lld (width overflows %lld) rounds %lld widths lrA %.0f lrB %.0f dd %.0f flushK %.0f; "

@@ -7,8 +7,9 @@ namespace cbie {
 // Largest rank an admissible block may reach in the ACA (columns of its
 // workspace); blocks that hit it are reported as not converged.
 constexpr int kAcaMaxRank = 512;
-// explicit block copies compressed per round (N-Mueller), complex128 entries
-constexpr int64_t kAcaDense = int64_t(1) << 28;
+// most explicit block copies compressed per round (N-Mueller), complex128
+// entries (32 GiB)
+constexpr int64_t kAcaDense = int64_t(1) << 31;
 
 struct AcaJob {
     int row_node0, row_nodes;    // tree-order node range of the rows

@@ -75,3 +75,4 @@ def test_graph_replays_equal_eager_runs(prec):
     print(f"prec {prec}: replays {s.stats()['solve_replays']}, vs dense oracle {e:.2e}")
     assert e < 1e-7
     s.close()
+
