@@ -654,21 +654,35 @@ void rand_batched(hipStream_t s, const RandDesc<T>* d_desc, int n) {
 }
 
 // ------------------------------------------------------ pivoted Cholesky
-// LDS path (p <= PL): the Gram matrix is copied to LDS and factored
-// there; pivoting permutes logical indices (perm) instead of moving data;
-// pivots are chosen by one wave maximum of packed keys.  R^{-1} is then
-// formed one column per wave: back substitution with lane-parallel sums.
+// LDS path (p <= PL): the Hermitian Gram matrix is copied to LDS as its
+// upper triangle in physical indices, packed by columns (entry (a, b),
+// a <= b, at a + b (b + 1) / 2; (b, a) is its conjugate), and factored
+// there.  Pivoting permutes logical indices (perm) instead of moving data;
+// pivots are chosen by one wave maximum of packed keys.  Row j of R is
+// written over the slots {perm[j], perm[t]} (t > j), which no later step
+// reads as Gram entries, and the downdate touches each remaining unordered
+// pair once.  R^{-1} is then formed one column per wave: back substitution
+// with lane-parallel sums.
 template <typename T> struct PcholLds {
-    static constexpr int PL = sizeof(T) == 4 ? 128 : 90;
+    // packed triangle plus four back-substitution vectors within 160 KB of LDS
+    static constexpr int PL = sizeof(T) == 4 ? 128 : 132;
+    static constexpr int SLOTS = PL * (PL + 1) / 2;
 };
+__device__ inline int tri_slot(int a, int b) {
+    const int lo = min(a, b), hi = max(a, b);
+    return lo + hi * (hi + 1) / 2;
+}
 template <typename T>
 __device__ void pchol_lds(const PcholDesc<T>& D, cplx<T>* G, int* perm, unsigned* wmax, double* red,
                           cplx<T>* xs) {
     const int p = D.p, tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    for (int e = tid; e < p * p; e += 256) G[e] = D.G[e];
+    const gcptr<T> Gg = as_global((const cplx<T>*)D.G);
+    for (int b = wave; b < p; b += 4)
+        for (int a = lane; a <= b; a += 64) G[a + b * (b + 1) / 2] = gld<T>(Gg + a + (int64_t)b * p);
     for (int i = tid; i < p; i += 256) perm[i] = i;
+    __syncthreads();
     double m0 = 0.0;
-    for (int i = tid; i < p; i += 256) m0 = fmax(m0, (double)D.G[i + (int64_t)i * p].re);
+    for (int i = tid; i < p; i += 256) m0 = fmax(m0, (double)G[i + i * (i + 1) / 2].re);
     for (int off = 32; off > 0; off >>= 1) m0 = fmax(m0, __shfl_xor(m0, off));
     if (lane == 0) red[wave] = m0;
     __syncthreads();
@@ -677,7 +691,8 @@ __device__ void pchol_lds(const PcholDesc<T>& D, cplx<T>* G, int* perm, unsigned
     for (int j = 0; j < p; ++j) {
         unsigned key = 0u;
         for (int t = j + tid; t < p; t += 256) {
-            const double v = fmax((double)G[perm[t] * (p + 1)].re, 0.0);
+            const int q = perm[t];
+            const double v = fmax((double)G[q + q * (q + 1) / 2].re, 0.0);
             key = max(key, ((unsigned)(__double_as_longlong(v) >> 40) << 8) | (unsigned)(255 - t));
         }
         key = __ockl_wfred_max_u32(key);
@@ -686,7 +701,7 @@ __device__ void pchol_lds(const PcholDesc<T>& D, cplx<T>* G, int* perm, unsigned
         const unsigned best = max(max(wmax[0], wmax[1]), max(wmax[2], wmax[3]));
         const int bi = 255 - (int)(best & 255u);
         const int pj = perm[bi], pjo = perm[j];
-        const double bv = (double)G[pj * (p + 1)].re;
+        const double bv = (double)G[pj + pj * (pj + 1) / 2].re;
         if (!(bv > D.thr * dmax0) || bv <= 0.0) {
             k = j;
             break;
@@ -697,41 +712,53 @@ __device__ void pchol_lds(const PcholDesc<T>& D, cplx<T>* G, int* perm, unsigned
             perm[j] = pj;
         }
         const T rjj = sqrt((T)bv);
-        // row j of R (logical), stored in place; thread 0 changes only
-        // perm[j] and perm[bi], so logical t > j maps to q below
+        // row j of R: R[j, t] = G(pj, q) / rjj with q the physical index of
+        // logical t > j (thread 0 changes only perm[j] and perm[bi])
         for (int t = j + 1 + tid; t < p; t += 256) {
             const int q = bi == t ? pjo : perm[t];
-            G[pj + q * p] = (T(1) / rjj) * G[pj + q * p];
+            const int sl = tri_slot(pj, q);
+            const cplx<T> g = pj <= q ? G[sl] : conj(G[sl]);
+            G[sl] = (T(1) / rjj) * g;
         }
-        if (tid == 0) G[pj * (p + 1)] = cplx<T>{rjj, (T)0};
+        if (tid == 0) G[pj + pj * (pj + 1) / 2] = cplx<T>{rjj, (T)0};
         __syncthreads();
+        // downdate G(a, b) -= conj(R[j, a]) R[j, b] over the unordered pairs of
+        // the remaining logical indices, stored at (min, max)
         const int R = p - j - 1;
-        for (int e = tid; e < R * R; e += 256) {
-            const int pt = perm[j + 1 + e % R], pu = perm[j + 1 + e / R];
-            cfma(G[pt + pu * p], -conj(G[pj + pt * p]), G[pj + pu * p]);
+        for (int u = wave; u < R; u += 4) {
+            const int b = perm[j + 1 + u];
+            const cplx<T> rb = G[tri_slot(pj, b)];
+            for (int t = lane; t <= u; t += 64) {
+                const int a = perm[j + 1 + t];
+                const cplx<T> ra = G[tri_slot(pj, a)];
+                if (a <= b) cfma(G[tri_slot(a, b)], -conj(ra), rb);
+                else cfma(G[tri_slot(a, b)], -conj(rb), ra);
+            }
         }
         __syncthreads();
     }
-    // S = Pi R^{-1}: column j of R^{-1} solves R x = e_j (x zero below j)
+    // S = Pi R^{-1}: column j of R^{-1} solves R x = e_j (x zero below j);
+    // R[t, u] (t < u) sits in slot {perm[t], perm[u]}
     cplx<T>* x = xs + wave * PcholLds<T>::PL;
-    for (int e = tid; e < p * p; e += 256) D.S[e] = bz<T>();
+    const gptr<T> Sg = as_global(D.S);
+    for (int e = tid; e < p * p; e += 256) gst<T>(Sg + e, bz<T>());
     __syncthreads();
     for (int j = wave; j < k; j += 4) {
         for (int t = j; t >= 0; --t) {
             cplx<T> acc = bz<T>();
             const int pt = perm[t];
-            for (int u = t + 1 + lane; u <= j; u += 64) cfma(acc, G[pt + perm[u] * p], x[u]);
+            for (int u = t + 1 + lane; u <= j; u += 64) cfma(acc, G[tri_slot(pt, perm[u])], x[u]);
             for (int off = 32; off > 0; off >>= 1) {
                 acc.re += __shfl_xor(acc.re, off);
                 acc.im += __shfl_xor(acc.im, off);
             }
             const cplx<T> num = cplx<T>{(T)(t == j ? 1 : 0), (T)0} - acc;
-            const cplx<T> xt = cdiv(num, G[pt * (p + 1)]);
+            const cplx<T> xt = cdiv(num, G[pt + pt * (pt + 1) / 2]);
             if (lane == 0) x[t] = xt;
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         }
-        for (int t = lane; t <= j; t += 64) D.S[perm[t] + (int64_t)j * p] = x[t];
+        for (int t = lane; t <= j; t += 64) gst<T>(Sg + perm[t] + (int64_t)j * p, x[t]);
         __builtin_amdgcn_wave_barrier();
     }
     if (tid == 0) D.k_out[0] = k;
@@ -743,11 +770,14 @@ __global__ __launch_bounds__(256) void k_pchol_b(const PcholDesc<T>* __restrict_
     const PcholDesc<T> D = descs[blockIdx.x];
     const int p = D.p;
     constexpr int PL = PcholLds<T>::PL;
-    static_assert(PL * PL >= 4 * 512, "back-substitution vectors");
+    static_assert(PcholLds<T>::SLOTS >= 4 * 512, "back-substitution vectors");
     __shared__ int perm[512];
-    __shared__ cplx<T> Gl[PL * PL];   // the matrix when p <= PL, else the vectors of the back substitution
+    // the packed matrix when p <= PL; on the global path the pivot row
+    // during the factorization, then R packed (rank <= PL) or the vectors
+    // of the back substitution
+    __shared__ cplx<T> Gl[PcholLds<T>::SLOTS];
+    __shared__ cplx<T> xs[4 * PL];
     {
-        __shared__ cplx<T> xs[4 * PL];
         __shared__ unsigned wmax[4];
         __shared__ double red[4];
         if (p <= PL) {
@@ -770,6 +800,7 @@ __global__ __launch_bounds__(256) void k_pchol_b(const PcholDesc<T>* __restrict_
         kk = p;
     }
     __syncthreads();
+    cplx<T>* rrow = Gl;   // row j of R, indexed by column
     for (int j = 0; j < p; ++j) {
         // pivot: largest remaining diagonal
         double bv = -1.0;
@@ -809,40 +840,67 @@ __global__ __launch_bounds__(256) void k_pchol_b(const PcholDesc<T>* __restrict_
             if (tid == 0) { const int x = perm[j]; perm[j] = perm[bi]; perm[bi] = x; }
             __syncthreads();
         }
-        // row j of R: R[j, j] = sqrt(G[j, j]), R[j, t] = G[j, t] / R[j, j]
+        // row j of R: R[j, j] = sqrt(G[j, j]), R[j, t] = G[j, t] / R[j, j],
+        // kept in LDS for the downdate
         const T rjj = sqrt((T)bv);
-        for (int t = j + 1 + tid; t < p; t += 256)
-            gst<T>(G + j + (int64_t)t * p, (T(1) / rjj) * gld<T>(G + j + (int64_t)t * p));
-        __syncthreads();
+        for (int t = j + 1 + tid; t < p; t += 256) {
+            const cplx<T> v = (T(1) / rjj) * gld<T>(G + j + (int64_t)t * p);
+            gst<T>(G + j + (int64_t)t * p, v);
+            rrow[t] = v;
+        }
         if (tid == 0) gst<T>(G + j + (int64_t)j * p, cplx<T>{rjj, (T)0});
-        // trailing downdate G[t, u] -= conj(R[j, t]) R[j, u], t, u > j
-        const int R = p - j - 1;
-        for (int64_t e = tid; e < (int64_t)R * R; e += 256) {
-            const int t = j + 1 + (int)(e % R), u = j + 1 + (int)(e / R);
-            cplx<T> v = gld<T>(G + t + (int64_t)u * p);
-            cfma(v, -conj(gld<T>(G + j + (int64_t)t * p)), gld<T>(G + j + (int64_t)u * p));
-            gst<T>(G + t + (int64_t)u * p, v);
+        __syncthreads();
+        // trailing downdate G[t, u] -= conj(R[j, t]) R[j, u], t, u > j: lanes
+        // along columns (coalesced), four elements in flight per thread
+        const unsigned R = (unsigned)(p - j - 1), RR = R * R;
+        for (unsigned e0 = tid; e0 < RR; e0 += 4 * 256) {
+            cplx<T> v[4];
+            gptr<T> g[4];
+            cplx<T> rt[4], ru[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const unsigned e = e0 + 256u * q;
+                const unsigned t = e < RR ? e % R : 0u, u = e < RR ? e / R : 0u;
+                g[q] = G + (j + 1 + (int)t) + (int64_t)(j + 1 + (int)u) * p;
+                rt[q] = rrow[j + 1 + t];
+                ru[q] = rrow[j + 1 + u];
+                if (e < RR) v[q] = gld<T>(g[q]);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q)
+                if (e0 + 256u * q < RR) {
+                    cfma(v[q], -conj(rt[q]), ru[q]);
+                    gst<T>(g[q], v[q]);
+                }
         }
         __syncthreads();
     }
     __syncthreads();
     const int k = kk;
     // S = Pi R_kk^{-1}: column j solves R x = e_j by back substitution, one
-    // wave per column with its lanes over the inner sums, x in LDS
+    // wave per column with its lanes over the inner sums.  R (upper, k x k)
+    // is staged in LDS, packed by columns, when it fits; x in LDS
     const gptr<T> Sg = as_global(D.S);
     for (int64_t e = tid; e < (int64_t)p * p; e += 256) gst<T>(Sg + e, bz<T>());
+    const bool rl = k <= PL;
+    if (rl)
+        for (int u = wave; u < k; u += 4)
+            for (int t = lane; t <= u; t += 64) Gl[t + u * (u + 1) / 2] = gld<T>(G + t + (int64_t)u * p);
     __syncthreads();
-    cplx<T>* x = Gl + wave * 512;
+    cplx<T>* x = rl ? xs + wave * PL : Gl + wave * 512;
     for (int j = wave; j < k; j += 4) {
         for (int t = j; t >= 0; --t) {
             cplx<T> acc = bz<T>();
-            for (int u = t + 1 + lane; u <= j; u += 64) cfma(acc, gld<T>(G + t + (int64_t)u * p), x[u]);
+            if (rl)
+                for (int u = t + 1 + lane; u <= j; u += 64) cfma(acc, Gl[t + u * (u + 1) / 2], x[u]);
+            else
+                for (int u = t + 1 + lane; u <= j; u += 64) cfma(acc, gld<T>(G + t + (int64_t)u * p), x[u]);
             for (int off = 32; off > 0; off >>= 1) {
                 acc.re += __shfl_xor(acc.re, off);
                 acc.im += __shfl_xor(acc.im, off);
             }
             const cplx<T> num = cplx<T>{(T)(t == j ? 1 : 0), (T)0} - acc;
-            const cplx<T> xt = cdiv(num, gld<T>(G + t + (int64_t)t * p));
+            const cplx<T> xt = cdiv(num, rl ? Gl[t + t * (t + 1) / 2] : gld<T>(G + t + (int64_t)t * p));
             if (lane == 0) x[t] = xt;
             __builtin_amdgcn_wave_barrier();
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
