@@ -105,6 +105,7 @@ struct Ctx {
         std::vector<hipEvent_t> ev;
         size_t used = 0;
         double seconds = 0.0;
+        std::vector<float>* log = nullptr;   // each pair's milliseconds, in order (debug)
         void begin(hipStream_t s);
         void end(hipStream_t s);
         void harvest();

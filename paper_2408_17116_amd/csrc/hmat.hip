@@ -596,7 +596,10 @@ template <typename T> struct HF {
         Ctx::KernelTimer& tm = c.gemm_timer;
         if (tm.on) tm.begin(s);
         gemm_batched<T>(s, d, t, ntiles, sh);
-        if (tm.on) tm.end(s);
+        if (tm.on) {
+            tm.end(s);
+            if (debug) launch_log.push_back(LaunchRec{ntiles, sh, fl});
+        }
         ++launches;
         ++c.stats.gemm_launches;
         c.stats.gemm_flops += fl;
@@ -1302,6 +1305,13 @@ template <typename T> struct HF {
             for (int k = 0; k < 4; ++k) collect_lr(b.child[k], out);
     }
     int64_t flushes = 0, flush_overflow = 0, flush_mem = 0;
+    // timed GEMM launches (debug): tiles, shape and flops, in launch order
+    struct LaunchRec {
+        int tiles, sh;
+        double fl;
+    };
+    std::vector<LaunchRec> launch_log;
+    std::vector<float> launch_ms;
     // Storage pressure: the factors grow by appended update columns (up to
     // kmax per block) and dense accumulators until a recompression folds
     // them.  When the live storage passes mem_next elements every pending
@@ -1951,6 +1961,7 @@ void Ctx::KernelTimer::harvest() {
         float ms = 0.f;
         CBIE_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
         seconds += 1e-3 * ms;
+        if (log) log->push_back(ms);
     }
     used = 0;
 }
@@ -1963,6 +1974,7 @@ void Ctx::KernelTimer::harvest_ready() {
         float ms = 0.f;
         CBIE_HIP(hipEventElapsedTime(&ms, ev[done], ev[done + 1]));
         seconds += 1e-3 * ms;
+        if (log) log->push_back(ms);
         done += 2;
     }
     if (done == 0) return;
@@ -2034,6 +2046,10 @@ template <typename T> static std::shared_ptr<HF<T>> make_factor(Ctx& c) {
 
 template <typename T> static void run_factor(Ctx& c, HF<T>& f) {
     Tuner<T>::tune(c.stream, f.debug);
+    if (f.debug && c.gemm_timer.on) {
+        c.gemm_timer.harvest();
+        c.gemm_timer.log = &f.launch_ms;
+    }
     {
         const char* em = getenv("CBIE_FACTOR_MEM");
         size_t fr = 0, tot = 0;
@@ -2089,6 +2105,37 @@ template <typename T> static void run_factor(Ctx& c, HF<T>& f) {
     c.stats.n_kernel_launches = f.launches;
     c.gemm_timer.harvest();
     c.stats.gemm_seconds = c.gemm_timer.seconds;
+    if (c.gemm_timer.log == &f.launch_ms) {
+        c.gemm_timer.log = nullptr;
+        // GEMM launches by shape, work-groups and mean depth per tile
+        const size_t n = std::min(f.launch_log.size(), f.launch_ms.size());
+        const int NT = 5, NK = 5;
+        const int tb[NT] = {256, 1024, 4096, 16384, 1 << 30};
+        const double kbnd[NK] = {64, 128, 256, 512, 1e30};
+        double ms[kNumTileShapes][NT][NK] = {}, fl[kNumTileShapes][NT][NK] = {};
+        int cnt[kNumTileShapes][NT][NK] = {};
+        for (size_t i = 0; i < n; ++i) {
+            const auto& r = f.launch_log[i];
+            const double kbar = r.fl / ((double)std::max(r.tiles, 1) * 8.0 * tile_rows(r.sh) * tile_cols(r.sh));
+            int a = 0, b = 0;
+            while (r.tiles >= tb[a]) ++a;
+            while (kbar >= kbnd[b]) ++b;
+            ms[r.sh][a][b] += f.launch_ms[i];
+            fl[r.sh][a][b] += r.fl;
+            ++cnt[r.sh][a][b];
+        }
+        fprintf(stderr, "[cbie] GEMM launches (shape, work-groups <256/<1k/<4k/<16k/more x mean tile depth "
+                        "<64/<128/<256/<512/more): ms, launches, TFLOP/s executed\n");
+        for (int sh = 0; sh < kNumTileShapes; ++sh)
+            for (int a = 0; a < NT; ++a) {
+                fprintf(stderr, "[cbie]  %dx%d %s:", tile_rows(sh), tile_cols(sh),
+                        a == 0 ? "<256" : a == 1 ? "<1k " : a == 2 ? "<4k " : a == 3 ? "<16k" : "more");
+                for (int b = 0; b < NK; ++b)
+                    fprintf(stderr, " %7.1f/%5d/%5.1f |", ms[sh][a][b], cnt[sh][a][b],
+                            ms[sh][a][b] > 0 ? fl[sh][a][b] / (ms[sh][a][b] * 1e-3) / 1e12 : 0.0);
+                fprintf(stderr, "\n");
+            }
+    }
     c.leaf_timer.harvest();
     c.stats.leaf_lu_seconds = c.leaf_timer.seconds;
     if (getenv("CBIE_DEBUG"))
