@@ -739,13 +739,22 @@ template <typename T> struct HF {
             Seg& sg = seg[lv];
             Batch bt;
             ws.reset();
-            int64_t lt = 0;
+            // a level whose unforced thin products (tuned to the 256 x 32 or
+            // 32 x 256 tiles) add up to few tiles runs them on 64 x 64 tiles
+            // with the rest: one launch instead of up to three small ones
+            int64_t thin = 0;
             for (int i : gl[lv])
-                lt += ntiles(gd[i], gshape[i] >= 0 ? gshape[i] : pick_shape(gd[i].m, gd[i].n, gd[i].k));
-            for (int i : gl[lv]) {
-                const GemmDesc<T>& d = gd[i];
-                add_gemm(bt, d, gshape[i] >= 0 ? gshape[i] : pick_shape(d.m, d.n, d.k), gshape[i] >= 0, lt, ws, galg[i]);
-            }
+                if (gshape[i] < 0) {
+                    const int sh = pick_shape(gd[i].m, gd[i].n, gd[i].k);
+                    if (sh != kTile64x64) thin += ntiles(gd[i], sh);
+                }
+            const bool fold = thin > 0 && thin < merge_thin;
+            auto shape_of = [&](int i) {
+                return gshape[i] >= 0 ? gshape[i] : (fold ? (int)kTile64x64 : pick_shape(gd[i].m, gd[i].n, gd[i].k));
+            };
+            int64_t lt = 0;
+            for (int i : gl[lv]) lt += ntiles(gd[i], shape_of(i));
+            for (int i : gl[lv]) add_gemm(bt, gd[i], shape_of(i), gshape[i] >= 0, lt, ws, galg[i]);
             for (int sh = 0; sh < kNumTileShapes; ++sh) {
                 sg.g[sh] = put(bt.g[sh].data(), bt.g[sh].size() * sizeof(GemmDesc<T>));
                 sg.gt[sh] = put(bt.t[sh].data(), bt.t[sh].size() * sizeof(GemmTile));
@@ -1935,6 +1944,9 @@ template <typename T> struct HF {
     // 0: never)
     const int64_t exec_after_update =
         getenv("CBIE_EXEC_UPDATE") ? atoll(getenv("CBIE_EXEC_UPDATE")) : 1000;
+    // thin-shape tiles below which a level's thin products join its 64 x 64
+    // launch (CBIE_MERGE_THIN; 0: never)
+    const int64_t merge_thin = getenv("CBIE_MERGE_THIN") ? atoll(getenv("CBIE_MERGE_THIN")) : 4096;
 
 };
 
