@@ -383,7 +383,8 @@ def high_contrast(cbie, W, eps_list):
 def gemm_traffic(pipeline):
     """HBM bytes per k_zgemm launch from the committed counter runs
     (FETCH_SIZE + WRITE_SIZE, scaled by a copy kernel of known size), or
-    None when the GEMM source has changed since they were taken."""
+    None when the GEMM kernel or the scheduler that forms its launches has
+    changed since they were taken."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "k_zgemm_traffic_sphere_ka20_49152_mixed.json")
     if pipeline != "mixed" or not os.path.exists(path):
