@@ -860,6 +860,7 @@ template <typename T> struct HF {
             }
         }
         levels_run += L;
+        gpu_drained = false;
         t_ex_launch += now_s() - tb2;
         store.launched();
         gd.clear(); glev.clear(); gshape.clear(); gseq.clear(); galg.clear();
@@ -1056,7 +1057,14 @@ template <typename T> struct HF {
         const double t0 = now_s(), w0 = t_wait;
         recompress_(std::move(todo));
         t_recomp += now_s() - t0 - (t_wait - w0);
+        gpu_drained = true;   // it waited for its ranks: little is queued now
     }
+    // Set after a recompression has synchronized the stream; the next
+    // program then goes out as soon as it holds first_chunk products, so
+    // the GPU works while the host records the rest (CBIE_FIRST_CHUNK; 0:
+    // never).  Later programs keep their full level batches.
+    bool gpu_drained = false;
+    const int64_t first_chunk = getenv("CBIE_FIRST_CHUNK") ? atoll(getenv("CBIE_FIRST_CHUNK")) : 2000;
     void recompress_(std::vector<int> todo) {
         std::vector<int> pq(todo.size());
         for (size_t q = 0; q < todo.size(); ++q) {
@@ -1555,7 +1563,9 @@ template <typename T> struct HF {
         // program's temporaries grow large, run it and recycle them.  A
         // substitution recorded for replay is one program (its launches keep
         // pointers into its one descriptor buffer): it never goes out early.
-        if (pin == 0 && !rec_into && scratch.live > kScratchBudget) execute();
+        if (pin == 0 && !rec_into &&
+            (scratch.live > kScratchBudget || (gpu_drained && first_chunk > 0 && (int64_t)gd.size() >= first_chunk)))
+            execute();
         const bool hc = kind(C) == HIER, ha = kind(A) == HIER, hb = kind(B) == HIER;
         const Busy busy_a(lr_busy, kind(A) == LRK ? leaf_of(A) : -1), busy_b(lr_busy, kind(B) == LRK ? leaf_of(B) : -1);
         // low-rank times hierarchical: the product has the operand's rank;
