@@ -68,6 +68,7 @@ typedef struct cbie_ctx cbie_ctx;
 typedef enum { CBIE_MFIE_PEC = 0, CBIE_NMULLER = 1 } cbie_formulation;
 typedef enum { CBIE_PREC_C128 = 0, CBIE_PREC_C64_IR = 1 } cbie_precision;
 typedef enum { CBIE_RANK_ADAPTIVE = 0, CBIE_RANK_PREDICTED = 1 } cbie_rank_mode;
+typedef enum { CBIE_ORDER_ENTIRE = 0, CBIE_ORDER_COMPONENT = 1 } cbie_ordering;
 
 /* One patch of the equiangular cube sphere mapped onto an ellipsoid:
  * face f (0..5 = +x,-x,+y,-y,+z,-z), sub-square (i, j) of split x split,
@@ -155,6 +156,22 @@ cbie_status cbie_factor(cbie_ctx* ctx, cbie_precision prec);
  * cbie_solve_gmres still converges to the stored FP64 operator's solution
  * while it contracts.  Errors: EINVAL. */
 cbie_status cbie_set_factor_tolerance(cbie_ctx* ctx, double tol);
+
+/* Ordering of the unknowns for later factorizations (Sec. III, Fig. 3).
+ * CBIE_ORDER_ENTIRE (the default, Sec. III-B): one cluster tree over the
+ * nodes, every block holding all components of its nodes interleaved.
+ * CBIE_ORDER_COMPONENT (Sec. III-A, eqs. 22-28): per object, the unknowns
+ * ordered component by component and one H-matrix per component
+ * interaction block (MFIE: uu, uv, vu, vv; N-Mueller: the 16 of eq. 19),
+ * factored as the 2 x 2 block LU of eq. 23 (N-Mueller: nested twice) with
+ * the substitutions of eqs. 26-28.  The component blocks are taken from
+ * the compressed operator: dense leaves as strided copies, low-rank blocks
+ * as the matching rows of U and V, truncated at the factorization's
+ * truncation tolerance (t_factor_reorder in cbie_stats, part of t_factor).  Leaves hold a
+ * single component, so diagonal leaves are leaf_size / unknowns-per-node
+ * unknowns.  cbie_solve and cbie_solve_gmres take and return the original
+ * order either way.  Errors: EINVAL. */
+cbie_status cbie_set_factor_ordering(cbie_ctx* ctx, cbie_ordering ordering);
 
 /* Solve A x = b for nrhs right-hand sides (per object).  b_dev, x_dev:
  * complex128 device arrays, n_unknowns x nrhs, leading dimension ld,
@@ -301,6 +318,9 @@ typedef struct {
      * pressure (the factors grew by more than half the device memory free
      * when the factorization started, or by CBIE_FACTOR_MEM bytes) */
     int64_t factor_mem_flushes;
+    /* last factor in CBIE_ORDER_COMPONENT: seconds spent truncating the
+     * component blocks taken from the low-rank blocks (0 otherwise) */
+    double t_factor_reorder;
 } cbie_stats;
 cbie_status cbie_get_stats(cbie_ctx* ctx, void* stats_out, size_t bytes);
 

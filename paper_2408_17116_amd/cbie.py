@@ -20,13 +20,14 @@ OK, EINVAL, ENOMEM, EHIP, ESTATE, ENOCONV, ESINGULAR, EINTERNAL = 0, -1, -2, -3,
 MFIE_PEC, NMULLER = 0, 1
 PREC_C128, PREC_C64_IR = 0, 1
 RANK_ADAPTIVE, RANK_PREDICTED = 0, 1
+ORDER_ENTIRE, ORDER_COMPONENT = 0, 1
 
 EXPORTED = ["cbie_create", "cbie_build_tree", "cbie_fill", "cbie_compress", "cbie_factor",
             "cbie_solve", "cbie_matvec", "cbie_rhs_planewave", "cbie_farfield", "cbie_get_stats",
             "cbie_set_profiling", "cbie_get_near_pairs", "cbie_export_dense", "cbie_last_error",
             "cbie_destroy", "cbie_get_block_features", "cbie_set_rank_model", "cbie_mlp_forward",
             "cbie_mlp_grad", "cbie_mlp_train", "cbie_matvec_noalloc", "cbie_solve_gmres",
-            "cbie_set_factor_tolerance"]
+            "cbie_set_factor_tolerance", "cbie_set_factor_ordering"]
 
 MLP_NFEAT, MLP_NPARAMS = 8, 4801
 
@@ -62,7 +63,8 @@ class Stats(C.Structure):
         ("leaf_lu_launches", C.c_int64), ("leaf_lu_flops", C.c_double), ("leaf_lu_seconds", C.c_double),
         ("quad_points", C.c_double), ("quad_flops", C.c_double),
         ("solve_factor_bytes", C.c_double), ("far_fill_seconds", C.c_double), ("gemm_bytes_alg", C.c_double),
-        ("gemm_flops_mfma", C.c_double), ("factor_mem_flushes", C.c_int64)]
+        ("gemm_flops_mfma", C.c_double), ("factor_mem_flushes", C.c_int64),
+        ("t_factor_reorder", C.c_double)]
 
 
 _lib = None
@@ -88,6 +90,7 @@ def load(path: str = LIB_PATH):
         "cbie_matvec_noalloc": ([vp, i32, vp, vp, C.c_long], i32),
         "cbie_solve_gmres": ([vp, i32, vp, vp, C.c_long, dbl, i32, i32, C.POINTER(i32)], i32),
         "cbie_set_factor_tolerance": ([vp, dbl], i32),
+        "cbie_set_factor_ordering": ([vp, i32], i32),
         "cbie_rhs_planewave": ([vp, i32, vp, vp, vp, C.c_long], i32),
         "cbie_farfield": ([vp, i32, vp, C.c_long, i32, vp, vp], i32),
         "cbie_get_stats": ([vp, vp, C.c_size_t], i32),
@@ -183,6 +186,10 @@ class Solver:
     def set_factor_tolerance(self, tol):
         """Truncation tolerance of later factorizations (0: the compress tolerance)."""
         self._check(self.lib.cbie_set_factor_tolerance(self.h, tol))
+
+    def set_factor_ordering(self, ordering):
+        """ORDER_ENTIRE (default) or ORDER_COMPONENT for later factorizations."""
+        self._check(self.lib.cbie_set_factor_ordering(self.h, ordering))
 
     def _cols(self, v):
         """(n,) or (n, m) complex128 cuda tensor -> contiguous (m, n) tensor."""

@@ -191,6 +191,13 @@ cbie_status cbie_set_factor_tolerance(cbie_ctx* ctx, double tol) {
     });
 }
 
+cbie_status cbie_set_factor_ordering(cbie_ctx* ctx, cbie_ordering ordering) {
+    return guarded(ctx, [&](Ctx& c) {
+        CBIE_REQUIRE(ordering == CBIE_ORDER_ENTIRE || ordering == CBIE_ORDER_COMPONENT, CBIE_EINVAL, "ordering");
+        c.factor_ordering = (int)ordering;
+    });
+}
+
 cbie_status cbie_solve(cbie_ctx* ctx, int nrhs, const void* b_dev, void* x_dev, long ld, double ir_tol,
                        int ir_maxit, int* ir_iters_out) {
     return guarded(ctx, [&](Ctx& c) {

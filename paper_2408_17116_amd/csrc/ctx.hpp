@@ -74,6 +74,7 @@ struct Ctx {
     DBuf<DenseBlockDev> d_lblk;
     double aca_tol = 1e-6;
     double factor_tol = 0.0;                // truncation of formatted sums (0: aca_tol)
+    int factor_ordering = CBIE_ORDER_ENTIRE;   // unknown ordering of the factorization
 
     // exclusive prefix sums of the low-rank ranks (nl + 1 entries, set by
     // compress): block b's V^T x occupies rows prefix[b] * nrhs .. of the

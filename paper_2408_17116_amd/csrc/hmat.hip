@@ -236,10 +236,65 @@ template <typename T> struct Tuner {
     }
 };
 
+// The block structure a factorization runs on: the context's tree, whose
+// blocks hold all components of their nodes interleaved (the entire-matrix
+// ordering, Sec. III-B), or its component-wise counterpart (Sec. III-A,
+// eqs. 22-23), whose dense leaves are laid out afresh and whose unknowns
+// are permuted object by object.
+struct FactorLayout {
+    int ordering = CBIE_ORDER_ENTIRE;
+    const Tree* tree = nullptr;
+    const std::vector<DenseBlockDev>* dblk = nullptr;
+    ComponentTree comp;
+    std::vector<DenseBlockDev> comp_dblk;
+    DBuf<int> d_perm;   // component-wise: tree-order unknown -> factor-order unknown
+};
+
+static std::shared_ptr<FactorLayout> make_layout(Ctx& c) {
+    auto L = std::make_shared<FactorLayout>();
+    L->ordering = c.factor_ordering;
+    if (L->ordering == CBIE_ORDER_ENTIRE) {
+        L->tree = &c.tree;
+        L->dblk = &c.dblk;
+        return L;
+    }
+    L->comp = component_tree(c.tree, c.upn);
+    const Tree& C = L->comp.tree;
+    L->comp_dblk.resize(C.dense_blocks.size());
+    int64_t off = 0;
+    for (size_t d = 0; d < C.dense_blocks.size(); ++d) {
+        const Block& B = C.blocks[C.dense_blocks[d]];
+        const Cluster &t = C.clusters[B.t], &u = C.clusters[B.s];
+        const DenseBlockDev& src = c.dblk[L->comp.dense_src[d][0]];
+        CBIE_REQUIRE(src.ld == c.upn * src.row_nodes && t.nunk() == src.row_nodes && u.nunk() == src.col_nodes, -7,
+                     "component layout: dense leaf " + std::to_string(d) + " does not match its source");
+        DenseBlockDev& D = L->comp_dblk[d];
+        D = src;
+        D.offset = off;
+        D.ld = src.row_nodes;
+        D.upn = 1;
+        off += (int64_t)src.row_nodes * src.col_nodes;
+    }
+    CBIE_REQUIRE(off == c.stats.dense_entries, -7, "component layout: dense entries differ from the fill's");
+    std::vector<int> perm(c.n_unk);
+    for (int root : c.tree.roots) {
+        const Cluster& R = c.tree.clusters[root];
+        for (int i = 0; i < R.nodes; ++i)
+            for (int a = 0; a < c.upn; ++a)
+                perm[(size_t)c.upn * (R.node0 + i) + a] = c.upn * R.node0 + a * R.nodes + i;
+    }
+    L->d_perm.upload(perm, c.stream);
+    L->tree = &L->comp.tree;
+    L->dblk = &L->comp_dblk;
+    return L;
+}
+
 template <typename T> struct HF {
     Ctx& c;
     hipStream_t s;
+    std::shared_ptr<FactorLayout> lay;
     const Tree& T_;
+    const std::vector<DenseBlockDev>& leafd;   // dense leaves: offset into dense, leading dimension
     double tol;
     DBuf<cplx<T>> dense;
     std::vector<int64_t> piv_off, inv_off;   // per dense block (diagonal leaves), -1 otherwise
@@ -254,7 +309,8 @@ template <typename T> struct HF {
         int K = 0, cap = 0;
         cplx<T>* D = nullptr;   // dense accumulator of dense x dense updates (m x n)
         bool dirty = false;     // D holds pending updates
-        bool pending() const { return K > r || dirty; }
+        bool fresh = false;     // taken from a larger block: truncate at the next recompression
+        bool pending() const { return K > r || dirty || fresh; }
     };
     static constexpr int64_t kDenseAccMax = int64_t(1) << 26;   // entries
     std::vector<LR> lr;
@@ -306,7 +362,8 @@ template <typename T> struct HF {
     hipEvent_t staged_ev = nullptr;   // recorded after the last program's descriptor copy
     int64_t staged_gen = -1;          // that program's launch number (-1: none)
 
-    HF(Ctx& cc, double t) : c(cc), s(cc.stream), T_(cc.tree), tol(t) {}
+    HF(Ctx& cc, double t, std::shared_ptr<FactorLayout> l)
+        : c(cc), s(cc.stream), lay(std::move(l)), T_(*lay->tree), leafd(*lay->dblk), tol(t) {}
     ~HF() {
         for (auto e : dev_ev)
             if (e) (void)hipEventDestroy(e);
@@ -419,7 +476,7 @@ template <typename T> struct HF {
         cseq.push_back(seq++);
     }
     void rec_leaf(int leaf) {
-        const DenseBlockDev& db = c.dblk[leaf];
+        const DenseBlockDev& db = leafd[leaf];
         CBIE_REQUIRE(db.ld <= 256, CBIE_EINVAL, "diagonal leaf above 256 unknowns: use leaf_size <= 256");
         cplx<T>* LP = inv.p + inv_off[leaf];
         ld.push_back(LeafDesc<T>{db.ld, db.ld, dense.p + db.offset, piv.p + piv_off[leaf], info.p + leaf, LP,
@@ -1261,6 +1318,7 @@ template <typename T> struct HF {
                 L.D = nullptr;
                 L.r = L.K = rr;
                 L.dirty = false;
+                L.fresh = false;
             }
             run_copies(cp);
             wait_stream();
@@ -1441,7 +1499,7 @@ template <typename T> struct HF {
     }
     cplx<T>* dptr(const View& v, int& ldp) const {
         if (v.blk < 0) { ldp = v.ld; return v.p; }
-        const DenseBlockDev& d = c.dblk[T_.blocks[v.blk].leaf_index];
+        const DenseBlockDev& d = leafd[T_.blocks[v.blk].leaf_index];
         ldp = d.ld;
         return dense.p + d.offset + (int64_t)v.c0 * d.ld + v.r0;
     }
@@ -1798,7 +1856,7 @@ template <typename T> struct HF {
         int ldx;
         cplx<T>* p = dptr(X, ldx);
         if (D.type == BLK_DENSE) {
-            apply_inverse('L', D.leaf_index, c.dblk[D.leaf_index].ld, p, ldx, X.n, res(X));
+            apply_inverse('L', D.leaf_index, leafd[D.leaf_index].ld, p, ldx, X.n, res(X));
             return;
         }
         const View X1 = sub(X, 0, -1), X2 = sub(X, 1, -1);
@@ -1812,7 +1870,7 @@ template <typename T> struct HF {
         int ldx;
         cplx<T>* p = dptr(X, ldx);
         if (D.type == BLK_DENSE) {
-            apply_inverse('U', D.leaf_index, c.dblk[D.leaf_index].ld, p, ldx, X.n, res(X));
+            apply_inverse('U', D.leaf_index, leafd[D.leaf_index].ld, p, ldx, X.n, res(X));
             return;
         }
         const View X1 = sub(X, 0, -1), X2 = sub(X, 1, -1);
@@ -1826,7 +1884,7 @@ template <typename T> struct HF {
         int ldx;
         cplx<T>* p = dptr(X, ldx);
         if (D.type == BLK_DENSE) {
-            apply_inverse('R', D.leaf_index, c.dblk[D.leaf_index].ld, p, ldx, X.m, res(X));
+            apply_inverse('R', D.leaf_index, leafd[D.leaf_index].ld, p, ldx, X.m, res(X));
             return;
         }
         const View X1 = sub(X, -1, 0), X2 = sub(X, -1, 1);
@@ -1840,7 +1898,7 @@ template <typename T> struct HF {
         int ldx;
         cplx<T>* p = dptr(X, ldx);
         if (D.type == BLK_DENSE) {
-            apply_inverse('T', D.leaf_index, c.dblk[D.leaf_index].ld, p, ldx, X.n, res(X));
+            apply_inverse('T', D.leaf_index, leafd[D.leaf_index].ld, p, ldx, X.n, res(X));
             return;
         }
         // U^T = [[U11^T, 0], [U12^T, U22^T]]: X1 := U11^{-T} X1; X2 -= U12^T X1; X2 := U22^{-T} X2
@@ -2026,43 +2084,76 @@ template <typename T> static std::shared_ptr<HF<T>> make_factor(Ctx& c) {
     // recovers the compression tolerance.
     double tol = c.factor_tol > 0.0 ? c.factor_tol : c.aca_tol;
     if (sizeof(T) == 4) tol = std::max(tol, 1e-5);
-    auto f = std::make_shared<HF<T>>(c, tol);
+    auto f = std::make_shared<HF<T>>(c, tol, make_layout(c));
     hipStream_t s = c.stream;
-    const Tree& T_ = c.tree;
+    const Tree& T_ = f->T_;
+    const std::vector<DenseBlockDev>& dblk = f->leafd;
     f->dense.alloc(std::max<int64_t>(c.stats.dense_entries, 1));
-    convert<double, T>(s, c.stats.dense_entries, c.dense.p, f->dense.p);
-    f->lr.resize(c.lblk.size());
-    f->lr_busy.assign(c.lblk.size(), 0);
-    std::vector<ConvDesc<double, T>> conv;
-    conv.reserve(2 * c.lblk.size());
-    for (size_t b = 0; b < c.lblk.size(); ++b) {
-        auto& L = f->lr[b];
-        L.m = c.upn * c.lblk[b].row_nodes;
-        L.n = c.upn * c.lblk[b].col_nodes;
-        L.r = L.K = c.lr.rank[b];
-        L.cap = std::max(L.r, 1);
-        L.U = f->store.alloc((size_t)L.m * L.cap);
-        L.V = f->store.alloc((size_t)L.n * L.cap);
-        conv.push_back(ConvDesc<double, T>{c.lr.mem.p + c.lr.u_off[b], L.U, (int64_t)L.m * L.r});
-        conv.push_back(ConvDesc<double, T>{c.lr.mem.p + c.lr.v_off[b], L.V, (int64_t)L.n * L.r});
+    const size_t nl = T_.lr_blocks.size();
+    f->lr.resize(nl);
+    f->lr_busy.assign(nl, 0);
+    if (f->lay->ordering == CBIE_ORDER_ENTIRE) {
+        convert<double, T>(s, c.stats.dense_entries, c.dense.p, f->dense.p);
+        std::vector<ConvDesc<double, T>> conv;
+        conv.reserve(2 * nl);
+        for (size_t b = 0; b < nl; ++b) {
+            auto& L = f->lr[b];
+            L.m = c.upn * c.lblk[b].row_nodes;
+            L.n = c.upn * c.lblk[b].col_nodes;
+            L.r = L.K = c.lr.rank[b];
+            L.cap = std::max(L.r, 1);
+            L.U = f->store.alloc((size_t)L.m * L.cap);
+            L.V = f->store.alloc((size_t)L.n * L.cap);
+            conv.push_back(ConvDesc<double, T>{c.lr.mem.p + c.lr.u_off[b], L.U, (int64_t)L.m * L.r});
+            conv.push_back(ConvDesc<double, T>{c.lr.mem.p + c.lr.v_off[b], L.V, (int64_t)L.n * L.r});
+        }
+        convert_batched<double, T>(s, conv);
+    } else {
+        // component (a, b) of a block holding all components of its nodes:
+        // its rows a, a + upn, ... and columns b, b + upn, ...; a low-rank
+        // block's U and V give theirs at the block's rank, truncated before
+        // the factorization starts
+        const int u = c.upn;
+        const ComponentTree& CT = f->lay->comp;
+        std::vector<SliceDesc<double, T>> sl;
+        sl.reserve(dblk.size() + 2 * nl);
+        for (size_t d = 0; d < dblk.size(); ++d) {
+            const DenseBlockDev& src = c.dblk[CT.dense_src[d][0]];
+            const int a = CT.dense_src[d][1], b = CT.dense_src[d][2];
+            sl.push_back(SliceDesc<double, T>{c.dense.p + src.offset + a + (int64_t)b * src.ld, f->dense.p + dblk[d].offset,
+                                              src.row_nodes, src.col_nodes, u, (int64_t)u * src.ld, dblk[d].ld});
+        }
+        for (size_t l = 0; l < nl; ++l) {
+            const int sb = CT.lr_src[l][0], a = CT.lr_src[l][1], b = CT.lr_src[l][2];
+            auto& L = f->lr[l];
+            L.m = c.lblk[sb].row_nodes;
+            L.n = c.lblk[sb].col_nodes;
+            L.r = L.K = c.lr.rank[sb];
+            L.fresh = L.r > 0;
+            L.cap = std::max(L.r, 1);
+            L.U = f->store.alloc((size_t)L.m * L.cap);
+            L.V = f->store.alloc((size_t)L.n * L.cap);
+            sl.push_back(SliceDesc<double, T>{c.lr.mem.p + c.lr.u_off[sb] + a, L.U, L.m, L.r, u, (int64_t)u * L.m, L.m});
+            sl.push_back(SliceDesc<double, T>{c.lr.mem.p + c.lr.v_off[sb] + b, L.V, L.n, L.r, u, (int64_t)u * L.n, L.n});
+        }
+        slice_batched<double, T>(s, sl);
     }
-    convert_batched<double, T>(s, conv);
-    f->piv_off.assign(c.dblk.size(), -1);
-    f->inv_off.assign(c.dblk.size(), -1);
+    f->piv_off.assign(dblk.size(), -1);
+    f->inv_off.assign(dblk.size(), -1);
     int64_t np = 0, ni = 0;
     for (size_t b = 0; b < T_.dense_blocks.size(); ++b) {
         const Block& B = T_.blocks[T_.dense_blocks[b]];
         if (B.t == B.s) {
             f->piv_off[b] = np;
-            np += c.dblk[b].ld;
+            np += dblk[b].ld;
             f->inv_off[b] = ni;
-            ni += 2 * (int64_t)c.dblk[b].ld * c.dblk[b].ld;
+            ni += 2 * (int64_t)dblk[b].ld * dblk[b].ld;
         }
     }
     f->piv.alloc(std::max<int64_t>(np, 1));
     f->inv.alloc(std::max<int64_t>(ni, 1));
-    f->info.alloc(std::max<size_t>(c.dblk.size(), 1));
-    CBIE_HIP(hipMemsetAsync(f->info.p, 0, sizeof(int) * std::max<size_t>(c.dblk.size(), 1), s));
+    f->info.alloc(std::max<size_t>(dblk.size(), 1));
+    CBIE_HIP(hipMemsetAsync(f->info.p, 0, sizeof(int) * std::max<size_t>(dblk.size(), 1), s));
     return f;
 }
 
@@ -2081,7 +2172,14 @@ template <typename T> static void run_factor(Ctx& c, HF<T>& f) {
         if (em || grow > 0) f.set_mem_budget(f.store.live * sizeof(cplx<T>) + grow);
     }
     try {
-        for (int root : c.tree.block_roots) f.hlu(root);
+        if (f.lay->ordering != CBIE_ORDER_ENTIRE) {
+            // the component blocks taken from the low-rank blocks, truncated
+            // as the factorization truncates its formatted sums
+            const double t0 = now_s();
+            f.flush_all();
+            c.stats.t_factor_reorder = now_s() - t0;
+        }
+        for (int root : f.T_.block_roots) f.hlu(root);
         f.flush_all();
     } catch (const Error&) {
         size_t mfree = 0, mtot = 0;
@@ -2114,7 +2212,7 @@ template <typename T> static void run_factor(Ctx& c, HF<T>& f) {
             fprintf(stderr, "\n");
         }
     }
-    std::vector<int> info(c.dblk.size());
+    std::vector<int> info(f.leafd.size());
     if (!info.empty()) f.info.download(info.data(), info.size(), c.stream);
     c.sync();
     for (size_t b = 0; b < info.size(); ++b)
@@ -2182,6 +2280,7 @@ template <typename T> static void run_factor(Ctx& c, HF<T>& f) {
 void stage_factor(Ctx& c, int prec) {
     const double t0 = now_s();
     c.hm.reset();   // release an earlier factorization before building this one
+    c.stats.t_factor_reorder = 0.0;
     auto hm = std::make_shared<HMat>();
     hm->prec = prec;
     if (prec == CBIE_PREC_C128) {
@@ -2198,10 +2297,11 @@ void stage_factor(Ctx& c, int prec) {
         using E = typename std::remove_reference<decltype(*f.dense.p)>::type;
         double el = 0.0;
         for (const auto& L : f.lr) el += (double)(L.m + L.n) * L.r;
-        const Tree& T_ = c.tree;
+        const Tree& T_ = f.T_;
         for (size_t b = 0; b < T_.dense_blocks.size(); ++b) {
             const Block& B = T_.blocks[T_.dense_blocks[b]];
-            const double e = (double)c.upn * c.dblk[b].row_nodes * c.upn * c.dblk[b].col_nodes;
+            const int ub = f.leafd[b].upn;
+            const double e = (double)ub * f.leafd[b].row_nodes * ub * f.leafd[b].col_nodes;
             el += B.t == B.s ? 2.0 * e : e;   // diagonal leaf: L^{-1} P and U^{-1}
         }
         return el * sizeof(E);
@@ -2219,9 +2319,9 @@ template <typename T> static void lu_solve_tree(Ctx& c, HF<T>& f, cplx<T>* X, in
         Thresholds(HF<T>& ff) : f(ff), k1(ff.split_k1), k2(ff.split_k2) { f.split_k1 = 768; f.split_k2 = 128; }
         ~Thresholds() { f.split_k1 = k1; f.split_k2 = k2; }
     } th(f);
-    for (int root : c.tree.block_roots) {
-        const int cl = c.tree.blocks[root].t;
-        const Cluster& C = c.tree.clusters[cl];
+    for (int root : f.T_.block_roots) {
+        const int cl = f.T_.blocks[root].t;
+        const Cluster& C = f.T_.clusters[cl];
         const auto v = f.raw(X + C.unk0(), ld, (int)C.nunk(), nrhs, cl, -1, RES_RHS, 0, C.unk0(), 0);
         f.solveL(root, v);
         f.solveU(root, v);
@@ -2252,6 +2352,44 @@ __global__ void k_add(int64_t n, const zd* __restrict__ d, zd* __restrict__ x) {
     if (e < n) x[e] = x[e] + d[e];
 }
 
+// X (the factor's unknown order, working precision) := rhs (tree order,
+// FP64), and back; the component-wise ordering permutes each column
+template <typename T>
+__global__ void k_perm_to(int64_t n, int nrhs, const int* __restrict__ perm, const zd* __restrict__ a,
+                          cplx<T>* __restrict__ b) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n * nrhs) return;
+    const int64_t i = e % n, r = e / n;
+    b[r * n + perm[i]] = cplx<T>{(T)a[e].re, (T)a[e].im};
+}
+template <typename T>
+__global__ void k_perm_from(int64_t n, int nrhs, const int* __restrict__ perm, const cplx<T>* __restrict__ b,
+                            zd* __restrict__ a) {
+    const int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (e >= n * nrhs) return;
+    const int64_t i = e % n, r = e / n;
+    const cplx<T> x = b[r * n + perm[i]];
+    a[e] = zd{(double)x.re, (double)x.im};
+}
+template <typename T> static void to_factor_order(Ctx& c, HF<T>& f, int nrhs, const zd* rhs, cplx<T>* X) {
+    const int64_t NN = c.n_unk * nrhs;
+    if (f.lay->ordering == CBIE_ORDER_ENTIRE) {
+        convert<double, T>(c.stream, NN, rhs, X);
+        return;
+    }
+    k_perm_to<T><<<ceil_div(NN, 256), 256, 0, c.stream>>>(c.n_unk, nrhs, f.lay->d_perm.p, rhs, X);
+    check_launch("k_perm_to");
+}
+template <typename T> static void from_factor_order(Ctx& c, HF<T>& f, int nrhs, const cplx<T>* X, zd* out) {
+    const int64_t NN = c.n_unk * nrhs;
+    if (f.lay->ordering == CBIE_ORDER_ENTIRE) {
+        convert<T, double>(c.stream, NN, X, out);
+        return;
+    }
+    k_perm_from<T><<<ceil_div(NN, 256), 256, 0, c.stream>>>(c.n_unk, nrhs, f.lay->d_perm.p, X, out);
+    check_launch("k_perm_from");
+}
+
 // out = LU^{-1} rhs (tree order, FP64 in and out).  The first call for a
 // factorization and a number of right-hand sides records the substitution
 // program into a replay (and runs it); later calls copy rhs into the
@@ -2265,7 +2403,7 @@ template <typename T> static void lu_solve_replay(Ctx& c, HF<T>& f, int nrhs, co
         auto R = std::make_unique<typename HF<T>::Replay>();
         R->nrhs = nrhs;
         R->X.alloc(NN);
-        convert<double, T>(s, NN, rhs, R->X.p);
+        to_factor_order(c, f, nrhs, rhs, R->X.p);
         std::swap(f.scratch, R->scratch);
         f.rec_into = R.get();
         try {
@@ -2280,10 +2418,10 @@ template <typename T> static void lu_solve_replay(Ctx& c, HF<T>& f, int nrhs, co
         f.capture_replay(*R);
         f.rp = std::move(R);
     } else {
-        convert<double, T>(s, NN, rhs, f.rp->X.p);
+        to_factor_order(c, f, nrhs, rhs, f.rp->X.p);
         f.run_replay(*f.rp);
     }
-    convert<T, double>(s, NN, f.rp->X.p, out);
+    from_factor_order(c, f, nrhs, f.rp->X.p, out);
 }
 
 void stage_solve(Ctx& c, int nrhs, const zd* b, zd* x, long ld, double tol, int maxit, int* iters) {
@@ -2304,20 +2442,23 @@ void stage_solve(Ctx& c, int nrhs, const zd* b, zd* x, long ld, double tol, int 
     k_colnorm2<<<nrhs, 256, 0, s>>>(N, nrhs, bt.p, nrm.p + nrhs);
     check_launch("k_colnorm2");
 
-    DBuf<zf> w;
-    if (c.hm->prec != CBIE_PREC_C128) w.alloc(NN);
     const bool replay = !(getenv("CBIE_SOLVE_REPLAY") && atoi(getenv("CBIE_SOLVE_REPLAY")) == 0);
+    DBuf<zf> w;
+    DBuf<zd> wd;
+    if (!replay && c.hm->prec != CBIE_PREC_C128) w.alloc(NN);
+    if (!replay && c.hm->prec == CBIE_PREC_C128) wd.alloc(NN);
     auto correction = [&](const zd* rhs, zd* out) {   // out = LU^{-1} rhs
         if (replay) {
             if (c.hm->prec == CBIE_PREC_C128) lu_solve_replay(c, *c.hm->f64, nrhs, rhs, out);
             else lu_solve_replay(c, *c.hm->f32, nrhs, rhs, out);
         } else if (c.hm->prec == CBIE_PREC_C128) {
-            if (out != rhs) CBIE_HIP(hipMemcpyAsync(out, rhs, sizeof(zd) * NN, hipMemcpyDeviceToDevice, s));
-            lu_solve_tree(c, *c.hm->f64, out, nrhs);
+            to_factor_order(c, *c.hm->f64, nrhs, rhs, wd.p);
+            lu_solve_tree(c, *c.hm->f64, wd.p, nrhs);
+            from_factor_order(c, *c.hm->f64, nrhs, wd.p, out);
         } else {
-            convert<double, float>(s, NN, rhs, w.p);
+            to_factor_order(c, *c.hm->f32, nrhs, rhs, w.p);
             lu_solve_tree(c, *c.hm->f32, w.p, nrhs);
-            convert<float, double>(s, NN, w.p, out);
+            from_factor_order(c, *c.hm->f32, nrhs, w.p, out);
         }
     };
     correction(bt.p, xt.p);

@@ -323,6 +323,35 @@ void convert_batched(hipStream_t s, const std::vector<ConvDesc<Tin, Tout>>& v) {
     CBIE_HIP(hipStreamSynchronize(s));   // the descriptor buffers are released on return
 }
 
+// work-group t copies flat elements [e0, e0 + 4096) (column-major over
+// m x n) of slice desc; consecutive threads take consecutive rows
+template <typename Tin, typename Tout>
+__global__ void k_slice_b(const SliceDesc<Tin, Tout>* __restrict__ d, const ConvTile* __restrict__ t, int nt) {
+    if ((int)blockIdx.x >= nt) return;
+    const ConvTile tl = t[blockIdx.x];
+    const SliceDesc<Tin, Tout> D = d[tl.desc];
+    const int64_t e1 = min((int64_t)D.m * D.n, tl.e0 + 4096);
+    for (int64_t e = tl.e0 + threadIdx.x; e < e1; e += 256) {
+        const int64_t i = e % D.m, j = e / D.m;
+        const cplx<Tin> x = D.a[i * D.rs + j * D.cs];
+        D.b[i + j * D.ldb] = cplx<Tout>{(Tout)x.re, (Tout)x.im};
+    }
+}
+template <typename Tin, typename Tout>
+void slice_batched(hipStream_t s, const std::vector<SliceDesc<Tin, Tout>>& v) {
+    std::vector<ConvTile> t;
+    for (size_t i = 0; i < v.size(); ++i)
+        for (int64_t e0 = 0; e0 < (int64_t)v[i].m * v[i].n; e0 += 4096) t.push_back(ConvTile{(int)i, 0, e0});
+    if (t.empty()) return;
+    DBuf<SliceDesc<Tin, Tout>> dd;
+    DBuf<ConvTile> dt;
+    dd.upload(v, s);
+    dt.upload(t, s);
+    k_slice_b<Tin, Tout><<<(unsigned)t.size(), 256, 0, s>>>(dd.p, dt.p, (int)t.size());
+    check_launch("k_slice_b");
+    CBIE_HIP(hipStreamSynchronize(s));   // the descriptor buffers are released on return
+}
+
 // the same launch over descriptors and tiles already on the device
 template <typename Tin, typename Tout>
 void convert_batched_dev(hipStream_t s, const ConvDesc<Tin, Tout>* d, const ConvTile* t, int nt) {
@@ -539,6 +568,8 @@ CBIE_LINALG_INST(double)
 CBIE_LINALG_INST(float)
 template void convert_batched<double, float>(hipStream_t, const std::vector<ConvDesc<double, float>>&);
 template void convert_batched<double, double>(hipStream_t, const std::vector<ConvDesc<double, double>>&);
+template void slice_batched<double, float>(hipStream_t, const std::vector<SliceDesc<double, float>>&);
+template void slice_batched<double, double>(hipStream_t, const std::vector<SliceDesc<double, double>>&);
 template void convert_batched_dev<float, double>(hipStream_t, const ConvDesc<float, double>*, const ConvTile*, int);
 template void convert_batched_dev<double, float>(hipStream_t, const ConvDesc<double, float>*, const ConvTile*, int);
 template void convert<double, float>(hipStream_t, int64_t, const zd*, zf*);

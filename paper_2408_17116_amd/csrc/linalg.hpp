@@ -53,6 +53,16 @@ struct ConvTile {
 // allocation, no synchronization)
 template <typename Tin, typename Tout>
 void convert_batched_dev(hipStream_t s, const ConvDesc<Tin, Tout>* d, const ConvTile* t, int nt);
+// b[i + j ldb] = (Tout) a[i rs + j cs] for i < m, j < n, every descriptor,
+// one launch (a strided sub-matrix, e.g. every upn-th row of a block)
+template <typename Tin, typename Tout> struct SliceDesc {
+    const cplx<Tin>* a;
+    cplx<Tout>* b;
+    int m, n;
+    int64_t rs, cs, ldb;
+};
+template <typename Tin, typename Tout>
+void slice_batched(hipStream_t s, const std::vector<SliceDesc<Tin, Tout>>& v);
 
 // ACA of an implicit product M = Uc Vc^T (m x n, inner K <= 2048): writes
 // U (m x cap) and V (n x cap), cap <= 1024, with M ~ U V^T to relative

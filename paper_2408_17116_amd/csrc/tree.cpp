@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <functional>
+#include <map>
 #include <numeric>
 
 namespace cbie {
@@ -143,6 +144,107 @@ Tree build_tree(const TreeInput& in, int leaf_unknowns, double eta) {
     };
     for (int o = 0; o < in.n_objs; ++o) T.block_roots.push_back(brec(T.roots[o], T.roots[o]));
     return T;
+}
+
+ComponentTree component_tree(const Tree& T, int upn) {
+    ComponentTree out;
+    Tree& C = out.tree;
+    int depth0 = 0;   // levels of the component split above the node trees
+    for (int w = upn; w > 1; w /= 2) ++depth0;
+    for (size_t o = 0; o < T.roots.size(); ++o) {
+        const Cluster& R = T.clusters[T.roots[o]];
+        const int64_t base = upn * (int64_t)R.node0;
+        // a copy of the object's cluster tree for each component
+        std::vector<std::vector<int>> cid(upn, std::vector<int>(T.clusters.size(), -1));
+        std::function<int(int, int, int)> copy = [&](int id, int a, int depth) -> int {
+            Cluster k = T.clusters[id];
+            k.upn = 1;
+            k.level = depth;
+            k.u0 = base + (int64_t)a * R.nodes + (k.node0 - R.node0);
+            k.nu = k.nodes;
+            const int nid = (int)C.clusters.size();
+            C.clusters.push_back(k);
+            cid[a][id] = nid;
+            if (!T.clusters[id].leaf()) {
+                const int c0 = copy(T.clusters[id].child[0], a, depth + 1);
+                const int c1 = copy(T.clusters[id].child[1], a, depth + 1);
+                C.clusters[nid].child[0] = c0;
+                C.clusters[nid].child[1] = c1;
+            }
+            return nid;
+        };
+        for (int a = 0; a < upn; ++a) copy(T.roots[o], a, depth0);
+        // cluster of components [lo, hi): a single component is its copy's
+        // root, a range is split in halves
+        std::map<std::pair<int, int>, int> gid;
+        std::function<int(int, int, int)> group = [&](int lo, int hi, int depth) -> int {
+            if (hi - lo == 1) return cid[lo][T.roots[o]];
+            Cluster k = R;
+            k.upn = hi - lo;
+            k.level = depth;
+            k.u0 = base + (int64_t)lo * R.nodes;
+            k.nu = (int64_t)(hi - lo) * R.nodes;
+            const int nid = (int)C.clusters.size();
+            C.clusters.push_back(k);
+            const int mid = (lo + hi) / 2;
+            const int c0 = group(lo, mid, depth + 1);
+            const int c1 = group(mid, hi, depth + 1);
+            C.clusters[nid].child[0] = c0;
+            C.clusters[nid].child[1] = c1;
+            gid[{lo, hi}] = nid;
+            return nid;
+        };
+        C.roots.push_back(group(0, upn, 0));
+        auto cluster_of = [&](int lo, int hi) { return hi - lo == 1 ? cid[lo][T.roots[o]] : gid.at({lo, hi}); };
+        // the object's node block tree for row component a, column component b
+        std::function<int(int, int, int)> bcopy = [&](int bid, int a, int b) -> int {
+            const Block& src = T.blocks[bid];
+            Block k;
+            k.t = cid[a][src.t];
+            k.s = cid[b][src.s];
+            k.type = src.type;
+            const int nid = (int)C.blocks.size();
+            C.blocks.push_back(k);
+            if (src.type == BLK_LR) {
+                C.blocks[nid].leaf_index = (int)C.lr_blocks.size();
+                C.lr_blocks.push_back(nid);
+                out.lr_src.push_back({src.leaf_index, a, b});
+            } else if (src.type == BLK_DENSE) {
+                C.blocks[nid].leaf_index = (int)C.dense_blocks.size();
+                C.dense_blocks.push_back(nid);
+                out.dense_src.push_back({src.leaf_index, a, b});
+            } else {
+                for (int q = 0; q < 4; ++q) {
+                    const int ch = bcopy(src.child[q], a, b);
+                    C.blocks[nid].child[q] = ch;
+                }
+            }
+            return nid;
+        };
+        // row components [rl, rh) x column components [cl, ch), halved together
+        std::function<int(int, int, int, int)> brec = [&](int rl, int rh, int cl, int ch) -> int {
+            if (rh - rl == 1) return bcopy(T.block_roots[o], rl, cl);
+            Block k;
+            k.t = cluster_of(rl, rh);
+            k.s = cluster_of(cl, ch);
+            k.type = BLK_HIER;
+            const int nid = (int)C.blocks.size();
+            C.blocks.push_back(k);
+            const int rm = (rl + rh) / 2, cm = (cl + ch) / 2;
+            const int q0 = brec(rl, rm, cl, cm), q1 = brec(rl, rm, cm, ch);
+            const int q2 = brec(rm, rh, cl, cm), q3 = brec(rm, rh, cm, ch);
+            Block& B = C.blocks[nid];
+            B.child[0] = q0;
+            B.child[1] = q1;
+            B.child[2] = q2;
+            B.child[3] = q3;
+            return nid;
+        };
+        C.block_roots.push_back(brec(0, upn, 0, upn));
+    }
+    for (const auto& k : C.clusters)
+        if (k.leaf()) ++C.n_leaves;
+    return out;
 }
 
 }  // namespace cbie

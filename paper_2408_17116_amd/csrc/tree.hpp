@@ -14,9 +14,12 @@ struct Cluster {
     int child[2] = {-1, -1};
     int upn = 2;                 // unknowns per node
     double bmin[3], bmax[3];     // bounding box of the cluster's nodes
+    // unknown range set explicitly (component-wise ordering); -1: the
+    // node range times all components of a node, interleaved
+    int64_t u0 = -1, nu = -1;
     bool leaf() const { return child[0] < 0; }
-    int64_t unk0() const { return upn * (int64_t)node0; }
-    int64_t nunk() const { return upn * (int64_t)nodes; }
+    int64_t unk0() const { return u0 >= 0 ? u0 : upn * (int64_t)node0; }
+    int64_t nunk() const { return nu >= 0 ? nu : upn * (int64_t)nodes; }
 };
 
 enum BlockType { BLK_DENSE = 0, BLK_LR = 1, BLK_HIER = 2 };
@@ -60,5 +63,22 @@ struct Tree {
 // and no near pair connects t to s; otherwise a dense leaf when t or s is a
 // leaf cluster, otherwise split into the four child pairs.
 Tree build_tree(const TreeInput& in, int leaf_unknowns, double eta);
+
+// Component-wise block structure (Sec. III-A, eqs. 22-23) derived from a
+// node tree T with upn components per node.  Per object the unknowns are
+// ordered component by component: component a of tree node i of an object
+// whose nodes are [n0, n0 + n) in tree order sits at upn n0 + a n + (i - n0).
+// Each component has its own copy of the object's cluster tree (upn = 1);
+// the object's root splits the components in halves down to single ones
+// (MFIE: u | v; N-Mueller: (Ju Jv) | (Mu Mv), then each pair), and the root
+// block splits the same way into the upn^2 component interaction blocks,
+// each the node block tree of the object with the same admissibility.
+// dense_src / lr_src give, per leaf of the result, the leaf of T it is
+// taken from and its row and column components.
+struct ComponentTree {
+    Tree tree;
+    std::vector<std::array<int, 3>> dense_src, lr_src;
+};
+ComponentTree component_tree(const Tree& T, int upn);
 
 }  // namespace cbie

@@ -19,6 +19,9 @@ assembly at full size and the solution against the matrix it solves.
     python tests/golden/make_dense_solutions.py resonance       # 38400 unknowns, eps_d 10.5074 (Sec. IV-B)
     python tests/golden/make_dense_solutions.py stretched       # 12288 unknowns: the 196,608-unknown ellipsoid's
                                                                 # shape and patch size, scaled down 4x
+    python tests/golden/make_dense_solutions.py component_small # 768-unknown MFIE and 1536-unknown N-Mueller
+                                                                # spheres: dense solve and the component-wise
+                                                                # block solve (Sec. III-A, eqs. 22-28)
 """
 from __future__ import annotations
 
@@ -33,7 +36,7 @@ import scipy.linalg as sla
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 
-from oracle import geometry as G, mfie, muller  # noqa: E402
+from oracle import dense, geometry as G, mfie, muller  # noqa: E402
 from synth import workloads as W  # noqa: E402
 
 _ND = None
@@ -149,6 +152,25 @@ def main():
         kh, pol = W.plane_waves(1, seed=0)
         x, rec = dense_solve(spec, kh, pol)
         np.savez(os.path.join(HERE, "stretched_ellipsoid_12288_dense.npz"), x=x, khat=kh, pol=pol, **rec)
+    elif which == "component_small":
+        out = {}
+        spec = W.tiny_sphere(s=2, q=4, k0=3.0)
+        nd = G.build_nodes(spec)
+        A = mfie.dense_matrix(nd, spec.k0, workers=8)
+        kh, pol = W.plane_waves(3, seed=11)
+        b = mfie.rhs_planewave(nd, spec.k0, kh, pol)
+        out.update(mfie_khat=kh, mfie_pol=pol, mfie_x=dense.solve(A, b), mfie_xc=dense.component_block_solve(A, b, 2))
+        spec = W.ObjectSpec(axes=(1.0, 1.0, 1.0), center=(0.0, 0.0, 0.0), s=2, q=4, k0=2.0,
+                            form=W.FORM_NMULLER, eps_r=4.0, mu_r=1.0)
+        nd = G.build_nodes(spec)
+        A = muller.dense_matrix(nd, spec.k0, spec.eps_r, workers=8)
+        kh, pol = W.axial_wave()
+        b = muller.rhs_planewave(nd, spec.k0, kh, pol)
+        out.update(nm_khat=kh, nm_pol=pol, nm_x=dense.solve(A, b), nm_xc=dense.component_block_solve(A, b, 4))
+        for k in ("mfie", "nm"):
+            d = np.linalg.norm(out[k + "_x"] - out[k + "_xc"]) / np.linalg.norm(out[k + "_x"])
+            log(f"{k}: component block solve vs dense solve {d:.2e}")
+        np.savez(os.path.join(HERE, "component_small_dense.npz"), **out)
     else:
         raise SystemExit(f"unknown workload {which}")
 

@@ -43,6 +43,8 @@ def shim(tmp_path_factory):
     lib.tree_leaves.argtypes = [C.c_int, C.c_int, C.c_int, ip, ip, dp, dp, ip, ip, C.c_int, C.c_double, ip, ip,
                                 C.c_int]
     lib.tree_leaves.restype = C.c_int
+    lib.component_leaves.argtypes = lib.tree_leaves.argtypes[:-3] + [ip, C.c_int]
+    lib.component_leaves.restype = C.c_int
     return lib
 
 
@@ -123,3 +125,59 @@ def test_oracle_tree_tiles_the_matrix_with_admissible_low_rank_blocks(name):
     same_obj = np.equal.outer([patch_obj[p] for p in order], [patch_obj[p] for p in order])
     assert (cover[same_obj] == 1).all() and (cover[~same_obj] == 0).all()
     assert n_lr > 0
+
+
+@pytest.mark.parametrize("name", ["sphere_s3q4_leaf64", "sphere_4_unknowns_per_node", "ellipsoid_batch3_leaf256"])
+def test_component_wise_structure_tiles_the_permuted_matrix(shim, name):
+    """The component-wise ordering (Sec. III-A, eqs. 22-23): every leaf of
+    the node tree gives one leaf per pair of components, holding exactly the
+    rows of its row component and the columns of its column component in the
+    component-by-component order, so the leaves tile each object's permuted
+    matrix once; the pivots are the leaves of one component against itself
+    on the node tree's diagonal leaves."""
+    _nds, inp, upn, leaf, eta = _case(name)
+    patch_obj, centroid, pbox, patch_nodes, near = inp
+    order, blocks = _library_tree(shim, inp, upn, leaf, eta)
+    P = len(patch_obj)
+    lists = [sorted(b for (a, b) in near if a == p) for p in range(P)]
+    ptr = np.zeros(P + 1, np.int32)
+    ptr[1:] = np.cumsum([len(v) for v in lists])
+    idx = np.array([b for v in lists for b in v], np.int32)
+    a_ = lambda x, t: np.ascontiguousarray(x, dtype=t)
+    po, cn, pb, pn = a_(patch_obj, np.int32), a_(centroid, np.float64), a_(pbox, np.float64), a_(patch_nodes, np.int32)
+    cap = upn * upn * len(blocks) + 1
+    out = np.zeros(13 * cap, np.int32)
+    ip = lambda x: x.ctypes.data_as(C.POINTER(C.c_int))
+    dp = lambda x: x.ctypes.data_as(C.POINTER(C.c_double))
+    n = shim.component_leaves(P, max(patch_obj) + 1, upn, ip(po), ip(pn), dp(cn), dp(pb), ip(ptr), ip(idx), leaf, eta,
+                              ip(out), cap)
+    assert n == upn * upn * len(blocks)
+    L = out[:13 * n].reshape(n, 13)
+    # tree-order node ranges of the objects
+    node0 = np.concatenate([[0], np.cumsum([patch_nodes[p] for p in order])])
+    objs = sorted(set(patch_obj))
+    orng = {}
+    for pos, p in enumerate(order):
+        o = patch_obj[p]
+        lo, hi = orng.get(o, (node0[pos], node0[pos + 1]))
+        orng[o] = (min(lo, node0[pos]), max(hi, node0[pos + 1]))
+    N = upn * node0[-1]
+    cover = np.zeros((N, N), np.int8)
+    n_diag = 0
+    for (kind, r0, m, c0, nc, skind, tn0, tn, sn0, sn, a, b, diag) in L:
+        assert kind == skind
+        o = next(o for o in objs if orng[o][0] <= tn0 < orng[o][1])
+        on0, on1 = orng[o]
+        assert on0 <= sn0 and sn0 + sn <= on1                    # within one object
+        base, no = upn * on0, on1 - on0
+        assert (r0, m) == (base + a * no + tn0 - on0, tn)
+        assert (c0, nc) == (base + b * no + sn0 - on0, sn)
+        assert diag == (a == b and tn0 == sn0 and tn == sn)
+        n_diag += int(diag)
+        cover[r0:r0 + m, c0:c0 + nc] += 1
+    for o in objs:
+        lo, hi = upn * orng[o][0], upn * orng[o][1]
+        assert (cover[lo:hi, lo:hi] == 1).all()
+    assert cover.sum() == sum((upn * (orng[o][1] - orng[o][0])) ** 2 for o in objs)
+    n_node_diag = sum(1 for (k, t0, t1, s0, s1) in blocks if k == "dense" and (t0, t1) == (s0, s1))
+    assert n_diag == upn * n_node_diag

@@ -2,7 +2,8 @@
 
 Fejer-1 rule, Chebyshev maps (eqs. 12-13), geometry and bases (eqs. 11, 14,
 17, 18), the cancellation-free patch difference, the Duffy rule against the
-closed-form integral of 1/R over rectangles, dense LU against LAPACK.
+closed-form integral of 1/R over rectangles, dense LU against LAPACK, the
+component-wise block LU (Sec. III-A, eqs. 22-28) against LAPACK.
 """
 import numpy as np
 import pytest
@@ -133,3 +134,47 @@ def test_hand_lu_matches_lapack():
     x2 = dense.solve(A, b)
     assert np.linalg.norm(x1 - x2) / np.linalg.norm(x2) < 1e-12
     assert dense.backward_error(A, x2, b) < 1e-15
+
+
+def test_component_order_gathers_the_component_blocks():
+    # position a n + i holds unknown (node i, component a): the blocks of the
+    # reordered matrix are the strided component interactions of eq. 22
+    rng = np.random.default_rng(5)
+    for upn, n in ((2, 7), (4, 5)):
+        A = rng.standard_normal((upn * n, upn * n))
+        p = dense.component_order(n, upn)
+        assert sorted(p) == list(range(upn * n))
+        K = A[np.ix_(p, p)]
+        for a in range(upn):
+            for b in range(upn):
+                assert np.array_equal(K[a * n:(a + 1) * n, b * n:(b + 1) * n], A[a::upn, b::upn])
+
+
+@pytest.mark.parametrize("upn,n", [(2, 37), (4, 19)])
+def test_component_block_solve_matches_lapack(upn, n):
+    # eqs. 23-28 with dense blocks reproduce the plain solve; the component
+    # diagonal blocks are made dominant so that no pivoting across them is
+    # needed (the H-LU pivots inside diagonal leaves only)
+    rng = np.random.default_rng(upn)
+    N = upn * n
+    A = rng.standard_normal((N, N)) + 1j * rng.standard_normal((N, N)) + 4.0 * np.sqrt(N) * np.eye(N)
+    B = rng.standard_normal((N, 3)) + 1j * rng.standard_normal((N, 3))
+    x = dense.component_block_solve(A, B, upn)
+    xr = dense.solve(A, B)
+    assert np.linalg.norm(x - xr) / np.linalg.norm(xr) < 1e-12
+
+
+def test_component_block_solve_on_the_cbie_matrices():
+    # the MFIE (2 components) and N-Mueller (4) matrices of a small sphere:
+    # the component-wise solve equals the interleaved LAPACK solve
+    from oracle import muller
+    spec = W.tiny_sphere(s=1, q=4, k0=2.0)
+    nd = G.build_nodes(spec)
+    A = mfie.dense_matrix(nd, spec.k0)
+    b = mfie.rhs_planewave(nd, spec.k0, *W.axial_wave())
+    xr = dense.solve(A, b)
+    assert np.linalg.norm(dense.component_block_solve(A, b, 2) - xr) / np.linalg.norm(xr) < 1e-11
+    A4 = muller.dense_matrix(nd, spec.k0, 4.0)
+    b4 = muller.rhs_planewave(nd, spec.k0, *W.axial_wave())
+    xr4 = dense.solve(A4, b4)
+    assert np.linalg.norm(dense.component_block_solve(A4, b4, 4) - xr4) / np.linalg.norm(xr4) < 1e-11
