@@ -227,6 +227,21 @@ cbie_status cbie_matvec_noalloc(cbie_ctx* ctx, int nrhs, const void* x_dev, void
  * (eq. 19, exterior vacuum) add the electric rows -a_v . E, a_u . E after
  * them.  khat, pol: host arrays of 3*nw doubles.  b_dev: complex128 device array n_unknowns x nw, ld.
  * Errors: ESTATE (before build_tree), EINVAL, EHIP. */
+/* Right-hand sides for n_dipoles point electric dipoles in free space (the
+ * x-polarized dipole feeding the spiral antenna of Sec. IV-A): each
+ * dipole's fields replace the plane wave's in the rows of eq. (22) (and the
+ * electric rows of eq. 19 for N-Mueller objects).  pos, moment: host arrays
+ * of 3*n_dipoles doubles, position r0 and current moment m (I l) of each
+ * dipole; in the normalized units eps = mu = 1, omega = k0, time factor
+ * e^{j omega t}, with d = r - r0, R = |d|, e = d / R, G = e^{-j k0 R} / (4 pi R):
+ * H = (1 + j k0 R) (G / R) m x e and
+ * E = G [(-1/R + j (1/(k0 R^2) - k0)) (m - (m.e) e) + (2/R - 2j/(k0 R^2)) (m.e) e].
+ * b_dev: complex128 device array n_unknowns x n_dipoles, leading dimension
+ * ld, original order.  Errors: ESTATE (before build_tree), EINVAL (also
+ * when a dipole sits exactly on a node), EHIP. */
+cbie_status cbie_rhs_dipole(cbie_ctx* ctx, int n_dipoles, const double* pos, const double* moment, void* b_dev,
+                            long ld);
+
 cbie_status cbie_rhs_planewave(cbie_ctx* ctx, int nw, const double* khat, const double* pol,
                                void* b_dev, long ld);
 

@@ -27,7 +27,7 @@ EXPORTED = ["cbie_create", "cbie_build_tree", "cbie_fill", "cbie_compress", "cbi
             "cbie_set_profiling", "cbie_get_near_pairs", "cbie_export_dense", "cbie_last_error",
             "cbie_destroy", "cbie_get_block_features", "cbie_set_rank_model", "cbie_mlp_forward",
             "cbie_mlp_grad", "cbie_mlp_train", "cbie_matvec_noalloc", "cbie_solve_gmres",
-            "cbie_set_factor_tolerance", "cbie_set_factor_ordering"]
+            "cbie_set_factor_tolerance", "cbie_set_factor_ordering", "cbie_rhs_dipole"]
 
 MLP_NFEAT, MLP_NPARAMS = 8, 4801
 
@@ -92,6 +92,7 @@ def load(path: str = LIB_PATH):
         "cbie_set_factor_tolerance": ([vp, dbl], i32),
         "cbie_set_factor_ordering": ([vp, i32], i32),
         "cbie_rhs_planewave": ([vp, i32, vp, vp, vp, C.c_long], i32),
+        "cbie_rhs_dipole": ([vp, i32, vp, vp, vp, C.c_long], i32),
         "cbie_farfield": ([vp, i32, vp, C.c_long, i32, vp, vp], i32),
         "cbie_get_stats": ([vp, vp, C.c_size_t], i32),
         "cbie_set_profiling": ([vp, i32], i32),
@@ -244,6 +245,19 @@ class Solver:
         b = self.torch.empty((nw, self.n), dtype=self.torch.complex128, device="cuda")
         self._check(self.lib.cbie_rhs_planewave(self.h, nw, khat.ctypes.data_as(C.c_void_p),
                                                 pol.ctypes.data_as(C.c_void_p), _ptr(b), self.n))
+        return b.t()
+
+    def rhs_dipole(self, pos, moment):
+        """Right-hand sides of point electric dipoles (positions, current
+        moments: (n, 3) each), one column per dipole."""
+        pos = np.ascontiguousarray(np.atleast_2d(pos), dtype=np.float64)
+        moment = np.ascontiguousarray(np.atleast_2d(moment), dtype=np.float64)
+        if pos.shape != moment.shape or pos.shape[1] != 3:
+            raise ValueError("pos and moment must both be (n, 3)")
+        nd = pos.shape[0]
+        b = self.torch.empty((nd, self.n), dtype=self.torch.complex128, device="cuda")
+        self._check(self.lib.cbie_rhs_dipole(self.h, nd, pos.ctypes.data_as(C.c_void_p),
+                                             moment.ctypes.data_as(C.c_void_p), _ptr(b), self.n))
         return b.t()
 
     def farfield(self, x, rhat):

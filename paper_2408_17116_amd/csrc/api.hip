@@ -246,6 +246,15 @@ cbie_status cbie_rhs_planewave(cbie_ctx* ctx, int nw, const double* khat, const 
     });
 }
 
+cbie_status cbie_rhs_dipole(cbie_ctx* ctx, int n_dipoles, const double* pos, const double* moment, void* b_dev,
+                            long ld) {
+    return guarded(ctx, [&](Ctx& c) {
+        CBIE_REQUIRE(c.state >= ST_TREE, CBIE_ESTATE, "rhs before build_tree");
+        CBIE_REQUIRE(n_dipoles > 0 && pos && moment && b_dev && ld >= c.n_unk, CBIE_EINVAL, "dipole rhs arguments");
+        stage_rhs_dipole(c, n_dipoles, pos, moment, (zd*)b_dev, ld);
+    });
+}
+
 cbie_status cbie_farfield(cbie_ctx* ctx, int nrhs, const void* x_dev, long ld, int ndir, const double* rhat,
                           void* E_out) {
     return guarded(ctx, [&](Ctx& c) {

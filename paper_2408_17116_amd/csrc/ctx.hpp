@@ -130,6 +130,7 @@ void stage_solve_gmres(Ctx& c, int nrhs, const zd* b, zd* x, long ld, double tol
 void stage_matvec(Ctx& c, int nrhs, const zd* x, zd* y, long ld);
 void stage_export_dense(Ctx& c, zd* A, long ld);
 void stage_rhs(Ctx& c, int nw, const double* khat, const double* pol, zd* b, long ld);
+void stage_rhs_dipole(Ctx& c, int ndp, const double* pos, const double* mom, zd* b, long ld);
 void stage_farfield(Ctx& c, int nrhs, const zd* x, long ld, int ndir, const double* rhat, zd* E);
 // plain-rule N-Mueller entries of blocks (offsets / leading dimensions into dst)
 void fill_blocks_nm(Ctx& c, const std::vector<DenseBlockDev>& blocks, const DenseBlockDev* d_blocks, zd* dst);

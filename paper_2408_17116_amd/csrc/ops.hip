@@ -292,6 +292,70 @@ void stage_rhs(Ctx& c, int nw, const double* khat, const double* pol, zd* b, lon
     c.sync();
 }
 
+// Right-hand sides for point electric dipoles in free space (the feed of
+// the spiral antenna, Sec. IV-A): the dipole's E and H replace the plane
+// wave's in the rows of eq. 22 (and eq. 19).  Moment m (I l) at r0; with
+// d = r - r0, R = |d|, e = d / R and G = e^{-jkR} / (4 pi R):
+//   H = (1 + j k R) (G / R) (m x e),
+//   E = G [(-1/R + j (1/(k R^2) - k)) (m - (m.e) e) + (2/R - 2j/(k R^2)) (m.e) e].
+// One thread per (node, dipole); dp holds (r0, m) per dipole.
+__global__ void k_rhs_dipole(NodeArrays nd, const int* __restrict__ node_patch, const PatchDev* __restrict__ patches,
+                             const ObjDev* __restrict__ objs, int n_nodes, int upn, int ndp,
+                             const double* __restrict__ dp, zd* __restrict__ b, int64_t ld) {
+    const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+    if (t >= (int64_t)n_nodes * ndp) return;
+    const int w = (int)(t / n_nodes), i = (int)(t % n_nodes);
+    const double k = objs[patches[node_patch[i]].obj].k0;
+    const V3 r0 = v3(dp[6 * w], dp[6 * w + 1], dp[6 * w + 2]);
+    const V3 m = v3(dp[6 * w + 3], dp[6 * w + 4], dp[6 * w + 5]);
+    const V3 d = v3(nd.rx[i], nd.ry[i], nd.rz[i]) - r0;
+    const double R = sqrt(dot(d, d)), iR = 1.0 / R;
+    const V3 e = iR * d;
+    double s, cs;
+    sincos(k * R, &s, &cs);
+    const double gr = cs * iR / (4.0 * M_PI), gi = -s * iR / (4.0 * M_PI);   // G
+    const double hr = (gr - k * R * gi) * iR, hi = (gi + k * R * gr) * iR;    // (1 + jkR) G / R
+    const double a = 1.0 / (k * R * R) - k;
+    const double tr = -gr * iR - gi * a, ti = -gi * iR + gr * a;              // G (-1/R + j a)
+    const double c2 = 2.0 / (k * R * R);
+    const double rr = 2.0 * gr * iR + gi * c2, ri = 2.0 * gi * iR - gr * c2;  // G (2/R - j c2)
+    const V3 au = v3(nd.aux[i], nd.auy[i], nd.auz[i]);
+    const V3 av = v3(nd.avx[i], nd.avy[i], nd.avz[i]);
+    const V3 mh = cross(m, e);
+    const double me = dot(m, e);
+    const V3 mt = m - me * e;
+    zd* bi = b + (int64_t)w * ld + (int64_t)upn * i;
+    const double hu = -dot(av, mh), hv = dot(au, mh);
+    bi[0] = zd{hr * hu, hi * hu};
+    bi[1] = zd{hr * hv, hi * hv};
+    if (upn == 4) {
+        const double tu = -dot(av, mt), tv = dot(au, mt);
+        const double ru = -me * dot(av, e), rv = me * dot(au, e);
+        bi[2] = zd{tr * tu + rr * ru, ti * tu + ri * ru};
+        bi[3] = zd{tr * tv + rr * rv, ti * tv + ri * rv};
+    }
+}
+
+void stage_rhs_dipole(Ctx& c, int ndp, const double* pos, const double* mom, zd* b, long ld) {
+    const int n = c.n_nodes;
+    std::vector<double> dp(6 * (size_t)ndp);
+    for (int w = 0; w < ndp; ++w) {
+        for (int d = 0; d < 3; ++d) { dp[6 * w + d] = pos[3 * w + d]; dp[6 * w + 3 + d] = mom[3 * w + d]; }
+        for (int i = 0; i < n; ++i) {
+            const double x = c.h_r[i] - pos[3 * w], y = c.h_r[(size_t)n + i] - pos[3 * w + 1],
+                         z = c.h_r[2 * (size_t)n + i] - pos[3 * w + 2];
+            CBIE_REQUIRE(x * x + y * y + z * z > 0.0, CBIE_EINVAL,
+                         "dipole " + std::to_string(w) + " sits on node " + std::to_string(i));
+        }
+    }
+    DBuf<double> d_dp;
+    d_dp.upload(dp, c.stream);
+    k_rhs_dipole<<<ceil_div((int64_t)n * ndp, 256), 256, 0, c.stream>>>(c.nd, c.d_node_patch.p, c.d_patches.p,
+                                                                      c.d_objs.p, n, c.upn, ndp, d_dp.p, b, ld);
+    check_launch("k_rhs_dipole");
+    c.sync();
+}
+
 // ---------------------------------------------------------------- far field
 // N(rhat) = sum_nodes w (F_J^u a_u + F_J^v a_v) e^{j k rhat.r}, L likewise
 // from M (N-Mueller only);  E = -j k (N_perp - rhat x L) / (4 pi).
