@@ -13,6 +13,12 @@ n = a_u x a_v / |a_u x a_v|.  Eq. (18) is circular as printed; it is read
 with a_n = n and V = sqrt(G) = |a_u x a_v|, which gives the test vectors
 t_u = sqrt(G) a^u = a_v x n and t_v = sqrt(G) a^v = n x a_u satisfying the
 duality of eq. (17): t_a . a_b = sqrt(G) delta_ab.
+
+Chebyshev-interpolated patches (generic surfaces, e.g. from CAD input):
+patch record (6, p, 0, 0) is patch p of a coefficient table C of shape
+(n_patches, 3, deg + 1, deg + 1), passed where an ellipsoid passes its
+semi-axes, with r(u, v) = sum_{n,m} C[p, :, n, m] T_n(u) T_m(v),
+a_u = sum C T_n'(u) T_m(v), a_v = sum C T_n(u) T_m'(v) (T_n' = n U_{n-1}).
 """
 from __future__ import annotations
 
@@ -32,12 +38,54 @@ FACE_FRAMES = np.array([
 ], dtype=float)
 
 
+CHEB_FACE = 6
+
+
+def _cheb_tables(x, deg):
+    """T_n(x) and T_n'(x), n = 0..deg, stacked on a last axis."""
+    x = np.asarray(x, dtype=float)
+    T = [np.ones_like(x), x]
+    U = [np.ones_like(x), 2 * x]          # Chebyshev polynomials of the second kind
+    for n in range(2, deg + 1):
+        T.append(2 * x * T[-1] - T[-2])
+        U.append(2 * x * U[-1] - U[-2])
+    dT = [np.zeros_like(x)] + [n * U[n - 1] for n in range(1, deg + 1)]
+    return np.stack(T[:deg + 1], axis=-1), np.stack(dT, axis=-1)
+
+
+def _cheb_patch_map(table, idx, u, v):
+    C = np.asarray(table)[np.asarray(idx)]               # (..., 3, d+1, d+1)
+    deg = C.shape[-1] - 1
+    Tu, dTu = _cheb_tables(u, deg)
+    Tv, dTv = _cheb_tables(v, deg)
+    r = np.einsum("...cnm,...n,...m->...c", C, Tu, Tv)
+    au = np.einsum("...cnm,...n,...m->...c", C, dTu, Tv)
+    av = np.einsum("...cnm,...n,...m->...c", C, Tu, dTv)
+    return r, au, av
+
+
+def _cheb_diffs(a, b, deg):
+    """T_n(a) - T_n(b), n = 0..deg, without cancellation: with D_n the
+    difference, D_0 = 0, D_1 = a - b and
+    D_{n+1} = 2 a D_n + 2 (a - b) T_n(b) - D_{n-1}."""
+    a = np.asarray(a, dtype=float)
+    b = np.asarray(b, dtype=float)
+    d = a - b
+    Tb, _ = _cheb_tables(b, deg)
+    D = [np.zeros_like(d), d]
+    for n in range(1, deg):
+        D.append(2 * a * D[n] + 2 * d * Tb[..., n] - D[n - 1])
+    return np.stack(D[:deg + 1], axis=-1), Tb
+
+
 def patch_map(patch, axes, center, u, v):
     """Position and covariant basis at parameter arrays u, v.
 
     `patch` is (f, i, j, s); each entry may be a scalar or an integer array
     broadcasting against u and v.  Returns r, a_u, a_v of shape (..., 3)."""
     f, i, j, s = (np.asarray(t) for t in patch)
+    if np.all(f == CHEB_FACE):
+        return _cheb_patch_map(axes, i, u, v)
     frame = FACE_FRAMES[f]                    # (..., 3, 3)
     e_n, e_1, e_2 = frame[..., 0, :], frame[..., 1, :], frame[..., 2, :]
     u = np.asarray(u, dtype=float)
@@ -65,7 +113,7 @@ class Nodes:
     q: int
     n_patches: int
     patches: list
-    axes: tuple
+    axes: tuple          # semi-axes, or the Chebyshev coefficient table
     center: tuple
     u: np.ndarray        # [n] parameter of the node
     v: np.ndarray
@@ -84,6 +132,13 @@ class Nodes:
         return self.r.shape[0]
 
 
+def shape_of(spec):
+    """What patch_map takes as `axes`: the semi-axes, or the coefficient
+    table of Chebyshev-interpolated patches."""
+    coeffs = getattr(spec, "coeffs", None)
+    return tuple(spec.axes) if coeffs is None else np.asarray(coeffs, dtype=float)
+
+
 def build_nodes(spec) -> Nodes:
     q = spec.q
     x, wq = cheb.fejer1(q)
@@ -92,7 +147,7 @@ def build_nodes(spec) -> Nodes:
     W = np.outer(wq, wq)                      # W[k, l] = w_k w_l
     rs, aus, avs, pid, uu, vv, ww = [], [], [], [], [], [], []
     for p, pt in enumerate(patches):
-        r, au, av = patch_map(pt, spec.axes, spec.center, U, V)
+        r, au, av = patch_map(pt, shape_of(spec), spec.center, U, V)
         rs.append(r.reshape(-1, 3))
         aus.append(au.reshape(-1, 3))
         avs.append(av.reshape(-1, 3))
@@ -107,7 +162,7 @@ def build_nodes(spec) -> Nodes:
     Jac = np.linalg.norm(cr, axis=1)
     n = cr / Jac[:, None]
     return Nodes(q=q, n_patches=len(patches), patches=patches,
-                 axes=tuple(spec.axes), center=tuple(spec.center),
+                 axes=shape_of(spec), center=tuple(spec.center),
                  u=np.concatenate(uu), v=np.concatenate(vv),
                  patch=np.concatenate(pid), r=r, au=au, av=av, n=n, J=Jac,
                  tu=np.cross(av, n), tv=np.cross(n, au), w=np.concatenate(ww))
@@ -157,8 +212,23 @@ def patch_diff(patch, axes, center, u0, v0, du, dv):
     of the tangents uses tan a - tan b = sin(a - b) / (cos a cos b), the
     difference of the normalisations uses |c|^2 - |c0|^2 = (c - c0).(c + c0).
     Needed where the self-patch kernel is evaluated very close to its
-    singular point.  Shapes broadcast; returns (..., 3)."""
+    singular point.  Shapes broadcast; returns (..., 3).  For a
+    Chebyshev-interpolated patch, T_n(u0) T_m(v0) - T_n(u1) T_m(v1) =
+    (T_n(u0) - T_n(u1)) T_m(v0) + T_n(u1) (T_m(v0) - T_m(v1)), each
+    difference from its own recurrence."""
     f, i, j, s = (np.asarray(t) for t in patch)
+    if np.all(f == CHEB_FACE):
+        C = np.asarray(axes)[i]
+        deg = C.shape[-1] - 1
+        du = np.asarray(du, dtype=float)
+        dv = np.asarray(dv, dtype=float)
+        u0 = np.asarray(u0, dtype=float) + 0.0 * du
+        v0 = np.asarray(v0, dtype=float) + 0.0 * dv
+        Du, Tu1 = _cheb_diffs(u0, u0 + du, deg)
+        Dv, _ = _cheb_diffs(v0, v0 + dv, deg)
+        Tv0, _ = _cheb_tables(v0, deg)
+        return (np.einsum("...cnm,...n,...m->...c", C, Du, Tv0)
+                + np.einsum("...cnm,...n,...m->...c", C, Tu1, Dv))
     frame = FACE_FRAMES[f]
     e_n, e_1, e_2 = frame[..., 0, :], frame[..., 1, :], frame[..., 2, :]
     du = np.asarray(du, dtype=float)

@@ -2,9 +2,13 @@
 
 This module holds *inputs only*: patch tables, material and wave parameters,
 and the random numbers the method consumes (plane-wave directions, ellipsoid
-shapes).  It contains none of the method's arithmetic: no geometry map, no
-quadrature, no kernel.  Both the CPU oracle and the GPU path read these tables
-and each computes everything else on its own.
+shapes).  It contains none of the method's arithmetic: no evaluation of a
+patch map, no quadrature, no kernel.  Both the CPU oracle and the GPU path
+read these tables and each computes everything else on its own.  The one
+surface formula here makes input data: closed-form surfaces (a gnomonic
+cube sphere, a torus) sampled at Chebyshev points and turned into the
+coefficient tables of Chebyshev-interpolated patches, the form a CAD
+surface would be handed over in.
 
 Workloads mirror the paper's structure (Sec. IV): curved quadrilateral patches
 covering a smooth closed surface, a tensor grid of q x q Chebyshev points per
@@ -16,7 +20,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
-from typing import List, Tuple
+from typing import List, Optional, Tuple
 
 import numpy as np
 
@@ -26,6 +30,7 @@ Patch = Tuple[int, int, int, int]
 
 FORM_MFIE_PEC = 0
 FORM_NMULLER = 1
+CHEB_FACE = 6          # patch record (CHEB_FACE, p, 0, 0): Chebyshev-interpolated patch p
 
 
 @dataclass
@@ -39,9 +44,15 @@ class ObjectSpec:
     form: int = FORM_MFIE_PEC
     eps_r: complex = 1.0        # interior relative permittivity (N-Mueller)
     mu_r: complex = 1.0         # interior relative permeability (N-Mueller)
+    # Chebyshev-interpolated patches instead of the cube sphere: coeffs[p, c,
+    # n, m] multiplies T_n(u) T_m(v) in coordinate c of r(u, v); axes, center
+    # and s are then unused
+    coeffs: Optional[np.ndarray] = None
 
     @property
     def n_patches(self) -> int:
+        if self.coeffs is not None:
+            return self.coeffs.shape[0]
         return 6 * self.s * self.s
 
     @property
@@ -57,6 +68,8 @@ class ObjectSpec:
         return self.n_nodes * self.unknowns_per_node
 
     def patches(self) -> List[Patch]:
+        if self.coeffs is not None:
+            return [(CHEB_FACE, p, 0, 0) for p in range(self.coeffs.shape[0])]
         return cube_sphere_patches(self.s)
 
 
@@ -150,6 +163,67 @@ def tiny_sphere(s: int = 1, q: int = 4, k0: float = 1.0) -> ObjectSpec:
     """Small spheres for brute-force checks (6 s^2 patches)."""
     return ObjectSpec(axes=(1.0, 1.0, 1.0), center=(0.0, 0.0, 0.0), s=s, q=q,
                       k0=k0)
+
+
+# --------------------------------------------------------------------------
+# Chebyshev-interpolated patches (generic surface input).
+# --------------------------------------------------------------------------
+
+def cheb_fit(f, deg: int) -> np.ndarray:
+    """Coefficients (3, deg + 1, deg + 1) of the tensor interpolant of the
+    map f(u, v) -> (..., 3) at the deg + 1 Chebyshev points of the first
+    kind per direction (numpy's Chebyshev Vandermonde matrix, inverted)."""
+    x = np.cos(np.pi * (np.arange(deg + 1) + 0.5) / (deg + 1))
+    V = np.polynomial.chebyshev.chebvander(x, deg)
+    Vi = np.linalg.inv(V)
+    U, Vg = np.meshgrid(x, x, indexing="ij")
+    F = f(U, Vg)
+    return np.einsum("nk,klc,ml->cnm", Vi, F, Vi)
+
+
+# right-handed frames (outward axis, first and second face directions)
+_GNOMONIC_FRAMES = np.array([
+    [[1, 0, 0], [0, 1, 0], [0, 0, 1]], [[-1, 0, 0], [0, 0, 1], [0, 1, 0]],
+    [[0, 1, 0], [0, 0, 1], [1, 0, 0]], [[0, -1, 0], [1, 0, 0], [0, 0, 1]],
+    [[0, 0, 1], [1, 0, 0], [0, 1, 0]], [[0, 0, -1], [0, 1, 0], [1, 0, 0]]], dtype=float)
+
+
+def gnomonic_sphere_cheb(s: int, q: int, k0: float, deg: int, radius: float = 1.0,
+                         form: int = FORM_MFIE_PEC, eps_r: float = 1.0) -> ObjectSpec:
+    """A sphere given as 6 s^2 Chebyshev-interpolated patches of degree deg:
+    the gnomonic cube sphere (face point e_n + x e_1 + y e_2 with x, y
+    uniform on the face, projected onto the sphere), a parametrization other
+    than the library's equiangular one."""
+    C = []
+    for f in range(6):
+        en, e1, e2 = _GNOMONIC_FRAMES[f]
+        for i in range(s):
+            for j in range(s):
+                def r(u, v, i=i, j=j, en=en, e1=e1, e2=e2):
+                    x = (2 * i + 1 + u) / s - 1.0
+                    y = (2 * j + 1 + v) / s - 1.0
+                    c = en + x[..., None] * e1 + y[..., None] * e2
+                    return radius * c / np.linalg.norm(c, axis=-1, keepdims=True)
+                C.append(cheb_fit(r, deg))
+    return ObjectSpec(axes=(radius, radius, radius), center=(0.0, 0.0, 0.0), s=s, q=q, k0=k0,
+                      form=form, eps_r=eps_r, coeffs=np.array(C))
+
+
+def torus_cheb(n_theta: int, n_phi: int, q: int, k0: float, deg: int, R: float = 1.0,
+               rho: float = 0.4) -> ObjectSpec:
+    """A torus (major radius R, minor radius rho) as n_theta x n_phi
+    Chebyshev-interpolated patches of degree deg: u runs along the major
+    angle theta, v along the minor angle phi, so a_u x a_v points outward."""
+    C = []
+    for a in range(n_theta):
+        for b in range(n_phi):
+            def r(u, v, a=a, b=b):
+                th = 2 * np.pi * (a + 0.5 * (u + 1)) / n_theta
+                ph = 2 * np.pi * (b + 0.5 * (v + 1)) / n_phi
+                w = R + rho * np.cos(ph)
+                return np.stack([w * np.cos(th), w * np.sin(th), rho * np.sin(ph)], axis=-1)
+            C.append(cheb_fit(r, deg))
+    return ObjectSpec(axes=(R + rho, R + rho, rho), center=(0.0, 0.0, 0.0), s=0, q=q, k0=k0, coeffs=np.array(C))
 
 
 def sample_indices(n_total: int, n_sample: int, seed: int) -> np.ndarray:
