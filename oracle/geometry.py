@@ -64,14 +64,13 @@ def _cheb_patch_map(table, idx, u, v):
     return r, au, av
 
 
-def _cheb_diffs(a, b, deg):
-    """T_n(a) - T_n(b), n = 0..deg, without cancellation: with D_n the
-    difference, D_0 = 0, D_1 = a - b and
-    D_{n+1} = 2 a D_n + 2 (a - b) T_n(b) - D_{n-1}."""
+def _cheb_diffs(a, d, deg):
+    """T_n(a) - T_n(b) for b = a - d, n = 0..deg, without cancellation: the
+    step d is taken as given (never formed as a - b), D_0 = 0, D_1 = d and
+    D_{n+1} = 2 a D_n + 2 d T_n(b) - D_{n-1}.  Also returns T_n(b)."""
     a = np.asarray(a, dtype=float)
-    b = np.asarray(b, dtype=float)
-    d = a - b
-    Tb, _ = _cheb_tables(b, deg)
+    d = np.asarray(d, dtype=float)
+    Tb, _ = _cheb_tables(a - d, deg)
     D = [np.zeros_like(d), d]
     for n in range(1, deg):
         D.append(2 * a * D[n] + 2 * d * Tb[..., n] - D[n - 1])
@@ -224,8 +223,8 @@ def patch_diff(patch, axes, center, u0, v0, du, dv):
         dv = np.asarray(dv, dtype=float)
         u0 = np.asarray(u0, dtype=float) + 0.0 * du
         v0 = np.asarray(v0, dtype=float) + 0.0 * dv
-        Du, Tu1 = _cheb_diffs(u0, u0 + du, deg)
-        Dv, _ = _cheb_diffs(v0, v0 + dv, deg)
+        Du, Tu1 = _cheb_diffs(u0, -du, deg)
+        Dv, _ = _cheb_diffs(v0, -dv, deg)
         Tv0, _ = _cheb_tables(v0, deg)
         return (np.einsum("...cnm,...n,...m->...c", C, Du, Tv0)
                 + np.einsum("...cnm,...n,...m->...c", C, Tu1, Dv))
