@@ -94,6 +94,16 @@ typedef struct {
     double eps_r, mu_r;        /* N-Mueller: interior relative permittivity and
                                   permeability (real, > 0; the exterior is
                                   vacuum); ignored for CBIE_MFIE_PEC        */
+    /* Chebyshev-interpolated patches (generic surfaces, the form a CAD
+     * surface is handed over in; eqs. 11-14 on patches of any shape):
+     * patch_degree d in 1..16 and patch_coeffs, a host array of
+     * n_patches x 3 x (d+1) x (d+1) doubles, coefficient [p][c][n][m]
+     * multiplying T_n(u) T_m(v) in coordinate c of patch p's r(u, v) on
+     * [-1, 1]^2, with a_u x a_v pointing outward; copied at create.  Then
+     * patches, axes and center are ignored (patches may be NULL).
+     * patch_degree 0: the cube-sphere patches above.                      */
+    int patch_degree;
+    const double* patch_coeffs;
 } cbie_object;
 
 /* Create a context for n_objs independent objects (block-diagonal system,

@@ -220,7 +220,8 @@ def _singular_chunk(args):
 
 def dense_matrix(nd: Nodes, k, delta=NEAR_DELTA, rule=None, pairs=None, workers=1):
     """Dense complex128 MFIE matrix (2n x 2n) in the original unknown order.
-    `workers` > 1 spreads the singular integrals over a process pool."""
+    `workers` > 1 spreads the singular integrals over a pool of spawned
+    processes (safe in a process that has initialised a GPU)."""
     n = nd.size
     q2 = nd.q * nd.q
     A = np.empty((n, 2, n, 2), dtype=complex)
@@ -233,10 +234,10 @@ def dense_matrix(nd: Nodes, k, delta=NEAR_DELTA, rule=None, pairs=None, workers=
     if pairs is None:
         pairs = near_pairs(nd, delta)
     if workers > 1:
-        from multiprocessing import Pool
+        import multiprocessing
         size = max(1, len(pairs) // (8 * workers))
         chunks = [pairs[i:i + size] for i in range(0, len(pairs), size)]
-        with Pool(workers) as pool:
+        with multiprocessing.get_context("spawn").Pool(workers) as pool:
             results = pool.map(_singular_chunk, [(nd, k, ch, rule) for ch in chunks])
         blocks = [b for r in results for b in r]
     else:

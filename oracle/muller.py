@@ -210,7 +210,9 @@ def _singular_chunk(args):
 
 
 def dense_matrix(nd: Nodes, k0, eps_r, mu_r=1.0, delta=NEAR_DELTA, rule=None, pairs=None, workers=1):
-    """Dense complex128 N-Mueller matrix (4n x 4n), original unknown order."""
+    """Dense complex128 N-Mueller matrix (4n x 4n), original unknown order.
+    `workers` > 1 spreads the singular integrals over a pool of spawned
+    processes."""
     md = Media(k0, eps_r, mu_r)
     n = nd.size
     q2 = nd.q * nd.q
@@ -223,10 +225,10 @@ def dense_matrix(nd: Nodes, k0, eps_r, mu_r=1.0, delta=NEAR_DELTA, rule=None, pa
     if pairs is None:
         pairs = near_pairs(nd, delta)
     if workers > 1:
-        from multiprocessing import Pool
+        import multiprocessing
         size = max(1, len(pairs) // (8 * workers))
         chunks = [pairs[i:i + size] for i in range(0, len(pairs), size)]
-        with Pool(workers) as pool:
+        with multiprocessing.get_context("spawn").Pool(workers) as pool:
             res = pool.map(_singular_chunk, [(nd, md, ch, rule) for ch in chunks])
         blocks = [b for r in res for b in r]
     else:

@@ -45,7 +45,8 @@ class _Patch(C.Structure):
 class _Object(C.Structure):
     _fields_ = [("form", C.c_int), ("k0", C.c_double), ("axes", C.c_double * 3),
                 ("center", C.c_double * 3), ("q", C.c_int), ("n_patches", C.c_int),
-                ("patches", C.POINTER(_Patch)), ("eps_r", C.c_double), ("mu_r", C.c_double)]
+                ("patches", C.POINTER(_Patch)), ("eps_r", C.c_double), ("mu_r", C.c_double),
+                ("patch_degree", C.c_int), ("patch_coeffs", C.POINTER(C.c_double))]
 
 
 class Stats(C.Structure):
@@ -131,16 +132,27 @@ class Solver:
         objs = (_Object * len(objects))()
         self._keep = []
         for o, spec in enumerate(objects):
-            pts = spec.patches()
-            arr = (_Patch * len(pts))(*[_Patch(f, i, j, s) for (f, i, j, s) in pts])
-            self._keep.append(arr)
             objs[o].form = spec.form
             objs[o].k0 = spec.k0
             objs[o].axes = (C.c_double * 3)(*spec.axes)
             objs[o].center = (C.c_double * 3)(*spec.center)
             objs[o].q = spec.q
-            objs[o].n_patches = len(pts)
-            objs[o].patches = arr
+            coeffs = getattr(spec, "coeffs", None)
+            if coeffs is not None:
+                # Chebyshev-interpolated patches: (n_patches, 3, d + 1, d + 1)
+                cf = np.ascontiguousarray(coeffs, dtype=np.float64)
+                if cf.ndim != 4 or cf.shape[1] != 3 or cf.shape[2] != cf.shape[3]:
+                    raise ValueError("coeffs must be (n_patches, 3, d + 1, d + 1)")
+                self._keep.append(cf)
+                objs[o].n_patches = cf.shape[0]
+                objs[o].patch_degree = cf.shape[2] - 1
+                objs[o].patch_coeffs = cf.ctypes.data_as(C.POINTER(C.c_double))
+            else:
+                pts = spec.patches()
+                arr = (_Patch * len(pts))(*[_Patch(f, i, j, s) for (f, i, j, s) in pts])
+                self._keep.append(arr)
+                objs[o].n_patches = len(pts)
+                objs[o].patches = arr
             eps, mu = complex(getattr(spec, "eps_r", 1.0)), complex(getattr(spec, "mu_r", 1.0))
             if eps.imag != 0 or mu.imag != 0:
                 raise ValueError("lossless interior materials only (real eps_r, mu_r)")

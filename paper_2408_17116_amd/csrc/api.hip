@@ -63,8 +63,16 @@ cbie_status cbie_create(const cbie_object* objs, int n_objs, void* hip_stream, c
         if (ob.form == CBIE_NMULLER &&
             !(ob.eps_r > 0 && ob.mu_r > 0 && std::isfinite(ob.eps_r) && std::isfinite(ob.mu_r)))
             return CBIE_EINVAL;
-        if (!(ob.k0 > 0) || ob.q < 2 || ob.q > 11 || ob.n_patches <= 0 || !ob.patches) return CBIE_EINVAL;
+        if (!(ob.k0 > 0) || ob.q < 2 || ob.q > 11 || ob.n_patches <= 0) return CBIE_EINVAL;
         if (ob.form == CBIE_NMULLER && ob.q > 8) return CBIE_EINVAL;
+        if (ob.patch_degree != 0) {
+            if (ob.patch_degree < 1 || ob.patch_degree > kChebMaxDeg || !ob.patch_coeffs) return CBIE_EINVAL;
+            const int64_t nc = (int64_t)ob.n_patches * 3 * (ob.patch_degree + 1) * (ob.patch_degree + 1);
+            for (int64_t e = 0; e < nc; ++e)
+                if (!std::isfinite(ob.patch_coeffs[e])) return CBIE_EINVAL;
+            continue;
+        }
+        if (!ob.patches) return CBIE_EINVAL;
         for (int d = 0; d < 3; ++d)
             if (!(ob.axes[d] > 0)) return CBIE_EINVAL;
         for (int p = 0; p < ob.n_patches; ++p) {
@@ -88,25 +96,39 @@ cbie_status cbie_create(const cbie_object* objs, int n_objs, void* hip_stream, c
     cbie_status st = guarded(ctx, [&](Ctx& c) {
         c.stream = (hipStream_t)hip_stream;
         int node = 0;
+        std::vector<int64_t> coef_off(n_objs, -1);
+        std::vector<double> coef;
         for (int o = 0; o < n_objs; ++o) {
             const cbie_object& ob = objs[o];
+            const bool cheb = ob.patch_degree > 0;
             ObjDev od{};
-            for (int d = 0; d < 3; ++d) { od.axes[d] = ob.axes[d]; od.center[d] = ob.center[d]; }
+            for (int d = 0; d < 3; ++d) { od.axes[d] = cheb ? 1.0 : ob.axes[d]; od.center[d] = cheb ? 0.0 : ob.center[d]; }
             od.k0 = ob.k0;
             od.q = ob.q;
             od.form = ob.form;
             od.eps_r = ob.form == CBIE_NMULLER ? ob.eps_r : 1.0;
             od.mu_r = ob.form == CBIE_NMULLER ? ob.mu_r : 1.0;
+            od.deg = cheb ? ob.patch_degree : 0;
+            if (cheb) {
+                coef_off[o] = (int64_t)coef.size();
+                coef.insert(coef.end(), ob.patch_coeffs,
+                            ob.patch_coeffs + (size_t)ob.n_patches * 3 * (ob.patch_degree + 1) * (ob.patch_degree + 1));
+            }
             c.objs.push_back(od);
             c.obj_patch0.push_back((int)c.patches.size());
             c.obj_npatch.push_back(ob.n_patches);
             c.obj_node0.push_back(node);
             for (int p = 0; p < ob.n_patches; ++p) {
                 PatchDev pd{};
-                pd.face = ob.patches[p].face;
-                pd.i = ob.patches[p].i;
-                pd.j = ob.patches[p].j;
-                pd.split = ob.patches[p].split;
+                if (cheb) {
+                    pd.face = -1;
+                    pd.i = p;
+                } else {
+                    pd.face = ob.patches[p].face;
+                    pd.i = ob.patches[p].i;
+                    pd.j = ob.patches[p].j;
+                    pd.split = ob.patches[p].split;
+                }
                 pd.obj = o;
                 pd.node0 = node;
                 pd.q = ob.q;
@@ -120,6 +142,11 @@ cbie_status cbie_create(const cbie_object* objs, int n_objs, void* hip_stream, c
         c.n_nodes = node;
         c.upn = objs[0].form == CBIE_NMULLER ? 4 : 2;
         c.n_unk = c.upn * (int64_t)node;
+        if (!coef.empty()) {
+            c.d_coef.upload(coef, c.stream);
+            for (int o = 0; o < n_objs; ++o)
+                if (coef_off[o] >= 0) c.objs[o].coef = c.d_coef.p + coef_off[o];
+        }
         c.d_patches.upload(c.patches, c.stream);
         c.d_objs.upload(c.objs, c.stream);
         c.d_node_patch.upload(c.node_patch, c.stream);

@@ -42,6 +42,7 @@ struct Ctx {
 
     // device problem tables
     DBuf<PatchDev> d_patches;
+    DBuf<double> d_coef;                    // Chebyshev-interpolated patch coefficients (all objects)
     DBuf<ObjDev> d_objs;
     DBuf<int> d_node_patch, d_obj_patch0, d_obj_npatch;
     DBuf<double> d_fej11_x, d_fej11_w, d_fej01_x, d_fej01_w;

@@ -191,9 +191,10 @@ __device__ inline int quad_triangles(double us, double vs, double (*tri)[6]) {
 }
 
 // Parameter distance of a near target from its projection point.
+template <bool CHEB = true>
 __device__ inline double near_param_dist(const PatchDev& P, const ObjDev& O, double us, double vs, double dist) {
     V3 r0, au0, av0;
-    patch_eval(P, O, us, vs, r0, au0, av0);
+    patch_eval<CHEB>(P, O, us, vs, r0, au0, av0);
     return dist / sqrt(norm(au0) * norm(av0));
 }
 
@@ -247,7 +248,7 @@ template <int QM> struct QuadPointLDS {
 // QM = 8: lane kl of each wave owns node kl (q^2 <= 64).  QM = 11: lane kl
 // owns nodes kl and kl + 64 (q^2 <= 121, up to 242 unknowns per patch, the
 // most a 256-unknown leaf holds).
-template <int QM>
+template <int QM, bool CHEB>
 __global__ __launch_bounds__(256) void k_quad(
     const PatchDev* __restrict__ patches, const ObjDev* __restrict__ objs, NodeArrays nd,
     const NearPair* __restrict__ pairs, int64_t n_pairs, const double* __restrict__ fej11_x,
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(256) void k_quad(
     if (tid == 0) s_ntri = quad_triangles(us, vs, s_tri);
     __syncthreads();
     const int ntri = s_ntri;
-    const double dpar = E.self ? 0.0 : near_param_dist(P, O, us, vs, E.dist);
+    const double dpar = E.self ? 0.0 : near_param_dist<CHEB>(P, O, us, vs, E.dist);
     const int nt = rule.n_ang;
     const int nr = E.self ? rule.n_rad : (rule.n_in + rule.n_out);
     const int64_t npts = (int64_t)ntri * nt * nr;
@@ -311,8 +312,8 @@ __global__ __launch_bounds__(256) void k_quad(
             quad_point(s_tri, nt, nr, E.self, dpar, rule, fej_x, fej_w, pidx, du, dv, wgt);
             const double u = us + du, v = vs + dv;
             V3 r, au, av;
-            patch_eval(P, O, u, v, r, au, av);
-            const V3 R = E.self ? patch_delta(P, O, us, vs, du, dv) : (rt - r);
+            patch_eval<CHEB>(P, O, u, v, r, au, av);
+            const V3 R = E.self ? patch_delta<CHEB>(P, O, us, vs, du, dv) : (rt - r);
             zd K[2][2];
             mfie_kernel(O.k0, R, aut, avt, au, av, K);
             kw[0] = wgt * K[0][0].re; kw[1] = wgt * K[0][0].im;
@@ -363,10 +364,13 @@ __global__ __launch_bounds__(256) void k_quad(
         out[pid * stride + ((int64_t)b * q2 + kl2) * 2 + a] = zd{re, im};
     }
 }
-template __global__ void k_quad<8>(const PatchDev*, const ObjDev*, NodeArrays, const NearPair*, int64_t,
-                                   const double*, const double*, const double*, QuadRule, int64_t, zd*);
-template __global__ void k_quad<11>(const PatchDev*, const ObjDev*, NodeArrays, const NearPair*, int64_t,
-                                    const double*, const double*, const double*, QuadRule, int64_t, zd*);
+#define CBIE_KQUAD_INST(QM, CH)                                                                                \
+    template __global__ void k_quad<QM, CH>(const PatchDev*, const ObjDev*, NodeArrays, const NearPair*, int64_t, \
+                                            const double*, const double*, const double*, QuadRule, int64_t, zd*);
+CBIE_KQUAD_INST(8, false)
+CBIE_KQUAD_INST(11, false)
+CBIE_KQUAD_INST(8, true)
+CBIE_KQUAD_INST(11, true)
 
 // ------------------------------------------------------------- far fill
 // Dense block tile: 64 row nodes x 16 column nodes per work-group; thread

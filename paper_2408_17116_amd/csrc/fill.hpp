@@ -55,7 +55,7 @@ __global__ void k_nodes(const PatchDev*, const ObjDev*, const double*, const dou
 __global__ void k_patch_info(const PatchDev*, const ObjDev*, int, double*);
 __global__ void k_near(const PatchDev*, const ObjDev*, const double*, const int*, const int*, const int*,
                        NodeArrays, int, double, int*, const int64_t*, NearPair*);
-template <int QM>
+template <int QM, bool CHEB>
 __global__ void k_quad(const PatchDev*, const ObjDev*, NodeArrays, const NearPair*, int64_t,
                        const double*, const double*, const double*, QuadRule, int64_t, zd*);
 template <typename T>

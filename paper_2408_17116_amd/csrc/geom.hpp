@@ -4,18 +4,24 @@
 // its spheres): xi = (2i+1+u)/s - 1, eta = (2j+1+v)/s - 1,
 // c = e_n + tan(pi xi/4) e_1 + tan(pi eta/4) e_2, r = center + diag(axes) c/|c|.
 // Covariant basis a_u = dr/du, a_v = dr/dv (eq. 14).
+//
+// Chebyshev-interpolated patch (generic surface input, e.g. from CAD):
+// r(u, v) = sum_{n, m <= deg} C[c][n][m] T_n(u) T_m(v) per coordinate c,
+// a_u and a_v from T_n'(x) = n U_{n-1}(x).
 #pragma once
 #include "common.hpp"
 
 namespace cbie {
 
 struct PatchDev {
-    int face, i, j, split;
+    int face, i, j, split;   // Chebyshev-interpolated objects: i = the patch's index in the coefficient table
     int obj;          // object index
     int node0;        // first node (original order)
     int q;
     int pad;
 };
+
+constexpr int kChebMaxDeg = 16;   // highest degree of a Chebyshev-interpolated patch
 
 struct ObjDev {
     double axes[3];
@@ -24,6 +30,9 @@ struct ObjDev {
     int q;
     int form;
     double eps_r, mu_r;   // interior material (N-Mueller)
+    const double* coef;   // Chebyshev-interpolated patches: device table [patch][3][deg+1][deg+1]
+    int deg;              // their degree (0: cube-sphere patches on the ellipsoid)
+    int pad;
 };
 
 __device__ __constant__ static const double kFaceFrames[6][3][3] = {
@@ -51,9 +60,94 @@ __device__ inline V3 frame(int f, int row) {
     return v3(kFaceFrames[f][row][0], kFaceFrames[f][row][1], kFaceFrames[f][row][2]);
 }
 
-// r, a_u, a_v of a patch at (u, v)
-__device__ inline void patch_eval(const PatchDev& P, const ObjDev& O, double u, double v,
-                                  V3& r, V3& au, V3& av) {
+// Chebyshev-interpolated patch: every T_n and its derivative n U_{n-1} by
+// running recurrences (no tables), so the evaluation needs few registers
+// and no stack inside the quadrature kernels.
+__device__ inline void cheb_patch_eval(const double* __restrict__ C, int deg, double u, double v, V3& r, V3& au,
+                                       V3& av) {
+    const int d1 = deg + 1;
+    double x[3] = {0.0, 0.0, 0.0}, xu[3] = {0.0, 0.0, 0.0}, xv[3] = {0.0, 0.0, 0.0};
+    double tn = 1.0, tp = u, un = 0.0, up = 1.0;   // T_n(u), T_{n-1}(u) (T_{-1} = T_1), U_{n-1}(u), U_{n-2}(u)
+    for (int n = 0; n < d1; ++n) {
+        const double dtn = n * un;                   // T_n'(u) = n U_{n-1}(u)
+        for (int c = 0; c < 3; ++c) {
+            const double* row = C + ((size_t)c * d1 + n) * d1;
+            double s0 = 0.0, s1 = 0.0;
+            double tm = 1.0, tq = v, um = 0.0, uq = 1.0;
+            for (int m = 0; m < d1; ++m) {
+                s0 += row[m] * tm;
+                s1 += row[m] * (m * um);
+                const double t2 = (m == 0 ? v : 2.0 * v * tm - tq);
+                tq = tm;
+                tm = t2;
+                const double u2 = (m == 0 ? 1.0 : 2.0 * v * um - uq);
+                uq = um;
+                um = u2;
+            }
+            x[c] += tn * s0;
+            xu[c] += dtn * s0;
+            xv[c] += tn * s1;
+        }
+        const double t2 = (n == 0 ? u : 2.0 * u * tn - tp);
+        tp = tn;
+        tn = t2;
+        const double u2 = (n == 0 ? 1.0 : 2.0 * u * un - up);
+        up = un;
+        un = u2;
+    }
+    r = v3(x[0], x[1], x[2]);
+    au = v3(xu[0], xu[1], xu[2]);
+    av = v3(xv[0], xv[1], xv[2]);
+}
+
+// r(u0, v0) - r(u0 + du, v0 + dv) of a Chebyshev-interpolated patch without
+// cancellation: T_n(u0) T_m(v0) - T_n(u1) T_m(v1) =
+// (T_n(u0) - T_n(u1)) T_m(v0) + T_n(u1) (T_m(v0) - T_m(v1)); each difference
+// D_n = T_n(a) - T_n(b), b = a - d, runs D_0 = 0, D_1 = d,
+// D_{n+1} = 2 a D_n + 2 d T_n(b) - D_{n-1}, with the step d as given.
+__device__ inline V3 cheb_patch_delta(const double* __restrict__ C, int deg, double u0, double v0, double du,
+                                      double dv) {
+    const int d1 = deg + 1;
+    const double du_ = -du, dv_ = -dv, u1 = u0 + du, v1 = v0 + dv;
+    double x[3] = {0.0, 0.0, 0.0};
+    double Dn = 0.0, Dp = 0.0, bn = 1.0, bp = 0.0;   // D_n, D_{n-1}, T_n(u1), T_{n-1}(u1)
+    for (int n = 0; n < d1; ++n) {
+        for (int c = 0; c < 3; ++c) {
+            const double* row = C + ((size_t)c * d1 + n) * d1;
+            double s0 = 0.0, s1 = 0.0;
+            double Em = 0.0, Eq = 0.0, am = 1.0, aq = 0.0, cm = 1.0, cq = 0.0;   // D_m(v), T_m(v0), T_m(v1)
+            for (int m = 0; m < d1; ++m) {
+                s0 += row[m] * am;
+                s1 += row[m] * Em;
+                const double E2 = (m == 0 ? dv_ : 2.0 * v0 * Em + 2.0 * dv_ * cm - Eq);
+                Eq = Em;
+                Em = E2;
+                const double a2 = (m == 0 ? v0 : 2.0 * v0 * am - aq);
+                aq = am;
+                am = a2;
+                const double c2 = (m == 0 ? v1 : 2.0 * v1 * cm - cq);
+                cq = cm;
+                cm = c2;
+            }
+            x[c] += Dn * s0 + bn * s1;
+        }
+        const double D2 = (n == 0 ? du_ : 2.0 * u0 * Dn + 2.0 * du_ * bn - Dp);
+        Dp = Dn;
+        Dn = D2;
+        const double b2 = (n == 0 ? u1 : 2.0 * u1 * bn - bp);
+        bp = bn;
+        bn = b2;
+    }
+    return v3(x[0], x[1], x[2]);
+}
+
+__device__ inline const double* cheb_coef(const PatchDev& P, const ObjDev& O) {
+    return O.coef + (size_t)P.i * 3 * (O.deg + 1) * (O.deg + 1);
+}
+
+// r, a_u, a_v of a cube-sphere patch at (u, v)
+__device__ inline void sphere_patch_eval(const PatchDev& P, const ObjDev& O, double u, double v, V3& r, V3& au,
+                                         V3& av) {
     const double s = (double)P.split;
     const double xi = (2.0 * P.i + 1.0 + u) / s - 1.0;
     const double eta = (2.0 * P.j + 1.0 + v) / s - 1.0;
@@ -75,8 +169,8 @@ __device__ inline void patch_eval(const PatchDev& P, const ObjDev& O, double u, 
 // r(u0, v0) - r(u0 + du, v0 + dv) formed without cancellation: the tangent
 // difference uses tan a - tan b = sin(a - b)/(cos a cos b) and the
 // normalisation difference uses |c1|^2 - |c0|^2 = (c1 - c0).(c1 + c0).
-__device__ inline V3 patch_delta(const PatchDev& P, const ObjDev& O, double u0, double v0,
-                                 double du, double dv) {
+__device__ inline V3 sphere_patch_delta(const PatchDev& P, const ObjDev& O, double u0, double v0, double du,
+                                        double dv) {
     const double s = (double)P.split;
     const double q4 = M_PI * 0.25 / s;
     const double a0 = M_PI * 0.25 * ((2.0 * P.i + 1.0 + u0) / s - 1.0);
@@ -93,6 +187,19 @@ __device__ inline V3 patch_delta(const PatchDev& P, const ObjDev& O, double u0, 
     const double d2 = -dot(dc, c0 + c1);             // |c1|^2 - |c0|^2
     const V3 dp = (1.0 / n0) * dc + (d2 / (n0 * n1 * (n0 + n1))) * c1;
     return mulc(O.axes, dp);
+}
+
+// Either patch kind.  CHEB = false leaves the Chebyshev branch out, for
+// the hot quadrature kernel of contexts without such patches.
+template <bool CHEB = true>
+__device__ inline void patch_eval(const PatchDev& P, const ObjDev& O, double u, double v, V3& r, V3& au, V3& av) {
+    if (CHEB && O.deg > 0) cheb_patch_eval(cheb_coef(P, O), O.deg, u, v, r, au, av);
+    else sphere_patch_eval(P, O, u, v, r, au, av);
+}
+template <bool CHEB = true>
+__device__ inline V3 patch_delta(const PatchDev& P, const ObjDev& O, double u0, double v0, double du, double dv) {
+    if (CHEB && O.deg > 0) return cheb_patch_delta(cheb_coef(P, O), O.deg, u0, v0, du, dv);
+    return sphere_patch_delta(P, O, u0, v0, du, dv);
 }
 
 // MFIE kernel entries K[b][a] (see the library header): with

@@ -208,6 +208,8 @@ void stage_fill(Ctx& c, int n_ang, int n_rad) {
     const int64_t np = (int64_t)c.near.size();
     int qmax = 0;
     for (const auto& p : c.patches) qmax = std::max(qmax, p.q);
+    bool cheb = false;   // any Chebyshev-interpolated patches
+    for (const auto& o : c.objs) cheb = cheb || o.deg > 0;
     const int q2 = qmax * qmax;
     const int64_t stride = (int64_t)c.upn * c.upn * q2;   // entries of one (target, patch) pair
     DBuf<zd> vals;
@@ -226,15 +228,21 @@ void stage_fill(Ctx& c, int n_ang, int n_rad) {
             check_launch("k_quad_nm");
         } else {
             // orders above 8: two nodes per lane (a separate instance keeps
-            // the registers of the common case)
-            if (qmax <= 8)
-                k_quad<8><<<(unsigned)cnt, 256, 0, c.stream>>>(c.d_patches.p, c.d_objs.p, c.nd, c.d_near.p + p0, cnt,
-                                                               c.d_fej11_x.p, c.d_fej01_x.p, c.d_fej01_w.p, rule,
-                                                               stride, vals.p + p0 * stride);
-            else
-                k_quad<11><<<(unsigned)cnt, 256, 0, c.stream>>>(c.d_patches.p, c.d_objs.p, c.nd, c.d_near.p + p0,
-                                                                cnt, c.d_fej11_x.p, c.d_fej01_x.p, c.d_fej01_w.p,
-                                                                rule, stride, vals.p + p0 * stride);
+            // the registers of the common case); the Chebyshev-patch
+            // geometry only in the instances of contexts that hold such
+            // patches
+            auto launch = [&](auto kern) {
+                kern<<<(unsigned)cnt, 256, 0, c.stream>>>(c.d_patches.p, c.d_objs.p, c.nd, c.d_near.p + p0, cnt,
+                                                          c.d_fej11_x.p, c.d_fej01_x.p, c.d_fej01_w.p, rule, stride,
+                                                          vals.p + p0 * stride);
+            };
+            if (qmax <= 8) {
+                if (cheb) launch(k_quad<8, true>);
+                else launch(k_quad<8, false>);
+            } else {
+                if (cheb) launch(k_quad<11, true>);
+                else launch(k_quad<11, false>);
+            }
             check_launch("k_quad");
         }
     }
