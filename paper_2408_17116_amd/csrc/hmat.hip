@@ -247,7 +247,10 @@ struct FactorLayout {
     const std::vector<DenseBlockDev>* dblk = nullptr;
     ComponentTree comp;
     std::vector<DenseBlockDev> comp_dblk;
-    DBuf<int> d_perm;   // component-wise: tree-order unknown -> factor-order unknown
+    // component-wise: tree-order unknown -> factor-order unknown (the host
+    // copy outlives the asynchronous upload)
+    std::vector<int> perm;
+    DBuf<int> d_perm;
 };
 
 static std::shared_ptr<FactorLayout> make_layout(Ctx& c) {
@@ -276,14 +279,14 @@ static std::shared_ptr<FactorLayout> make_layout(Ctx& c) {
         off += (int64_t)src.row_nodes * src.col_nodes;
     }
     CBIE_REQUIRE(off == c.stats.dense_entries, -7, "component layout: dense entries differ from the fill's");
-    std::vector<int> perm(c.n_unk);
+    L->perm.resize(c.n_unk);
     for (int root : c.tree.roots) {
         const Cluster& R = c.tree.clusters[root];
         for (int i = 0; i < R.nodes; ++i)
             for (int a = 0; a < c.upn; ++a)
-                perm[(size_t)c.upn * (R.node0 + i) + a] = c.upn * R.node0 + a * R.nodes + i;
+                L->perm[(size_t)c.upn * (R.node0 + i) + a] = c.upn * R.node0 + a * R.nodes + i;
     }
-    L->d_perm.upload(perm, c.stream);
+    L->d_perm.upload(L->perm, c.stream);
     L->tree = &L->comp.tree;
     L->dblk = &L->comp_dblk;
     return L;
